@@ -1,0 +1,352 @@
+/*
+ * oracle.c -- plain, slow, obviously-correct CPU reference for the
+ * S4-BP128-D4 codec and sorted-set intersection.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; it exists so that tests, the smoke check and the CPU
+ * baseline leg of the benchmark can check the GPU path against an
+ * independent implementation.  It shares no source, header, table or
+ * helper with the GPU library: the stream layout below is re-implemented
+ * here from its written description.
+ *
+ * Paper: D. Lemire, L. Boytsov, N. Kurz, "SIMD Compression and the
+ * Intersection of Sorted Integers" (arXiv:1401.6399).
+ *
+ *   - Binary packing in 128-integer blocks, one bit-width byte per block,
+ *     width = smallest b with every value < 2^b, 0 <= b <= 32
+ *     (Sec. 4.3, S4-BP128).
+ *   - 4-way interleaved packing: integer 4q+j of a block goes to lane j;
+ *     lane j is an LSB-first stream of 32 values of b bits stored in words
+ *     j, 4+j, 8+j, ...; a value that straddles a word boundary continues in
+ *     the same lane's next word (Sec. 4.2, Fig. 2).
+ *   - D4 differential coding: delta_i = x_i - x_{i-4}, prefix sum seeded
+ *     with (0,0,0,0) and carried from block to block (Sec. 5, Alg. 1).
+ *   - Intersection: the textbook two-pointer merge ("scalar", Sec. 6) and
+ *     SvS folding of k lists (Sec. 6).
+ *
+ * Readings where the paper is silent or garbled (each is also listed in
+ * the design notes):
+ *   - the final < 128 integers are stored as raw uint32 (the paper stores
+ *     them with varint, Sec. 4.3);
+ *   - the width bytes of all blocks are stored together before the packed
+ *     payload (the paper groups them per 2048-integer meta-block); the
+ *     byte count differs only by the <= 3 padding bytes;
+ *   - b = 0 decodes to 128 zero deltas; at b = 32 the mask is all ones;
+ *   - intersections require strictly increasing inputs; results are sets.
+ *
+ * Serialized stream (little-endian), as written and read here:
+ *   0  u32 magic 0x34443453 ("S4D4")
+ *   4  u16 version (1)
+ *   6  u16 flags  (bit 0: input strictly increasing; other bits zero)
+ *   8  u64 n      (number of integers)
+ *   16 u32 nb     (= floor(n / 128), number of packed blocks)
+ *   20 u32 t      (= n - 128 nb, raw tail length)
+ *   24 u64 pw     (payload words = sum over blocks of 4 b_k)
+ *   32 u8 widths[nb], then zero bytes up to a multiple of 4
+ *      u32 payload[pw]
+ *      u32 tail[t]
+ *
+ * Parity status of each function is recorded in the tests that pin it.
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#include <stdlib.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_EUNSORTED (-2)
+#define ORC_ERANGE (-3)
+#define ORC_ECORRUPT (-4)
+#define ORC_ENOMEM (-5)
+
+#define ORC_MAGIC 0x34443453u
+#define ORC_HEADER 32u
+
+static void put32(uint8_t *p, uint32_t v) {
+  p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8);
+  p[2] = (uint8_t)(v >> 16); p[3] = (uint8_t)(v >> 24);
+}
+static void put16(uint8_t *p, uint16_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static void put64(uint8_t *p, uint64_t v) { put32(p, (uint32_t)v); put32(p + 4, (uint32_t)(v >> 32)); }
+static uint32_t get32(const uint8_t *p) {
+  return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+static uint16_t get16(const uint8_t *p) { return (uint16_t)(p[0] | (p[1] << 8)); }
+static uint64_t get64(const uint8_t *p) { return (uint64_t)get32(p) | ((uint64_t)get32(p + 4) << 32); }
+
+/* Sec. 4.3: "the smallest value b such that all corresponding integers are
+ * smaller than 2^b".  Written as the definition (increase b until every
+ * value fits), in 64-bit arithmetic so that b = 32 is reachable. */
+static uint32_t orc_width(const uint32_t *d, size_t count) {
+  uint32_t b = 0;
+  for (;;) {
+    int all_fit = 1;
+    for (size_t i = 0; i < count; ++i)
+      if ((uint64_t)d[i] >= ((uint64_t)1 << b)) { all_fit = 0; break; }
+    if (all_fit) return b;
+    ++b;
+  }
+}
+
+static size_t pad4(size_t v) { return (v + 3u) & ~(size_t)3u; }
+
+/* Exact serialized size given the block widths (Sec. 4.2: 128 b bits, i.e.
+ * 16 b bytes, per block). */
+size_t orc_stream_bytes(uint64_t n, const uint8_t *widths) {
+  uint64_t nb = n / 128u, t = n % 128u, pw = 0;
+  for (uint64_t k = 0; k < nb; ++k) pw += 4u * widths[k];
+  return ORC_HEADER + pad4((size_t)nb) + 4u * (size_t)pw + 4u * (size_t)t;
+}
+
+/* Encode a non-decreasing list: D4 deltas (Sec. 5), per-block width
+ * (Sec. 4.3), 4-lane interleaved LSB-first packing (Sec. 4.2, Fig. 2). */
+int orc_encode(const uint32_t *x, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes) {
+  if ((!x && n) || !out_bytes) return ORC_EINVAL;
+  int strictly = 1;
+  for (uint64_t i = 1; i < n; ++i) {
+    if (x[i] < x[i - 1]) return ORC_EUNSORTED;
+    if (x[i] == x[i - 1]) strictly = 0;
+  }
+  uint64_t nb = n / 128u, t = n % 128u;
+  if (nb > 0xFFFFFFFFull) return ORC_EINVAL;
+  uint64_t packed = nb * 128u;
+
+  /* deltas over the global index: delta_i = x_i - x_{i-4}, x_{-4..-1} = 0 */
+  uint32_t *d = (uint32_t *)malloc((packed ? packed : 1) * sizeof(uint32_t));
+  uint8_t *w = (uint8_t *)malloc(nb ? nb : 1);
+  if (!d || !w) { free(d); free(w); return ORC_ENOMEM; }
+  for (uint64_t i = 0; i < packed; ++i) d[i] = x[i] - (i >= 4 ? x[i - 4] : 0u);
+  uint64_t pw = 0;
+  for (uint64_t k = 0; k < nb; ++k) { w[k] = (uint8_t)orc_width(d + 128u * k, 128u); pw += 4u * w[k]; }
+
+  size_t need = ORC_HEADER + pad4((size_t)nb) + 4u * (size_t)pw + 4u * (size_t)t;
+  *out_bytes = need;
+  if (cap < need) { free(d); free(w); return ORC_ERANGE; }
+  memset(out, 0, need);
+  put32(out, ORC_MAGIC);
+  put16(out + 4, 1);
+  put16(out + 6, (uint16_t)(strictly ? 1 : 0));
+  put64(out + 8, n);
+  put32(out + 16, (uint32_t)nb);
+  put32(out + 20, (uint32_t)t);
+  put64(out + 24, pw);
+  memcpy(out + ORC_HEADER, w, (size_t)nb);
+  uint8_t *payload = out + ORC_HEADER + pad4((size_t)nb);
+
+  uint64_t word_base = 0;
+  for (uint64_t k = 0; k < nb; ++k) {
+    uint32_t b = w[k];
+    for (uint32_t j = 0; j < 4; ++j) {
+      /* lane j: append d[128k + 4q + j], q = 0..31, LSB first; emit each
+       * completed 32-bit word m at payload word 4m + j */
+      uint64_t acc = 0;
+      uint32_t have = 0, m = 0;
+      for (uint32_t q = 0; q < 32; ++q) {
+        acc |= (uint64_t)d[128u * k + 4u * q + j] << have;
+        have += b;
+        while (have >= 32) {
+          put32(payload + 4u * (word_base + 4u * m + j), (uint32_t)acc);
+          acc >>= 32; have -= 32; ++m;
+        }
+      }
+      /* 32 values of b bits fill exactly b words: nothing is left over */
+    }
+    word_base += 4u * b;
+  }
+  uint8_t *tail = payload + 4u * pw;
+  for (uint64_t i = 0; i < t; ++i) put32(tail + 4u * i, x[packed + i]);
+  free(d); free(w);
+  return ORC_OK;
+}
+
+typedef struct {
+  uint64_t n, nb, t, pw;
+  uint16_t flags;
+  const uint8_t *widths;
+  const uint8_t *payload; /* byte pointer, read with get32 */
+  const uint8_t *tail;
+} orc_view;
+
+static int orc_parse(const uint8_t *enc, size_t bytes, orc_view *v) {
+  if (!enc || bytes < ORC_HEADER) return ORC_ECORRUPT;
+  if (get32(enc) != ORC_MAGIC || get16(enc + 4) != 1) return ORC_ECORRUPT;
+  v->flags = get16(enc + 6);
+  if (v->flags & ~1u) return ORC_ECORRUPT;
+  v->n = get64(enc + 8);
+  v->nb = get32(enc + 16);
+  v->t = get32(enc + 20);
+  v->pw = get64(enc + 24);
+  if (v->t >= 128 || v->nb * 128u + v->t != v->n) return ORC_ECORRUPT;
+  size_t wbytes = pad4((size_t)v->nb);
+  if (bytes < ORC_HEADER + wbytes) return ORC_ECORRUPT;
+  v->widths = enc + ORC_HEADER;
+  uint64_t pw = 0;
+  for (uint64_t k = 0; k < v->nb; ++k) {
+    if (v->widths[k] > 32) return ORC_ECORRUPT;
+    pw += 4u * v->widths[k];
+  }
+  for (uint64_t k = v->nb; k < wbytes; ++k)
+    if (enc[ORC_HEADER + k] != 0) return ORC_ECORRUPT;
+  if (pw != v->pw) return ORC_ECORRUPT;
+  if (bytes != ORC_HEADER + wbytes + 4u * pw + 4u * v->t) return ORC_ECORRUPT;
+  v->payload = enc + ORC_HEADER + wbytes;
+  v->tail = v->payload + 4u * pw;
+  return ORC_OK;
+}
+
+int orc_decoded_length(const uint8_t *enc, size_t bytes, uint64_t *n) {
+  orc_view v;
+  int rc = orc_parse(enc, bytes, &v);
+  if (rc) return rc;
+  *n = v.n;
+  return ORC_OK;
+}
+
+/* Widths of the blocks, for tests of the per-block size formula. */
+int orc_widths(const uint8_t *enc, size_t bytes, uint8_t *out, uint64_t cap, uint64_t *nb) {
+  orc_view v;
+  int rc = orc_parse(enc, bytes, &v);
+  if (rc) return rc;
+  *nb = v.nb;
+  if (cap < v.nb) return ORC_ERANGE;
+  memcpy(out, v.widths, (size_t)v.nb);
+  return ORC_OK;
+}
+
+/* Random-access extraction of delta p (0..127) of a block whose 4b payload
+ * words start at byte pointer w: lane j = p mod 4, position q = p div 4,
+ * bits [qb, qb+b) of lane j's stream.  The 64-bit window holds lane words
+ * m and m+1 (payload words 4m+j and 4m+4+j). */
+static uint32_t orc_extract(const uint8_t *w, uint32_t b, uint32_t p) {
+  if (b == 0) return 0;
+  uint32_t j = p % 4u, q = p / 4u;
+  uint32_t bit = q * b, m = bit / 32u, s = bit % 32u;
+  uint64_t window = get32(w + 4u * (4u * m + j));
+  if (s + b > 32u) window |= (uint64_t)get32(w + 4u * (4u * (m + 1u) + j)) << 32;
+  uint64_t mask = (b == 32u) ? 0xFFFFFFFFull : (((uint64_t)1 << b) - 1u);
+  return (uint32_t)((window >> s) & mask);
+}
+
+/* Decode: unpack every delta by random access, then the D4 inverse as one
+ * running sum per residue class mod 4 over the whole list (Sec. 5), then
+ * copy the raw tail. */
+int orc_decode(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, uint64_t *n_out) {
+  orc_view v;
+  int rc = orc_parse(enc, bytes, &v);
+  if (rc) return rc;
+  if (n_out) *n_out = v.n;
+  if (cap < v.n) return ORC_ERANGE;
+  uint64_t word_base = 0;
+  for (uint64_t k = 0; k < v.nb; ++k) {
+    uint32_t b = v.widths[k];
+    for (uint32_t p = 0; p < 128u; ++p)
+      out[128u * k + p] = orc_extract(v.payload + 4u * word_base, b, p);
+    word_base += 4u * b;
+  }
+  for (uint64_t i = 4; i < 128u * v.nb; ++i) out[i] += out[i - 4];
+  for (uint64_t i = 0; i < v.t; ++i) out[128u * v.nb + i] = get32(v.tail + 4u * i);
+  return ORC_OK;
+}
+
+/* Second, structurally different decoder that follows the steps of the
+ * paper's block unpacking procedure (Alg. 1): walk the b input vectors
+ * (four lanes each) with a running bit offset i; while a whole value fits
+ * in the current vector, shift it out and mask; otherwise complete it with
+ * the low bits of the next vector shifted left by 32-i; after each
+ * 4-vector apply the D4 prefix P(t,v) = t + v and make t the new seed. */
+static void orc_alg1_block(const uint8_t *y, uint32_t b, uint32_t v[4], uint32_t *w) {
+  uint32_t M = (b == 32u) ? 0xFFFFFFFFu : ((1u << b) - 1u);
+  uint32_t produced = 0;
+  if (b == 0) {
+    /* no input vectors: 128 zero deltas, so each output is the seed */
+    for (uint32_t r = 0; r < 32u; ++r)
+      for (uint32_t c = 0; c < 4u; ++c) w[4u * r + c] = v[c];
+    return;
+  }
+  uint32_t i = 0;
+  for (uint32_t k = 0; k < b; ++k) {
+    while (i + b <= 32u) {
+      for (uint32_t c = 0; c < 4u; ++c) {
+        uint32_t t = (get32(y + 4u * (4u * k + c)) >> i) & M;
+        v[c] = t + v[c];
+        w[4u * produced + c] = v[c];
+      }
+      ++produced;
+      i += b;
+    }
+    if (i < 32u) {
+      for (uint32_t c = 0; c < 4u; ++c) {
+        uint32_t z = (get32(y + 4u * (4u * (k + 1u) + c)) << (32u - i)) & M;
+        uint32_t t = (get32(y + 4u * (4u * k + c)) >> i) | z;
+        v[c] = t + v[c];
+        w[4u * produced + c] = v[c];
+      }
+      ++produced;
+      i = i + b - 32u;
+    } else {
+      i = 0;
+    }
+  }
+}
+
+int orc_decode_alg1(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, uint64_t *n_out) {
+  orc_view v;
+  int rc = orc_parse(enc, bytes, &v);
+  if (rc) return rc;
+  if (n_out) *n_out = v.n;
+  if (cap < v.n) return ORC_ERANGE;
+  uint32_t seed[4] = {0, 0, 0, 0};
+  uint64_t word_base = 0;
+  for (uint64_t k = 0; k < v.nb; ++k) {
+    uint32_t b = v.widths[k];
+    orc_alg1_block(v.payload + 4u * word_base, b, seed, out + 128u * k);
+    word_base += 4u * b;
+  }
+  for (uint64_t i = 0; i < v.t; ++i) out[128u * v.nb + i] = get32(v.tail + 4u * i);
+  return ORC_OK;
+}
+
+/* Textbook two-pointer merge intersection ("scalar", Sec. 6): advance the
+ * pointer at the smaller value; on equality emit once and advance both.
+ * Inputs must be strictly increasing.  Safe when out aliases the shorter
+ * input (the output-to-input property, Sec. 6.2). */
+int orc_intersect(const uint32_t *a, uint64_t m, const uint32_t *b, uint64_t n, uint32_t *out,
+                  uint64_t *count) {
+  if (!count) return ORC_EINVAL;
+  for (uint64_t i = 1; i < m; ++i) if (a[i] <= a[i - 1]) return ORC_EUNSORTED;
+  for (uint64_t i = 1; i < n; ++i) if (b[i] <= b[i - 1]) return ORC_EUNSORTED;
+  uint64_t i = 0, j = 0, c = 0;
+  while (i < m && j < n) {
+    if (a[i] < b[j]) ++i;
+    else if (b[j] < a[i]) ++j;
+    else { out[c++] = a[i]; ++i; ++j; }
+  }
+  *count = c;
+  return ORC_OK;
+}
+
+/* k-way intersection as a left fold of the pairwise merge in the order
+ * given (the result is a set, so any order gives the same answer; SvS
+ * order is an optimisation only, Sec. 6).  k = 1 copies the list. */
+int orc_intersect_k(const uint32_t *const *lists, const uint64_t *lens, uint32_t k, uint32_t *out,
+                    uint64_t cap, uint64_t *count) {
+  if (!count || k == 0) return ORC_EINVAL;
+  for (uint32_t l = 0; l < k; ++l)
+    for (uint64_t i = 1; i < lens[l]; ++i)
+      if (lists[l][i] <= lists[l][i - 1]) return ORC_EUNSORTED;
+  uint64_t cur = lens[0];
+  if (cap < cur) {
+    /* the result is never longer than the first list; require room for it */
+    return ORC_ERANGE;
+  }
+  memcpy(out, lists[0], (size_t)cur * sizeof(uint32_t));
+  for (uint32_t l = 1; l < k; ++l) {
+    uint64_t c = 0;
+    int rc = orc_intersect(out, cur, lists[l], lens[l], out, &c);
+    if (rc) return rc;
+    cur = c;
+  }
+  *count = cur;
+  return ORC_OK;
+}

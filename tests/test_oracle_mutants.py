@@ -1,0 +1,82 @@
+"""Plant plausible mistakes in copies of the oracle (on the CPU) and check
+that the pins reject every one of them: a dropped term, a wrong index, a
+wrong comparison, a transposed operand."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = {
+    "delta_stride": ("x[i] - (i >= 4 ? x[i - 4] : 0u)", "x[i] - (i >= 4 ? x[i - 3] : 0u)"),
+    "inverse_stride": ("out[i] += out[i - 4];", "out[i] += out[i - 1];"),
+    "lane_word_index": ("get32(w + 4u * (4u * m + j))", "get32(w + 4u * (4u * j + m))"),
+    "width_compare": ("(uint64_t)d[i] >= ((uint64_t)1 << b)", "(uint64_t)d[i] > ((uint64_t)1 << b)"),
+    "width_drops_last": ("orc_width(d + 128u * k, 128u)", "orc_width(d + 128u * k, 127u)"),
+    "pack_lane_order": ("d[128u * k + 4u * q + j]", "d[128u * k + 32u * j + q]"),
+    "merge_advance": ("else if (b[j] < a[i]) ++j;", "else if (b[j] < a[i]) ++i;"),
+    "alg1_straddle_shift": ("<< (32u - i)) & M;", "<< (31u - i)) & M;"),
+    "alg1_dropped_prefix": ("v[c] = t + v[c];\n        w[4u * produced + c] = v[c];\n      }\n      ++produced;\n      i += b;",
+                            "v[c] = t;\n        w[4u * produced + c] = v[c];\n      }\n      ++produced;\n      i += b;"),
+    "b32_mask": ("(b == 32u) ? 0xFFFFFFFFull", "(b == 32u) ? 0x7FFFFFFFull"),
+    "tail_offset": ("out[128u * v.nb + i] = get32(v.tail + 4u * i);\n  return ORC_OK;\n}\n\n/* Second",
+                    "out[128u * v.nb + i] = get32(v.tail);\n  return ORC_OK;\n}\n\n/* Second"),
+    "extract_shift": ("(uint32_t)((window >> s) & mask)", "(uint32_t)((window >> (s + 1)) & mask)"),
+}
+
+
+def battery():
+    """Run the pins; return the names of those that failed."""
+    failed = []
+    checks = [
+        ("fig1c", pins.test_fig1c_bytes_are_one_lane_stream),
+        ("fig2", pins.test_fig2_interleaved_layout),
+        ("b32", pins.test_b32_block_is_raw_words),
+        ("b0", pins.test_b0_block_repeats_seed),
+        ("mixed", pins.test_mixed_widths_all_values),
+        ("width_floor", pins.test_width_floor_strictly_increasing),
+        ("plain_pair", pins.test_intersect_matches_numpy_set_routine),
+        ("k_invariants", pins.test_intersect_k_invariants),
+        ("random_subsets", pins.test_intersect_random_subsets_of_12),
+    ]
+    for b in (0, 1, 7, 18, 31, 32):
+        checks.append((f"alg1_b{b}", lambda b=b: pins.test_random_access_matches_alg1_walk(b)))
+        checks.append((f"round_trip_b{b}", lambda b=b: pins.test_round_trip_per_width(b)))
+    for n in (129, 2049):
+        checks.append((f"edge_{n}", lambda n=n: pins.test_round_trip_edge_lengths(n)))
+    for s in range(2):
+        checks.append((f"formula_{s}", lambda s=s: pins.test_bits_per_block_formula_and_widths(s)))
+    checks.append(("ap", lambda: pins.test_arithmetic_progression_closed_form(7, 3)))
+    for p in (0, 127):
+        checks.append((f"jump_{p}", lambda p=p: pins.test_width_reaches_every_position(p)))
+    for name, fn in checks:
+        try:
+            fn()
+        except (AssertionError, oracle.OracleError, ValueError, IndexError):
+            failed.append(name)
+    return failed
+
+
+def test_unmutated_oracle_passes_battery():
+    assert battery() == []
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / f"lib{name}.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", str(so), str(path)])
+    with oracle.use_variant(str(so)):
+        failed = battery()
+    assert failed, f"mutant {name} survived every pin"

@@ -1,0 +1,347 @@
+"""Pins for the CPU oracle: each test checks it against something the paper or
+mathematics fixes independently of the oracle's own code (worked examples,
+closed forms, invariants, brute force), never against a retyping of the
+oracle itself."""
+import itertools
+import struct
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from conftest import read_golden
+
+
+def lane_words(enc, block_word_base, b, lane):
+    """The b payload words of one lane of a block, in stream order."""
+    nb = struct.unpack_from("<I", enc.tobytes(), 16)[0]
+    payload_off = 32 + ((nb + 3) & ~3)
+    base = payload_off + 4 * block_word_base
+    return [struct.unpack_from("<I", enc.tobytes(), base + 4 * (4 * m + lane))[0] for m in range(b)]
+
+
+def header(enc):
+    magic, ver, flags, n, nb, t, pw = struct.unpack_from("<IHHQIIQ", enc.tobytes(), 0)
+    return dict(magic=magic, version=ver, flags=flags, n=n, nb=nb, t=t, pw=pw)
+
+
+# ------------------------------------------------------------- worked examples
+
+def test_fig1c_bytes_are_one_lane_stream():
+    """Fig. 1(c): 1, 3840, 131073, 2 at b = 18 are the 9 bytes printed in the
+    figure.  Every lane of the block carries these deltas (each value is
+    repeated four times, so the D4 deltas of every lane are the same), so
+    lane 0's stream must start with exactly those bytes."""
+    rows = {r[0]: r[1:] for r in read_golden("fig1c_packed.txt")}
+    vals = [int(v) for v in rows["values"]]
+    b = int(rows["bits"][0])
+    want = bytes(int(h, 16) for h in rows["bytes"])
+    x, acc = [], 0
+    for v in vals:
+        acc += v
+        x += [acc] * 4
+    x += [acc] * (128 - len(x))            # zero deltas afterwards
+    enc = oracle.encode(np.array(x, np.uint32))
+    assert list(oracle.widths(enc)) == [b]
+    words = lane_words(enc, 0, b, lane=0)
+    stream = b"".join(struct.pack("<I", w) for w in words)
+    assert stream[:9] == want
+    assert set(stream[9:]) == {0}
+    for lane in range(1, 4):
+        assert lane_words(enc, 0, b, lane) == words
+
+
+def test_fig2_interleaved_layout():
+    """Fig. 2 at b = 18: placement of x1..x9 in the interleaved words."""
+    rows = read_golden("fig2_interleave.txt")
+    b = int(rows[0][1])
+    rng = np.random.default_rng(7)
+    # sorted list: first quad 0,0,0,1, then consecutive gaps in [2^14, 2^16),
+    # so every later D4 delta (a sum of four gaps) lies in [2^16, 2^18)
+    gaps = rng.integers(1 << 14, 1 << 16, size=128).astype(np.int64)
+    gaps[:4] = [0, 0, 0, 1]
+    gaps[4] = 1 << 15
+    x = np.cumsum(gaps).astype(np.uint32)
+    d = [int(x[i]) - (int(x[i - 4]) if i >= 4 else 0) for i in range(128)]
+    assert max(d).bit_length() == b
+    enc = oracle.encode(x)
+    assert list(oracle.widths(enc)) == [b]
+    nb = header(enc)["nb"]
+    payload_off = 32 + ((nb + 3) & ~3)
+    words = struct.unpack_from(f"<{4 * b}I", enc.tobytes(), payload_off)
+    for r in rows[1:]:
+        xi = int(r[0][1:]) - 1
+        wi = int(r[1][4:]) - 1
+        bit = int(r[2][3:])
+        ln = int(r[3][3:])
+        frm = int(r[4][4:])
+        got = (words[wi] >> bit) & ((1 << ln) - 1)
+        assert got == (d[xi] >> frm) & ((1 << ln) - 1), r
+
+
+# ---------------------------------------------------------- two decoders agree
+
+def synthetic_stream(widths, rng, tail=()):
+    """A valid stream with arbitrary payload bits (not produced by encode)."""
+    nb = len(widths)
+    pw = 4 * sum(widths)
+    n = 128 * nb + len(tail)
+    hdr = struct.pack("<IHHQIIQ", oracle.MAGIC, 1, 0, n, nb, len(tail), pw)
+    wb = bytes(widths) + b"\0" * (((nb + 3) & ~3) - nb)
+    payload = rng.integers(0, 2**32, size=pw, dtype=np.uint64).astype(np.uint32).tobytes()
+    tl = np.array(tail, np.uint32).tobytes()
+    return np.frombuffer(hdr + wb + payload + tl, np.uint8).copy()
+
+
+@pytest.mark.parametrize("b", range(33))
+def test_random_access_matches_alg1_walk(b):
+    """The random-access extractor and the Alg. 1 vector walk are written
+    differently; on arbitrary payload bits at every width they must agree."""
+    rng = np.random.default_rng(100 + b)
+    enc = synthetic_stream([b, b, (b * 7) % 33, b], rng, tail=[5, 9])
+    assert np.array_equal(oracle.decode(enc), oracle.decode_alg1(enc))
+
+
+def test_mixed_widths_all_values():
+    rng = np.random.default_rng(3)
+    enc = synthetic_stream(list(range(33)) + list(range(32, -1, -1)), rng)
+    assert np.array_equal(oracle.decode(enc), oracle.decode_alg1(enc))
+
+
+def test_b32_block_is_raw_words():
+    """At b = 32 each lane word holds one delta verbatim (mask = all ones)."""
+    rng = np.random.default_rng(5)
+    enc = synthetic_stream([32], rng)
+    nb = 1
+    words = np.frombuffer(enc.tobytes()[32 + 4: 32 + 4 + 512], np.uint32)
+    out = oracle.decode(enc).astype(np.uint64)
+    # D4 inverse of raw deltas: out[p] = sum of words of lane p%4 up to q
+    d = words.reshape(32, 4).astype(np.uint64)
+    assert np.array_equal(out.reshape(32, 4), np.cumsum(d, axis=0) % (1 << 32))
+
+
+def test_b0_block_repeats_seed():
+    """b = 0 (reading A4): 128 zero deltas, every lane keeps its seed."""
+    x = np.full(256, 3, np.uint32)
+    enc = oracle.encode(x)
+    assert list(oracle.widths(enc)) == [2, 0]
+    assert np.array_equal(oracle.decode(enc), x)
+    assert np.array_equal(oracle.decode_alg1(enc), x)
+
+
+# ------------------------------------------------------------ round trips
+
+def recipe_list(b, n=4096, seed=0):
+    """Sec. 7.1 recipe: 4096 integers whose D4 gaps are below 2^b, built
+    as a sorted list (each consecutive gap below 2^b / 4)."""
+    rng = np.random.default_rng(seed + b)
+    g = max(1, (1 << b) // 4) if b >= 2 else 1
+    if b == 0:
+        return np.zeros(n, np.uint32)
+    if b == 1:
+        gaps = np.zeros(n, np.uint64)
+        gaps[::4] = rng.integers(0, 2, size=(n + 3) // 4)
+        gaps[:4] = 0
+    else:
+        gaps = rng.integers(0, g, size=n).astype(np.uint64)
+    x = np.cumsum(gaps) % (1 << 32)
+    x.sort()
+    return x.astype(np.uint32)
+
+
+@pytest.mark.parametrize("b", range(33))
+def test_round_trip_per_width(b):
+    x = recipe_list(b)
+    enc = oracle.encode(x)
+    w = oracle.widths(enc)
+    assert w.max() <= max(b, 1) or b == 32
+    assert np.array_equal(oracle.decode(enc), x)
+    assert np.array_equal(oracle.decode_alg1(enc), x)
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4, 5, 127, 128, 129, 255, 256, 2047, 2048, 2049, 4096 + 77])
+def test_round_trip_edge_lengths(n):
+    x = workloads.sorted_list(workloads.UNIFORM, 42 + n, 1 << 25, n)
+    enc = oracle.encode(x)
+    h = header(enc)
+    assert h["n"] == n and h["nb"] == n // 128 and h["t"] == n % 128
+    assert h["flags"] == 1
+    assert np.array_equal(oracle.decode(enc), x)
+    assert np.array_equal(oracle.decode_alg1(enc), x)
+
+
+def test_round_trip_full_range_values():
+    x = np.array(sorted({0, 1, 2**31, 2**32 - 1, 2**32 - 2} | set(range(5, 700, 3))), np.uint32)
+    enc = oracle.encode(x)
+    assert np.array_equal(oracle.decode(enc), x)
+
+
+# ------------------------------------------------ size formula and widths
+
+def brute_width(vals):
+    """Sec. 4.3 definition, by search: smallest b with all values < 2^b."""
+    for b in range(33):
+        if all(v < 2**b for v in vals):
+            return b
+    raise AssertionError
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bits_per_block_formula_and_widths(seed):
+    """Encoded size = header + width bytes (padded to 4) + 16 b bytes per
+    block (Sec. 4.2) + 4 bytes per tail integer; every width is the
+    smallest b that holds the block's D4 deltas (Sec. 4.3, Sec. 5)."""
+    n = 128 * 37 + seed * 31
+    kind = workloads.CLUSTERED if seed % 2 else workloads.UNIFORM
+    x = workloads.sorted_list(kind, 1000 + seed, 1 << (20 + 3 * seed), n)
+    xi = [int(v) for v in x]
+    enc = oracle.encode(x)
+    w = [int(v) for v in oracle.widths(enc)]
+    nb = n // 128
+    assert len(w) == nb
+    for k in range(nb):
+        deltas = [xi[i] - (xi[i - 4] if i >= 4 else 0) for i in range(128 * k, 128 * k + 128)]
+        assert w[k] == brute_width(deltas)
+    expect = 32 + ((nb + 3) // 4) * 4 + sum(16 * b for b in w) + 4 * (n % 128)
+    assert enc.size == expect
+    assert oracle.stream_bytes(n, np.array(w, np.uint8)) == expect
+
+
+@pytest.mark.parametrize("c,s", [(0, 1), (7, 3), (1000, 255), (5, 1 << 20), (0, (1 << 30) // 700)])
+def test_arithmetic_progression_closed_form(c, s):
+    """x_i = c + s i: every D4 delta past the first quad is 4s, so blocks
+    k >= 1 have width bitlen(4s); block 0 also holds x_0..x_3."""
+    n = 128 * 5 + 9
+    x = (c + s * np.arange(n, dtype=np.uint64))
+    assert x[-1] < 2**32
+    enc = oracle.encode(x.astype(np.uint32))
+    w = oracle.widths(enc)
+    assert int(w[0]) == max((c + 3 * s).bit_length(), (4 * s).bit_length())
+    assert all(int(b) == (4 * s).bit_length() for b in w[1:])
+    assert np.array_equal(oracle.decode(enc), x.astype(np.uint32))
+
+
+@pytest.mark.parametrize("p", [0, 3, 61, 124, 127])
+def test_width_reaches_every_position(p):
+    """A single jump of J at position p raises only the D4 deltas at
+    p..p+3 to 4 + J: the block width must follow it wherever it sits,
+    including the last delta of the block."""
+    J = 1000
+    x = np.arange(128, dtype=np.uint32)
+    x[p:] += J
+    w = oracle.widths(oracle.encode(x))
+    assert int(w[0]) == (4 + J).bit_length()
+    assert np.array_equal(oracle.decode(oracle.encode(x)), x)
+
+
+def test_width_floor_strictly_increasing():
+    """Strictly increasing input: every D4 delta after the first quad is
+    >= 4, so every block after the first has width >= 3."""
+    for seed in range(5):
+        x = workloads.sorted_list(workloads.CLUSTERED, 77 + seed, 1 << 26, 128 * 50)
+        w = oracle.widths(oracle.encode(x))
+        assert w[1:].min() >= 3
+
+
+def test_first_block_width_uses_zero_seed():
+    """The first quad's deltas are the values themselves (seed 0)."""
+    x = np.arange(128, dtype=np.uint32) + np.uint32(1 << 20)
+    w = oracle.widths(oracle.encode(x))
+    assert int(w[0]) == 21
+
+
+# ------------------------------------------------------------- errors
+
+def test_unsorted_rejected():
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.encode(np.array([1, 2, 3, 2], np.uint32))
+    assert e.value.code == oracle.EUNSORTED
+
+
+def test_corrupt_streams_rejected():
+    x = workloads.sorted_list(workloads.UNIFORM, 9, 1 << 20, 300)
+    enc = oracle.encode(x)
+    bad = [enc[:-1], enc.copy(), enc.copy(), enc.copy(), np.concatenate([enc, [0, 0, 0, 0]])]
+    bad[1][0] ^= 1                     # magic
+    bad[2][32] = 33                    # width > 32
+    bad[3][8] ^= 1                     # n inconsistent with nb, t
+    for e in bad:
+        with pytest.raises(oracle.OracleError) as ex:
+            oracle.decode(e)
+        assert ex.value.code == oracle.ECORRUPT
+
+
+def test_duplicates_allowed_by_codec_flag_cleared():
+    x = np.array([1, 1, 2, 3, 3, 3, 9] * 40, np.uint32)
+    x.sort()
+    enc = oracle.encode(x)
+    assert header(enc)["flags"] == 0
+    assert np.array_equal(oracle.decode(enc), x)
+
+
+# ------------------------------------------------------- intersection
+
+def brute_intersection(a, b):
+    """O(mn): keep each element of a that equals some element of b."""
+    out = []
+    for u in a:
+        for v in b:
+            if u == v:
+                out.append(u)
+                break
+    return out
+
+
+def test_intersect_exhaustive_small_universe():
+    """Every pair of subsets of [0, 7)."""
+    subsets = [list(c) for r in range(8) for c in itertools.combinations(range(7), r)]
+    for a in subsets:
+        for b in subsets:
+            got = oracle.intersect(np.array(a, np.uint32), np.array(b, np.uint32)).tolist()
+            assert got == brute_intersection(a, b)
+
+
+def test_intersect_random_subsets_of_12():
+    rng = np.random.default_rng(11)
+    for _ in range(3000):
+        a = np.flatnonzero(rng.random(12) < rng.random())
+        b = np.flatnonzero(rng.random(12) < rng.random())
+        got = oracle.intersect(a.astype(np.uint32), b.astype(np.uint32)).tolist()
+        assert got == brute_intersection(a.tolist(), b.tolist())
+
+
+def test_intersect_matches_numpy_set_routine():
+    a, b = workloads.plain_pair()
+    got = oracle.intersect(a, b)
+    assert np.array_equal(got, np.intersect1d(a, b, assume_unique=True))
+    assert np.array_equal(got, oracle.intersect(b, a))
+
+
+def test_plain_pair_intersection_size_is_plausible():
+    """E|A n B| = 2^20 2^14 / 2^25 = 512, sd about 22 (hypergeometric)."""
+    a, b = workloads.plain_pair()
+    c = oracle.intersect(a, b).size
+    assert abs(c - 512) < 6 * 23
+
+
+def test_intersect_rejects_unsorted_and_duplicates():
+    with pytest.raises(oracle.OracleError):
+        oracle.intersect(np.array([1, 1, 2], np.uint32), np.array([1], np.uint32))
+    with pytest.raises(oracle.OracleError):
+        oracle.intersect(np.array([3, 2], np.uint32), np.array([1], np.uint32))
+
+
+def test_intersect_k_invariants():
+    rng = np.random.default_rng(5)
+    lists = [np.unique(rng.integers(0, 300, size=rng.integers(0, 200))).astype(np.uint32)
+             for _ in range(4)]
+    ref = set(lists[0].tolist())
+    for l in lists[1:]:
+        ref &= set(l.tolist())
+    ref = sorted(ref)
+    for perm in itertools.permutations(range(4)):
+        assert oracle.intersect_k([lists[i] for i in perm]).tolist() == ref
+    assert oracle.intersect_k([lists[0]]).tolist() == lists[0].tolist()
+    assert oracle.intersect_k([lists[1], lists[1]]).tolist() == lists[1].tolist()
+    assert oracle.intersect_k([lists[2], np.zeros(0, np.uint32)]).tolist() == []
