@@ -1,0 +1,280 @@
+/*
+ * s4.h -- C ABI of the MI355X (gfx950) S4-BP128-D4 decode + intersection
+ * library (libs4.so).
+ *
+ * Method: D. Lemire, L. Boytsov, N. Kurz, "SIMD Compression and the
+ * Intersection of Sorted Integers" (arXiv:1401.6399).  Sorted 32-bit
+ * document-ID lists (Sec. 1) are stored as S4-BP128-D4: blocks of 128
+ * integers, one bit width per block (Sec. 4.3), 4-way interleaved bit
+ * packing (Sec. 4.2, Fig. 2), stride-4 differential coding (Sec. 5, Alg. 1);
+ * conjunctive queries intersect the decoded lists two at a time, shortest
+ * first (SvS, Sec. 6).
+ *
+ * Conventions for every call:
+ *   - Return value: S4_OK (0) or a negative S4_E* code; s4_last_error()
+ *     gives a thread-local message for the last failure.  No C++ exception
+ *     crosses this boundary.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers (d_*) are
+ *     HIP device memory on the current device.  The caller owns every raw
+ *     buffer it passes; the library owns the opaque handles it returns and
+ *     frees them only in the matching *_free / *_destroy call.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Device calls
+ *     are stream-ordered and asynchronous: they enqueue work and return;
+ *     counts are written to device memory, so no call synchronises unless
+ *     it says so.  A fault inside a kernel surfaces at the caller's next
+ *     synchronisation (hipStreamSynchronize), or as S4_EDEVICE from a later
+ *     call that checks the stream.
+ *   - Device output buffers must be 16-byte aligned.
+ */
+#ifndef S4_H
+#define S4_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define S4_OK 0
+#define S4_EINVAL (-1)    /* bad argument (null pointer, k = 0, misaligned buffer, ...) */
+#define S4_EUNSORTED (-2) /* input not non-decreasing (encode) or not strictly increasing
+                             (intersections) */
+#define S4_ERANGE (-3)    /* output or scratch capacity too small */
+#define S4_ECORRUPT (-4)  /* serialized stream malformed or truncated */
+#define S4_ENOMEM (-5)    /* host or device allocation failed */
+#define S4_EDEVICE (-6)   /* HIP runtime error or no usable gfx950 device */
+#define S4_EAGAIN (-7)    /* server: no slot or memory free right now; retry later */
+
+const char *s4_last_error(void);
+int s4_version(void); /* stream format version written by s4_encode (1) */
+
+/* ------------------------------------------------------------------ codec
+ *
+ * Serialized S4-BP128-D4 stream (little-endian, all offsets in bytes):
+ *   0  u32 magic 0x34443453 ("S4D4")      4  u16 version = 1
+ *   6  u16 flags (bit 0: strictly increasing; other bits 0)
+ *   8  u64 n      16 u32 nb = floor(n/128)  20 u32 t = n - 128 nb
+ *   24 u64 pw = sum over blocks of 4 b_k (payload 32-bit words)
+ *   32 u8 widths[nb], zero-padded to a multiple of 4 bytes
+ *      u32 payload[pw]   block k holds 4 b_k words: word 4m + j is the
+ *                        m-th word of lane j; lane j packs the D4 deltas
+ *                        of integers 4q + j (q = 0..31), b_k bits each,
+ *                        least significant bit first (Sec. 4.2, Fig. 2)
+ *      u32 tail[t]       the last t < 128 integers, raw (the paper uses
+ *                        varint here, Sec. 4.3)
+ * Width b_k is the smallest b with every D4 delta of block k below 2^b
+ * (Sec. 4.3); D4 delta i is x_i - x_{i-4} with x_{-4..-1} = 0 (Sec. 5).
+ */
+
+/* Worst-case stream size for n integers (every block at b = 32). */
+size_t s4_encoded_bound(uint64_t n);
+
+/* Encode host list in[n] (non-decreasing, duplicates allowed) into host
+ * buffer out[cap].  *out_bytes receives the stream size (also on
+ * S4_ERANGE, so the call can size the buffer).  S4_EUNSORTED if in[] ever
+ * decreases. Sec. 4.2-4.3, Sec. 5. */
+int s4_encode(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes);
+
+/* Encode `count` host lists in parallel: list i is in[in_offsets[i] ..
+ * in_offsets[i+1]) and its stream is written to out + out_offsets[i], which
+ * the caller sizes with s4_encoded_bound; out_bytes[i] receives each size.
+ * nthreads <= 0 picks the number of hardware threads. */
+int s4_encode_many(const uint32_t *in, const uint64_t *in_offsets, uint64_t count, uint8_t *out,
+                   const uint64_t *out_offsets, uint64_t *out_bytes, int nthreads);
+
+/* Number of integers in a stream; validates the whole header and width
+ * table (S4_ECORRUPT on any inconsistency). */
+int s4_decoded_length(const uint8_t *enc, size_t bytes, uint64_t *n);
+
+/* ----------------------------------------------------------- device lists
+ *
+ * s4_list: one list resident in device memory, structure of arrays:
+ * widths u8[nb], block word offsets u32[nb], payload u32[pw] (+32 bytes of
+ * padding), raw tail u32[t], and a skip index built on the device at upload:
+ * bmax[k] = x[128k + 127] (the block's largest value) and seed[k] =
+ * x[128k-4 .. 128k-1] (zeros for k = 0), the D4 prefix seed that lets any
+ * block be decoded alone (Alg. 1 seeds each block with the previous
+ * block's last four values).  The skip index is not part of the paper.
+ */
+typedef struct s4_list s4_list;
+
+/* Upload host stream enc[bytes]; builds the skip index with two kernels on
+ * `stream`.  Validates the stream (S4_ECORRUPT).  The host buffer may be
+ * reused once the call returns. */
+int s4_list_upload(const uint8_t *enc, size_t bytes, void *stream, s4_list **out);
+int s4_list_free(s4_list *list);
+
+/* Length facts of an uploaded list (host values, no device access).
+ * payload_bytes counts widths + payload + tail (the paper's size);
+ * index_bytes counts block offsets + skip index. */
+int s4_list_info(const s4_list *list, uint64_t *n, uint32_t *nb, uint32_t *flags,
+                 uint64_t *payload_bytes, uint64_t *index_bytes);
+
+/* Copy the skip index to host arrays bmax[nb] and seeds[4 nb]
+ * (synchronises `stream`).  For tests and tools. */
+int s4_list_skip_index(const s4_list *list, uint32_t *bmax, uint32_t *seeds, void *stream);
+
+/* Decode the whole list into device buffer d_out[cap] (cap >= n) on
+ * `stream`: unpack + D4 prefix sum fused in one kernel (Alg. 1), tail
+ * copied.  S4_ERANGE if cap < n. */
+int s4_decode_dev(const s4_list *list, uint32_t *d_out, uint64_t cap, void *stream);
+
+/* Decode blocks [first, first + count) into d_out (128 values per block);
+ * block index nb denotes the tail (t values).  Each block is seeded from
+ * the skip index, so any range decodes alone. */
+int s4_decode_blocks_dev(const s4_list *list, uint32_t first, uint32_t count, uint32_t *d_out,
+                         void *stream);
+
+/* --------------------------------------------------------- intersections
+ *
+ * Inputs must have been encoded from strictly increasing lists (flag bit 0),
+ * else S4_EUNSORTED.  Results are strictly increasing and never longer than
+ * the shorter input (the output-to-input property, Sec. 6.2), so
+ * cap >= min(len a, len b) is always enough; a smaller cap is S4_ERANGE.
+ * The count is written to device memory *d_count (u64).  Scratch is a
+ * caller-owned device buffer of at least the size the *_scratch_bytes call
+ * reports; its contents on entry do not matter.
+ */
+size_t s4_intersect_scratch_bytes(uint64_t len_a, uint64_t len_b);
+int s4_intersect(const s4_list *a, const s4_list *b, uint32_t *d_out, uint64_t cap,
+                 uint64_t *d_count, void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* k-way conjunction (SvS, Sec. 6): lists are ordered by length, the two
+ * shortest are intersected (both compressed), then the uncompressed
+ * intermediate is intersected with each next list in turn, decoding only
+ * the blocks it needs.  k = 0 is S4_EINVAL; k = 1 decodes the list. */
+size_t s4_intersect_k_scratch_bytes(const s4_list *const *lists, uint32_t k);
+int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap,
+                   uint64_t *d_count, void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* Intersect an uncompressed strictly increasing device list d_r[*d_len_r]
+ * (its length read on the device) with compressed list f; the building
+ * block of the chain above.  cap_r is the host-known upper bound of
+ * *d_len_r (sizes the launch and the scratch). */
+size_t s4_intersect_raw_scratch_bytes(uint64_t cap_r);
+int s4_intersect_raw(const uint32_t *d_r, const uint64_t *d_len_r, uint64_t cap_r,
+                     const s4_list *f, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
+                     void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* ---------------------------------------------------------------- tuning
+ *
+ * gallop_blocks: when a 128-value chunk of the short list spans more than
+ * this many blocks of the long list, candidate blocks are found by per-lane
+ * binary search over the long list's bmax in global memory (galloping
+ * regime, Sec. 6.1); otherwise the spanned bmax entries are staged in LDS
+ * first (merge regime).  Only candidate blocks are ever decoded.
+ * waves_per_group: waves per workgroup of the intersection kernels (1..8).
+ * groups_per_cu: resident workgroups per compute unit for persistent
+ * (batch) launches.  items_per_grab: work items a wave takes per atomic
+ * fetch in persistent launches.  Results never depend on these values. */
+typedef struct {
+  uint32_t gallop_blocks;
+  uint32_t waves_per_group;
+  uint32_t groups_per_cu;
+  uint32_t items_per_grab;
+} s4_tuning;
+
+int s4_get_tuning(s4_tuning *t);
+int s4_set_tuning(const s4_tuning *t);
+
+/* ------------------------------------------------------------------ index
+ *
+ * Many lists in one device arena (CSR of lists), for batched queries.
+ * encs is a host buffer holding `count` streams back to back, stream i at
+ * byte offset enc_offsets[i] with size enc_offsets[i+1] - enc_offsets[i].
+ * Synchronises `stream` before returning.
+ */
+typedef struct s4_index s4_index;
+int s4_index_build(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count, void *stream,
+                   s4_index **out);
+int s4_index_free(s4_index *index);
+/* lengths[count] of the indexed lists (host copy). */
+int s4_index_lengths(const s4_index *index, uint64_t *lengths);
+int s4_index_info(const s4_index *index, uint64_t *count, uint64_t *total_ints,
+                  uint64_t *payload_bytes, uint64_t *index_bytes);
+/* A view of list i of the index usable with every s4_list call; valid
+ * until the index is freed; release it with s4_list_free. */
+int s4_index_list(const s4_index *index, uint64_t i, s4_list **out);
+
+/* ------------------------------------------------------------------ batch
+ *
+ * A batch plan: nq conjunctive queries over an index, query q being terms
+ * h_terms[h_q_offsets[q] .. h_q_offsets[q+1]) (k >= 1 distinct list ids).
+ * The plan orders each query's terms by length (SvS), reserves intermediate
+ * memory from the output-to-input bound, and uploads its tables once.
+ * s4_batch_run executes every query: one persistent decode-fused launch per
+ * chain level (all queries advance together), with small scan/compaction
+ * kernels between levels; with use_graph != 0 the whole sequence is
+ * captured once into a hipGraph and replayed on later runs.
+ * Outputs (device): d_counts[nq] (u64), d_res_offsets[nq + 1] (u64, CSR),
+ * d_results[results_cap] (u32, query q's docIDs at
+ * d_results[d_res_offsets[q] ..]).  results_cap >= s4_batch_results_bound.
+ */
+typedef struct s4_batch s4_batch;
+int s4_batch_plan(const s4_index *index, const uint32_t *h_terms, const uint64_t *h_q_offsets,
+                  uint64_t nq, void *stream, s4_batch **out);
+int s4_batch_free(s4_batch *batch);
+uint64_t s4_batch_results_bound(const s4_batch *batch);
+int s4_batch_run(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offsets, uint32_t *d_results,
+                 uint64_t results_cap, int use_graph, void *stream);
+/* Per-query completion stamps of the last run, in device clock ticks
+ * (100 MHz constant clock) relative to the run's start: host array
+ * ticks[nq].  Synchronises `stream`. */
+int s4_batch_query_ticks(const s4_batch *batch, uint64_t *ticks, void *stream);
+
+/* Autotune gallop_blocks / waves_per_group / groups_per_cu / items_per_grab
+ * on this plan: times `reps` runs per candidate setting, keeps the fastest
+ * and installs it with s4_set_tuning.  best_ms receives its time.  The
+ * plan's results are identical under every candidate. */
+int s4_batch_autotune(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offsets,
+                      uint32_t *d_results, uint64_t results_cap, int reps, void *stream,
+                      s4_tuning *best, double *best_ms);
+
+/* ----------------------------------------------------------------- server
+ *
+ * Continuous-batching query server over a device-resident index.  A
+ * dispatcher thread owns one HIP stream; each iteration admits waiting
+ * queries into free slots while the reserved intermediate memory (the
+ * output-to-input bound of each query) fits the pool, runs one chain level
+ * for every active query in one persistent launch, and retires finished
+ * queries.  Queries that arrive while others run join at the next
+ * iteration.  Submission never blocks on the GPU.
+ */
+typedef struct s4_server s4_server;
+typedef struct {
+  uint32_t max_slots;       /* concurrent queries on the device */
+  uint64_t pool_bytes;      /* intermediate memory for admitted queries */
+  uint64_t result_bytes;    /* device memory for results of one iteration */
+  uint32_t max_terms;       /* longest query accepted */
+} s4_server_config;
+
+int s4_server_create(const s4_index *index, const s4_server_config *cfg, s4_server **out);
+/* Submit a query (host terms[k]); *id receives its ticket.  S4_EINVAL for
+ * bad terms, S4_ERANGE if it can never fit the pool, S4_EAGAIN if the
+ * waiting queue is full. */
+int s4_server_submit(s4_server *srv, const uint32_t *terms, uint32_t k, uint64_t *id);
+/* Retrieve up to max_done finished queries: ids[], counts[], latency_ns[]
+ * (submit -> result on host).  Results are copied to host memory:
+ * results + res_offsets[i] (res_offsets has max_done + 1 entries; the
+ * results buffer holds results_cap integers; a query whose result does not
+ * fit stays queued).  *done receives the number returned.  Non-blocking. */
+int s4_server_poll(s4_server *srv, uint64_t *ids, uint64_t *counts, uint64_t *latency_ns,
+                   uint32_t *results, uint64_t results_cap, uint64_t *res_offsets,
+                   uint32_t max_done, uint32_t *done);
+typedef struct {
+  uint64_t submitted, admitted, completed, rejected;
+  uint64_t iterations;
+  uint64_t peak_active;
+  uint64_t peak_pool_bytes;
+  uint64_t waits_for_memory; /* admissions deferred because the pool was full */
+} s4_server_stats;
+int s4_server_stats_get(const s4_server *srv, s4_server_stats *st);
+/* Stop accepting, finish every admitted query, join the dispatcher. */
+int s4_server_destroy(s4_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* S4_H */

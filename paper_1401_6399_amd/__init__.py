@@ -1,0 +1,492 @@
+"""Python binding of libs4.so (the C ABI declared in include/s4.h).
+
+Argument marshalling only: every step of decode and intersection runs in
+the library's HIP kernels.  Device buffers are torch tensors on the current
+CUDA (HIP) device; the library enqueues on torch's current stream.  If the
+shared library has not been built this module raises on first use: there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libs4.so")
+
+OK, EINVAL, EUNSORTED, ERANGE, ECORRUPT, ENOMEM, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
+
+# every symbol declared in include/s4.h, with (restype, argtypes)
+_vp = ctypes.c_void_p
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_sz = ctypes.c_size_t
+_i = ctypes.c_int
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("gallop_blocks", ctypes.c_uint32), ("waves_per_group", ctypes.c_uint32),
+                ("groups_per_cu", ctypes.c_uint32), ("items_per_grab", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_uint32), ("pool_bytes", ctypes.c_uint64),
+                ("result_bytes", ctypes.c_uint64), ("max_terms", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("iterations", ctypes.c_uint64), ("peak_active", ctypes.c_uint64),
+                ("peak_pool_bytes", ctypes.c_uint64), ("waits_for_memory", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+SIGNATURES = {
+    "s4_last_error": (ctypes.c_char_p, []),
+    "s4_version": (_i, []),
+    "s4_encoded_bound": (_sz, [_u64]),
+    "s4_encode": (_i, [_u32p, _u64, _u8p, _sz, ctypes.POINTER(_sz)]),
+    "s4_encode_many": (_i, [_u32p, _u64p, _u64, _u8p, _u64p, _u64p, _i]),
+    "s4_decoded_length": (_i, [_u8p, _sz, _u64p]),
+    "s4_list_upload": (_i, [_u8p, _sz, _vp, ctypes.POINTER(_vp)]),
+    "s4_list_free": (_i, [_vp]),
+    "s4_list_info": (_i, [_vp, _u64p, _u32p, _u32p, _u64p, _u64p]),
+    "s4_list_skip_index": (_i, [_vp, _u32p, _u32p, _vp]),
+    "s4_decode_dev": (_i, [_vp, _vp, _u64, _vp]),
+    "s4_decode_blocks_dev": (_i, [_vp, _u32, _u32, _vp, _vp]),
+    "s4_intersect_scratch_bytes": (_sz, [_u64, _u64]),
+    "s4_intersect": (_i, [_vp, _vp, _vp, _u64, _vp, _vp, _sz, _vp]),
+    "s4_intersect_k_scratch_bytes": (_sz, [ctypes.POINTER(_vp), _u32]),
+    "s4_intersect_k": (_i, [ctypes.POINTER(_vp), _u32, _vp, _u64, _vp, _vp, _sz, _vp]),
+    "s4_intersect_raw_scratch_bytes": (_sz, [_u64]),
+    "s4_intersect_raw": (_i, [_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp, _sz, _vp]),
+    "s4_get_tuning": (_i, [ctypes.POINTER(Tuning)]),
+    "s4_set_tuning": (_i, [ctypes.POINTER(Tuning)]),
+    "s4_index_build": (_i, [_u8p, _u64p, _u64, _vp, ctypes.POINTER(_vp)]),
+    "s4_index_free": (_i, [_vp]),
+    "s4_index_lengths": (_i, [_vp, _u64p]),
+    "s4_index_info": (_i, [_vp, _u64p, _u64p, _u64p, _u64p]),
+    "s4_index_list": (_i, [_vp, _u64, ctypes.POINTER(_vp)]),
+    "s4_batch_plan": (_i, [_vp, _u32p, _u64p, _u64, _vp, ctypes.POINTER(_vp)]),
+    "s4_batch_free": (_i, [_vp]),
+    "s4_batch_results_bound": (_u64, [_vp]),
+    "s4_batch_run": (_i, [_vp, _vp, _vp, _vp, _u64, _i, _vp]),
+    "s4_batch_query_ticks": (_i, [_vp, _u64p, _vp]),
+    "s4_batch_autotune": (_i, [_vp, _vp, _vp, _vp, _u64, _i, _vp, ctypes.POINTER(Tuning),
+                               ctypes.POINTER(ctypes.c_double)]),
+    "s4_server_create": (_i, [_vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
+    "s4_server_submit": (_i, [_vp, _u32p, _u32, _u64p]),
+    "s4_server_poll": (_i, [_vp, _u64p, _u64p, _u64p, _u32p, _u64, _u64p, _u32, _u32p]),
+    "s4_server_stats_get": (_i, [_vp, ctypes.POINTER(ServerStats)]),
+    "s4_server_destroy": (_i, [_vp]),
+}
+
+
+class S4Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"s4 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def library_built() -> bool:
+    return os.path.exists(LIB_PATH)
+
+
+def require_library():
+    """Load libs4.so or raise: there is no CPU fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(rc, what=""):
+    if rc != OK:
+        msg = require_library().s4_last_error()
+        raise S4Error(rc, (what + ": " if what else "") + (msg.decode() if msg else ""))
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _dptr(t):
+    """Raw device address of a torch tensor (or None)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ codec
+
+def encoded_bound(n: int) -> int:
+    return int(require_library().s4_encoded_bound(n))
+
+
+def encode(x) -> np.ndarray:
+    """Host encode of a non-decreasing uint32 list (s4_encode)."""
+    lib = require_library()
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    cap = encoded_bound(x.size)
+    out = np.zeros(cap, dtype=np.uint8)
+    nbytes = ctypes.c_size_t(0)
+    _check(lib.s4_encode(_ptr(x, ctypes.c_uint32), x.size, _ptr(out, ctypes.c_uint8), cap,
+                         ctypes.byref(nbytes)), "s4_encode")
+    return out[: nbytes.value].copy()
+
+
+def encode_many(flat, offsets, nthreads: int = 0):
+    """Encode many lists at once: returns (streams buffer, stream offsets)."""
+    lib = require_library()
+    flat = np.ascontiguousarray(flat, dtype=np.uint32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    count = offsets.size - 1
+    lens = np.diff(offsets)
+    bounds = np.array([encoded_bound(int(n)) for n in lens], dtype=np.uint64) if count else np.zeros(0, np.uint64)
+    out_offs = np.zeros(count + 1, dtype=np.uint64)
+    np.cumsum(bounds, out=out_offs[1:])
+    buf = np.zeros(max(1, int(out_offs[-1])), dtype=np.uint8)
+    sizes = np.zeros(max(1, count), dtype=np.uint64)
+    _check(lib.s4_encode_many(_ptr(flat if flat.size else np.zeros(1, np.uint32), ctypes.c_uint32),
+                              _ptr(offsets, ctypes.c_uint64), count, _ptr(buf, ctypes.c_uint8),
+                              _ptr(out_offs, ctypes.c_uint64), _ptr(sizes, ctypes.c_uint64), nthreads),
+           "s4_encode_many")
+    # compact the streams back to back
+    sizes = sizes[:count]
+    offs = np.zeros(count + 1, dtype=np.uint64)
+    np.cumsum(sizes, out=offs[1:])
+    packed = np.empty(max(1, int(offs[-1])), dtype=np.uint8)
+    for i in range(count):
+        s, n = int(out_offs[i]), int(sizes[i])
+        packed[int(offs[i]): int(offs[i]) + n] = buf[s: s + n]
+    return packed[: int(offs[-1])], offs
+
+
+def decoded_length(enc) -> int:
+    lib = require_library()
+    enc = np.ascontiguousarray(enc, dtype=np.uint8)
+    n = ctypes.c_uint64(0)
+    _check(lib.s4_decoded_length(_ptr(enc, ctypes.c_uint8), enc.size, ctypes.byref(n)), "s4_decoded_length")
+    return n.value
+
+
+# ----------------------------------------------------------------- lists
+
+class DeviceList:
+    """A list resident in device memory (s4_list)."""
+
+    def __init__(self, handle, owner=None):
+        self.h = ctypes.c_void_p(handle) if not isinstance(handle, ctypes.c_void_p) else handle
+        self._owner = owner
+        n = ctypes.c_uint64(0)
+        nb = ctypes.c_uint32(0)
+        fl = ctypes.c_uint32(0)
+        pb = ctypes.c_uint64(0)
+        ib = ctypes.c_uint64(0)
+        _check(require_library().s4_list_info(self.h, ctypes.byref(n), ctypes.byref(nb), ctypes.byref(fl),
+                                              ctypes.byref(pb), ctypes.byref(ib)), "s4_list_info")
+        self.n, self.nb, self.flags = n.value, nb.value, fl.value
+        self.payload_bytes, self.index_bytes = pb.value, ib.value
+
+    @classmethod
+    def upload(cls, enc, stream=None):
+        lib = require_library()
+        enc = np.ascontiguousarray(enc, dtype=np.uint8)
+        h = ctypes.c_void_p()
+        _check(lib.s4_list_upload(_ptr(enc, ctypes.c_uint8), enc.size, _stream(stream), ctypes.byref(h)),
+               "s4_list_upload")
+        return cls(h)
+
+    def free(self):
+        if self.h:
+            _check(require_library().s4_list_free(self.h), "s4_list_free")
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self.h and require_library() is not None:
+                require_library().s4_list_free(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    def skip_index(self, stream=None):
+        bmax = np.zeros(max(1, self.nb), np.uint32)
+        seeds = np.zeros(max(1, 4 * self.nb), np.uint32)
+        _check(require_library().s4_list_skip_index(self.h, _ptr(bmax, ctypes.c_uint32),
+                                                    _ptr(seeds, ctypes.c_uint32), _stream(stream)),
+               "s4_list_skip_index")
+        return bmax[: self.nb], seeds[: 4 * self.nb].reshape(-1, 4)
+
+    def decode_into(self, out, stream=None):
+        _check(require_library().s4_decode_dev(self.h, _dptr(out), out.numel(), _stream(stream)), "s4_decode_dev")
+
+    def decode(self, stream=None):
+        import torch
+        out = torch.empty(max(1, self.n), dtype=torch.int32, device="cuda")
+        self.decode_into(out, stream)
+        return out[: self.n]
+
+    def decode_blocks_into(self, first, count, out, stream=None):
+        _check(require_library().s4_decode_blocks_dev(self.h, first, count, _dptr(out), _stream(stream)),
+               "s4_decode_blocks_dev")
+
+
+def _device_u64():
+    import torch
+    return torch.zeros(1, dtype=torch.int64, device="cuda")
+
+
+def _scratch(nbytes):
+    import torch
+    return torch.empty(max(256, int(nbytes)), dtype=torch.uint8, device="cuda")
+
+
+def intersect(a: DeviceList, b: DeviceList, out=None, count=None, scratch=None, stream=None):
+    """Decode-fused pairwise intersection; returns (out tensor, device count)."""
+    import torch
+    lib = require_library()
+    m = min(a.n, b.n)
+    if out is None:
+        out = torch.empty(max(1, m), dtype=torch.int32, device="cuda")
+    if count is None:
+        count = _device_u64()
+    need = int(lib.s4_intersect_scratch_bytes(a.n, b.n))
+    if scratch is None:
+        scratch = _scratch(need)
+    _check(lib.s4_intersect(a.h, b.h, _dptr(out), out.numel(), _dptr(count), _dptr(scratch),
+                            scratch.numel(), _stream(stream)), "s4_intersect")
+    return out, count
+
+
+def _handles(lists):
+    arr = (ctypes.c_void_p * max(1, len(lists)))()
+    for i, l in enumerate(lists):
+        arr[i] = l.h.value if isinstance(l.h, ctypes.c_void_p) else l.h
+    return arr
+
+
+def intersect_k_scratch_bytes(lists) -> int:
+    return int(require_library().s4_intersect_k_scratch_bytes(_handles(lists), len(lists)))
+
+
+def intersect_k(lists, out=None, count=None, scratch=None, stream=None):
+    import torch
+    lib = require_library()
+    m = min(l.n for l in lists) if lists else 0
+    if out is None:
+        out = torch.empty(max(1, m), dtype=torch.int32, device="cuda")
+    if count is None:
+        count = _device_u64()
+    if scratch is None:
+        scratch = _scratch(intersect_k_scratch_bytes(lists))
+    _check(lib.s4_intersect_k(_handles(lists), len(lists), _dptr(out), out.numel(), _dptr(count),
+                              _dptr(scratch), scratch.numel(), _stream(stream)), "s4_intersect_k")
+    return out, count
+
+
+def intersect_raw(r, r_len, cap_r, f: DeviceList, out=None, count=None, scratch=None, stream=None):
+    import torch
+    lib = require_library()
+    if out is None:
+        out = torch.empty(max(1, min(cap_r, f.n)), dtype=torch.int32, device="cuda")
+    if count is None:
+        count = _device_u64()
+    if scratch is None:
+        scratch = _scratch(int(lib.s4_intersect_raw_scratch_bytes(cap_r)))
+    _check(lib.s4_intersect_raw(_dptr(r), _dptr(r_len), cap_r, f.h, _dptr(out), out.numel(), _dptr(count),
+                                _dptr(scratch), scratch.numel(), _stream(stream)), "s4_intersect_raw")
+    return out, count
+
+
+def get_tuning() -> Tuning:
+    t = Tuning()
+    _check(require_library().s4_get_tuning(ctypes.byref(t)), "s4_get_tuning")
+    return t
+
+
+def set_tuning(**kw):
+    t = get_tuning()
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    _check(require_library().s4_set_tuning(ctypes.byref(t)), "s4_set_tuning")
+    return t
+
+
+# ----------------------------------------------------------------- index
+
+class Index:
+    """Many device-resident lists in one arena (s4_index)."""
+
+    def __init__(self, streams, offsets, stream=None):
+        lib = require_library()
+        streams = np.ascontiguousarray(streams, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        self.h = ctypes.c_void_p()
+        _check(lib.s4_index_build(_ptr(streams if streams.size else np.zeros(1, np.uint8), ctypes.c_uint8),
+                                  _ptr(offsets, ctypes.c_uint64), offsets.size - 1, _stream(stream),
+                                  ctypes.byref(self.h)), "s4_index_build")
+        self.count = offsets.size - 1
+        self.lengths = np.zeros(max(1, self.count), np.uint64)
+        _check(lib.s4_index_lengths(self.h, _ptr(self.lengths, ctypes.c_uint64)), "s4_index_lengths")
+        self.lengths = self.lengths[: self.count]
+        c, ti, pb, ib = (ctypes.c_uint64() for _ in range(4))
+        _check(lib.s4_index_info(self.h, ctypes.byref(c), ctypes.byref(ti), ctypes.byref(pb), ctypes.byref(ib)),
+               "s4_index_info")
+        self.total_ints, self.payload_bytes, self.index_bytes = ti.value, pb.value, ib.value
+
+    def list(self, i) -> DeviceList:
+        h = ctypes.c_void_p()
+        _check(require_library().s4_index_list(self.h, i, ctypes.byref(h)), "s4_index_list")
+        return DeviceList(h, owner=self)
+
+    def free(self):
+        if self.h:
+            _check(require_library().s4_index_free(self.h), "s4_index_free")
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self.h:
+                require_library().s4_index_free(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+class Batch:
+    """A planned batch of conjunctive queries over an Index (s4_batch)."""
+
+    def __init__(self, index: Index, terms, q_offsets, stream=None):
+        import torch
+        lib = require_library()
+        terms = np.ascontiguousarray(terms, dtype=np.uint32)
+        q_offsets = np.ascontiguousarray(q_offsets, dtype=np.uint64)
+        self.index = index
+        self.nq = q_offsets.size - 1
+        self.h = ctypes.c_void_p()
+        _check(lib.s4_batch_plan(index.h, _ptr(terms if terms.size else np.zeros(1, np.uint32), ctypes.c_uint32),
+                                 _ptr(q_offsets, ctypes.c_uint64), self.nq, _stream(stream),
+                                 ctypes.byref(self.h)), "s4_batch_plan")
+        self.results_bound = int(lib.s4_batch_results_bound(self.h))
+        self.counts = torch.zeros(max(1, self.nq), dtype=torch.int64, device="cuda")
+        self.res_offsets = torch.zeros(self.nq + 1, dtype=torch.int64, device="cuda")
+        self.results = torch.zeros(max(1, self.results_bound), dtype=torch.int32, device="cuda")
+
+    def run(self, use_graph=False, stream=None):
+        _check(require_library().s4_batch_run(self.h, _dptr(self.counts), _dptr(self.res_offsets),
+                                              _dptr(self.results), self.results.numel(), int(bool(use_graph)),
+                                              _stream(stream)), "s4_batch_run")
+
+    def query_ticks(self, stream=None):
+        t = np.zeros(max(1, self.nq), np.uint64)
+        _check(require_library().s4_batch_query_ticks(self.h, _ptr(t, ctypes.c_uint64), _stream(stream)),
+               "s4_batch_query_ticks")
+        return t[: self.nq]
+
+    def autotune(self, reps=3, stream=None):
+        best = Tuning()
+        ms = ctypes.c_double(0)
+        _check(require_library().s4_batch_autotune(self.h, _dptr(self.counts), _dptr(self.res_offsets),
+                                                   _dptr(self.results), self.results.numel(), reps,
+                                                   _stream(stream), ctypes.byref(best), ctypes.byref(ms)),
+               "s4_batch_autotune")
+        return best.as_dict(), ms.value
+
+    def result(self, q):
+        """Host copy of query q's result (synchronises)."""
+        offs = self.res_offsets.cpu().numpy()
+        return self.results[int(offs[q]): int(offs[q + 1])].cpu().numpy().view(np.uint32)
+
+    def free(self):
+        if self.h:
+            _check(require_library().s4_batch_free(self.h), "s4_batch_free")
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            if self.h:
+                require_library().s4_batch_free(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------- server
+
+class Server:
+    """Continuous-batching query server (s4_server)."""
+
+    def __init__(self, index: Index, max_slots=4096, pool_bytes=1 << 30, result_bytes=1 << 28, max_terms=8):
+        cfg = ServerConfig(max_slots, pool_bytes, result_bytes, max_terms)
+        self.index = index
+        self.h = ctypes.c_void_p()
+        _check(require_library().s4_server_create(index.h, ctypes.byref(cfg), ctypes.byref(self.h)),
+               "s4_server_create")
+
+    def submit(self, terms):
+        terms = np.ascontiguousarray(terms, dtype=np.uint32)
+        qid = ctypes.c_uint64(0)
+        rc = require_library().s4_server_submit(self.h, _ptr(terms, ctypes.c_uint32), terms.size, ctypes.byref(qid))
+        if rc == EAGAIN:
+            return None
+        _check(rc, "s4_server_submit")
+        return qid.value
+
+    def poll(self, max_done=4096, results_cap=1 << 24):
+        ids = np.zeros(max_done, np.uint64)
+        counts = np.zeros(max_done, np.uint64)
+        lat = np.zeros(max_done, np.uint64)
+        res = np.zeros(results_cap, np.uint32)
+        roffs = np.zeros(max_done + 1, np.uint64)
+        done = ctypes.c_uint32(0)
+        _check(require_library().s4_server_poll(self.h, _ptr(ids, ctypes.c_uint64), _ptr(counts, ctypes.c_uint64),
+                                                _ptr(lat, ctypes.c_uint64), _ptr(res, ctypes.c_uint32), results_cap,
+                                                _ptr(roffs, ctypes.c_uint64), max_done, ctypes.byref(done)),
+               "s4_server_poll")
+        d = done.value
+        out = []
+        for i in range(d):
+            out.append((int(ids[i]), res[int(roffs[i]): int(roffs[i + 1])].copy(), int(lat[i])))
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(require_library().s4_server_stats_get(self.h, ctypes.byref(st)), "s4_server_stats_get")
+        return st.as_dict()
+
+    def close(self):
+        if self.h:
+            _check(require_library().s4_server_destroy(self.h), "s4_server_destroy")
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,668 @@
+// Kernels and C-ABI entry points for single lists: upload with skip-index
+// build, bulk decode (unpack + D4 prefix sum fused, Alg. 1), pairwise and
+// k-way (SvS) decode-fused intersection.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "s4_kernels.h"
+
+namespace s4 {
+
+// ------------------------------------------------------------ device state
+
+static std::mutex g_dev_mu;
+static int g_dev_checked = -1;  // device id verified, -1 none
+static int g_cus = 0;
+static s4_tuning g_tuning = {64u, 4u, 8u, 1u};
+
+int ensure_device() {
+  int dev = -1;
+  S4_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  if (g_dev_checked == dev) return S4_OK;
+  hipDeviceProp_t prop;
+  S4_HIP(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(S4_EDEVICE, std::string("libs4 is built for gfx950; device is ") + prop.gcnArchName);
+  g_cus = prop.multiProcessorCount;
+  g_dev_checked = dev;
+  return S4_OK;
+}
+
+int cu_count() { return g_cus > 0 ? g_cus : 256; }
+s4_tuning &tuning() { return g_tuning; }
+
+static inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ----------------------------------------------------------------- kernels
+
+// Per-lane sums of the D4 deltas of every block (one 16-lane row per
+// block), written into the seeds array as a first pass of the skip index.
+// Blocks are numbered globally over `nlists` lists; blk_prefix[l] is the
+// first global block of list l, pay_base[l] its first payload word.
+__global__ __launch_bounds__(256) void k_block_sums(const uint8_t *__restrict__ widths,
+                                                    const uint32_t *__restrict__ offs,
+                                                    const uint32_t *__restrict__ payload,
+                                                    const uint64_t *__restrict__ blk_prefix,
+                                                    const uint64_t *__restrict__ pay_base, uint32_t nlists,
+                                                    uint64_t total_blocks, uint4 *__restrict__ sums) {
+  const uint32_t lane = lane_id();
+  const uint64_t wave = uint64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint64_t g = wave * 4 + (lane >> 4);
+  const bool active = g < total_blocks;
+  uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
+  if (active) {
+    // list of block g: last l with blk_prefix[l] <= g
+    uint32_t lo = 0, hi = nlists;
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (blk_prefix[mid] <= g) lo = mid; else hi = mid;
+    }
+    extract_row(payload + pay_base[lo] + offs[g], widths[g], lane & 15u, d0, d1);
+  }
+  uint32_t t[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) t[j] = scan_row16(d0[j] + d1[j]);
+  if (active && (lane & 15u) == 15u) sums[g] = make_uint4(t[0], t[1], t[2], t[3]);
+}
+
+// Second pass: one wave per list turns per-block lane sums into seeds
+// (exclusive prefix over the list's blocks) and bmax (the block's last
+// value, lane 3 of the inclusive prefix).
+__global__ __launch_bounds__(256) void k_seed_scan(const uint64_t *__restrict__ blk_prefix, uint32_t nlists,
+                                                   uint4 *__restrict__ seeds, uint32_t *__restrict__ bmax) {
+  const uint32_t lane = lane_id();
+  const uint32_t list = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (list >= nlists) return;
+  const uint64_t b0 = blk_prefix[list], b1 = blk_prefix[list + 1];
+  uint32_t carry[4] = {0, 0, 0, 0};
+  for (uint64_t base = b0; base < b1; base += 64) {
+    const uint64_t g = base + lane;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (g < b1) v = seeds[g];
+    const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+    uint32_t inc[4], exc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      inc[j] = scan_wave64(vv[j]);
+      exc[j] = carry[j] + inc[j] - vv[j];
+    }
+    if (g < b1) {
+      seeds[g] = make_uint4(exc[0], exc[1], exc[2], exc[3]);
+      bmax[g] = carry[3] + inc[3];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) carry[j] += uint32_t(__builtin_amdgcn_readlane(int(inc[j]), 63));
+  }
+}
+
+// Bulk decode of blocks [first, first + count) of L (index nb = raw tail).
+// Each wave decodes 4 consecutive blocks per pass (one 16-lane row each)
+// for `passes` passes; the D4 prefix runs across the whole wave (row scans
+// joined by row broadcasts), so only the wave's first block reads a seed
+// from the skip index and later blocks carry it in registers.
+__global__ __launch_bounds__(256) void k_decode(DList L, uint32_t first, uint32_t count, uint32_t passes,
+                                                uint32_t block_waves, uint32_t *__restrict__ out) {
+  const uint32_t lane = lane_id();
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const uint32_t end = first + count;
+  const uint32_t full_end = min(end, L.nb);
+  if (wave >= block_waves) {
+    // the raw tail, when the range covers it
+    if (wave == block_waves && end > L.nb && L.t > 0) {
+      uint32_t *dst = out + uint64_t(L.nb - first) * kBlock;
+      if (lane < L.t) dst[lane] = L.tail[lane];
+      if (lane + 64 < L.t) dst[lane + 64] = L.tail[lane + 64];
+    }
+    return;
+  }
+  const uint32_t row = lane >> 4, i = lane & 15u;
+  const uint32_t kbase = first + wave * 4u * passes;
+  const uint4 s = L.seeds[kbase];
+  uint32_t c[4] = {s.x, s.y, s.z, s.w};
+  for (uint32_t p = 0; p < passes; ++p) {
+    const uint32_t k0 = kbase + 4u * p;
+    if (k0 >= full_end) break;
+    const uint32_t k = k0 + row;
+    const bool valid = k < full_end;
+    uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
+    if (valid) extract_row(L.payload + L.offs[k], L.widths[k], i, d0, d1);
+    uint32_t x0[4], x1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t sc = scan_wave64(d0[j] + d1[j]);
+      x1[j] = c[j] + sc;
+      x0[j] = x1[j] - d1[j];
+    }
+    if (valid) {
+      uint4 *dst = reinterpret_cast<uint4 *>(out + uint64_t(k - first) * kBlock + 8u * i);
+      dst[0] = make_uint4(x0[0], x0[1], x0[2], x0[3]);
+      dst[1] = make_uint4(x1[0], x1[1], x1[2], x1[3]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = uint32_t(__builtin_amdgcn_readlane(int(x1[j]), 63));
+  }
+}
+
+// One wave per chunk of r: decode-fused pairwise intersection.  Writes the
+// chunk's matches to stage[128 item ..] and their number to counts[item];
+// chunks past the end of r (its length may live on the device) get 0.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_pair(DList rl, const uint32_t *__restrict__ r_raw,
+                                                     const uint64_t *__restrict__ r_len_dev, DList f,
+                                                     uint32_t items_cap, uint32_t *__restrict__ stage,
+                                                     uint32_t *__restrict__ counts, uint32_t gallop_blocks) {
+  __shared__ ItemLds lds[WAVES];
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t item = blockIdx.x * WAVES + w;
+  if (item >= items_cap) return;
+  RSide r;
+  r.L = rl;
+  r.raw = r_raw;
+  r.len = r_raw ? *r_len_dev : rl.n;
+  const uint64_t n_items = (r.len + kBlock - 1) / kBlock;
+  if (item >= n_items) {
+    if (lane_id() == 0) counts[item] = 0;
+    return;
+  }
+  pair_item(r, f, item, lds[w], stage + uint64_t(item) * kBlock, counts + item, gallop_blocks);
+}
+
+// Exclusive scan of counts[n] in tiles of 1024 (256 threads x 4): local
+// offsets to excl[], tile totals to tile_sums[].
+__global__ __launch_bounds__(256) void k_scan_tiles(const uint32_t *__restrict__ counts, uint32_t n,
+                                                    uint32_t *__restrict__ excl, uint32_t *__restrict__ tile_sums) {
+  __shared__ uint32_t wsum[4];
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  const uint64_t base = uint64_t(blockIdx.x) * 1024 + threadIdx.x * 4u;
+  uint32_t v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) v[e] = (base + e < n) ? counts[base + e] : 0u;
+  const uint32_t local = v[0] + v[1] + v[2] + v[3];
+  const uint32_t inc = scan_wave64(local);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t off = 0;
+  for (uint32_t q = 0; q < w; ++q) off += wsum[q];
+  uint32_t run = off + inc - local;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (base + e < n) excl[base + e] = run;
+    run += v[e];
+  }
+  if (threadIdx.x == 255) tile_sums[blockIdx.x] = off + inc;
+}
+
+// Exclusive scan of the tile totals in place (one workgroup); the grand
+// total goes to *total.
+__global__ __launch_bounds__(256) void k_scan_top(uint32_t *__restrict__ tile_sums, uint32_t ntiles,
+                                                  uint64_t *__restrict__ total) {
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t carry_s;
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < ntiles; base += 256) {
+    const uint32_t idx = base + threadIdx.x;
+    const uint32_t v = idx < ntiles ? tile_sums[idx] : 0u;
+    const uint32_t inc = scan_wave64(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t off = carry_s;
+    for (uint32_t q = 0; q < w; ++q) off += wsum[q];
+    if (idx < ntiles) tile_sums[idx] = off + inc - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry_s = off + inc;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry_s;
+}
+
+// Ordered gather of every chunk's matches into out[] (one wave per chunk).
+__global__ __launch_bounds__(256) void k_compact(const uint32_t *__restrict__ stage,
+                                                 const uint32_t *__restrict__ counts,
+                                                 const uint32_t *__restrict__ excl,
+                                                 const uint32_t *__restrict__ tile_sums, uint32_t n,
+                                                 uint32_t *__restrict__ out) {
+  const uint32_t lane = lane_id();
+  const uint32_t item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (item >= n) return;
+  const uint32_t cnt = counts[item];
+  const uint64_t off = uint64_t(excl[item]) + tile_sums[item >> 10];
+  const uint32_t *src = stage + uint64_t(item) * kBlock;
+  if (lane < cnt) out[off + lane] = src[lane];
+  if (lane + 64 < cnt) out[off + 64 + lane] = src[lane + 64];
+}
+
+__global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
+__global__ void k_copy_u64(uint64_t *dst, const uint64_t *src) { *dst = *src; }
+
+// ------------------------------------------------------------ arena build
+
+// Parsed streams to be placed in one device arena.
+struct Upload {
+  std::vector<StreamView> views;
+  std::vector<uint64_t> blk_prefix, pay_base, tail_base;
+  uint64_t total_blocks = 0, total_words = 0, total_tail = 0;
+  ArenaLayout lay;
+};
+
+static void plan_arena(Upload &u) {
+  const size_t L = u.views.size();
+  u.blk_prefix.assign(L + 1, 0);
+  u.pay_base.assign(L, 0);
+  u.tail_base.assign(L, 0);
+  for (size_t i = 0; i < L; ++i) {
+    u.blk_prefix[i + 1] = u.blk_prefix[i] + u.views[i].nb;
+    u.pay_base[i] = u.total_words;
+    u.total_words += u.views[i].pw;
+    u.tail_base[i] = u.total_tail;
+    u.total_tail += u.views[i].t;
+  }
+  u.total_blocks = u.blk_prefix[L];
+  ArenaLayout &a = u.lay;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  a.desc_off = take(sizeof(DList) * L);
+  a.blkpre_off = take(sizeof(uint64_t) * (L + 1) + sizeof(uint64_t) * L);
+  a.widths_off = take(u.total_blocks);
+  a.offs_off = take(4 * u.total_blocks);
+  a.bmax_off = take(4 * u.total_blocks);
+  a.seeds_off = take(16 * u.total_blocks);
+  a.tail_off = take(4 * u.total_tail);
+  a.payload_off = take(4 * u.total_words + kPayloadPadBytes);
+  a.total = off;
+}
+
+static DList make_desc(const Upload &u, size_t i, char *base) {
+  const ArenaLayout &a = u.lay;
+  DList d;
+  const uint64_t b0 = u.blk_prefix[i];
+  d.widths = reinterpret_cast<const uint8_t *>(base + a.widths_off) + b0;
+  d.offs = reinterpret_cast<const uint32_t *>(base + a.offs_off) + b0;
+  d.bmax = reinterpret_cast<const uint32_t *>(base + a.bmax_off) + b0;
+  d.seeds = reinterpret_cast<const uint4 *>(base + a.seeds_off) + b0;
+  d.payload = reinterpret_cast<const uint32_t *>(base + a.payload_off) + u.pay_base[i];
+  d.tail = reinterpret_cast<const uint32_t *>(base + a.tail_off) + u.tail_base[i];
+  d.n = u.views[i].n;
+  d.nb = u.views[i].nb;
+  d.t = u.views[i].t;
+  return d;
+}
+
+// Copy the parsed streams into a new device arena and build the skip
+// index.  Synchronous with respect to `stream` only through the staging copy.
+static int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DList> *descs) {
+  int rc = ensure_device();
+  if (rc) return rc;
+  plan_arena(u);
+  const ArenaLayout &a = u.lay;
+  const size_t L = u.views.size();
+  char *dev = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(&dev), a.total);
+  if (e != hipSuccess) return fail(S4_ENOMEM, "hipMalloc of " + std::to_string(a.total) + " bytes failed");
+  // host image of everything except bmax / seeds
+  std::vector<char> img;
+  try {
+    img.assign(a.total, 0);
+  } catch (...) {
+    (void)hipFree(dev);
+    return fail(S4_ENOMEM, "host staging allocation failed");
+  }
+  descs->resize(L);
+  for (size_t i = 0; i < L; ++i) (*descs)[i] = make_desc(u, i, dev);
+  std::memcpy(img.data() + a.desc_off, descs->data(), sizeof(DList) * L);
+  std::memcpy(img.data() + a.blkpre_off, u.blk_prefix.data(), sizeof(uint64_t) * (L + 1));
+  std::memcpy(img.data() + a.blkpre_off + sizeof(uint64_t) * (L + 1), u.pay_base.data(), sizeof(uint64_t) * L);
+  for (size_t i = 0; i < L; ++i) {
+    const StreamView &v = u.views[i];
+    const uint64_t b0 = u.blk_prefix[i];
+    std::memcpy(img.data() + a.widths_off + b0, v.widths, v.nb);
+    uint32_t *offs = reinterpret_cast<uint32_t *>(img.data() + a.offs_off) + b0;
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < v.nb; ++k) {
+      offs[k] = run;
+      run += 4u * v.widths[k];
+    }
+    std::memcpy(img.data() + a.payload_off + 4 * u.pay_base[i], v.payload, 4 * v.pw);
+    std::memcpy(img.data() + a.tail_off + 4 * u.tail_base[i], v.tail, 4 * size_t(v.t));
+  }
+  e = hipMemcpyAsync(dev, img.data(), a.total, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    return hip_fail(e, "arena upload");
+  }
+  if (u.total_blocks) {
+    const uint64_t waves = (u.total_blocks + 3) / 4;
+    const uint64_t groups = (waves + 3) / 4;
+    hipLaunchKernelGGL(k_block_sums, dim3(uint32_t(groups)), dim3(256), 0, stream,
+                       reinterpret_cast<const uint8_t *>(dev + a.widths_off),
+                       reinterpret_cast<const uint32_t *>(dev + a.offs_off),
+                       reinterpret_cast<const uint32_t *>(dev + a.payload_off),
+                       reinterpret_cast<const uint64_t *>(dev + a.blkpre_off),
+                       reinterpret_cast<const uint64_t *>(dev + a.blkpre_off + sizeof(uint64_t) * (L + 1)),
+                       uint32_t(L), u.total_blocks, reinterpret_cast<uint4 *>(dev + a.seeds_off));
+    hipLaunchKernelGGL(k_seed_scan, dim3(uint32_t((L + 3) / 4)), dim3(256), 0, stream,
+                       reinterpret_cast<const uint64_t *>(dev + a.blkpre_off), uint32_t(L),
+                       reinterpret_cast<uint4 *>(dev + a.seeds_off), reinterpret_cast<uint32_t *>(dev + a.bmax_off));
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+      (void)hipFree(dev);
+      return hip_fail(e, "skip index build");
+    }
+  }
+  *arena_out = dev;
+  return S4_OK;
+}
+
+// ---------------------------------------------------------- pair pipeline
+
+// Scratch of one pairwise step whose short side has at most cap_r values.
+struct PairScratch {
+  uint32_t *stage, *counts, *excl, *tiles;
+  uint32_t items_cap, ntiles;
+};
+
+static size_t pair_scratch_layout(uint64_t cap_r, char *base, PairScratch *ps) {
+  const uint64_t items = (cap_r + kBlock - 1) / kBlock;
+  const uint64_t ntiles = (items + 1023) / 1024;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  size_t st = take(4 * kBlock * items), co = take(4 * items), ex = take(4 * items), ti = take(4 * ntiles + 4);
+  if (ps) {
+    ps->stage = reinterpret_cast<uint32_t *>(base + st);
+    ps->counts = reinterpret_cast<uint32_t *>(base + co);
+    ps->excl = reinterpret_cast<uint32_t *>(base + ex);
+    ps->tiles = reinterpret_cast<uint32_t *>(base + ti);
+    ps->items_cap = uint32_t(items);
+    ps->ntiles = uint32_t(ntiles);
+  }
+  return off;
+}
+
+template <int WAVES>
+static void launch_pair_w(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const DList &f,
+                          const PairScratch &ps, hipStream_t stream) {
+  const uint32_t groups = std::max<uint32_t>(1, (ps.items_cap + WAVES - 1) / WAVES);
+  hipLaunchKernelGGL(k_pair<WAVES>, dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len, f, ps.items_cap,
+                     ps.stage, ps.counts, std::min(tuning().gallop_blocks, kMaxGallopBlocks));
+}
+
+// match -> tile scan -> top scan -> ordered compaction; count to d_count.
+static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const DList &f,
+                    const PairScratch &ps, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
+  if (ps.items_cap == 0) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, stream, d_count, uint64_t(0));
+    S4_HIP(hipGetLastError());
+    return S4_OK;
+  }
+  switch (tuning().waves_per_group) {
+    case 1: launch_pair_w<1>(r, r_raw, r_len, f, ps, stream); break;
+    case 2: launch_pair_w<2>(r, r_raw, r_len, f, ps, stream); break;
+    case 8: launch_pair_w<8>(r, r_raw, r_len, f, ps, stream); break;
+    default: launch_pair_w<4>(r, r_raw, r_len, f, ps, stream); break;
+  }
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ps.ntiles), dim3(256), 0, stream, ps.counts, ps.items_cap, ps.excl, ps.tiles);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, stream, ps.tiles, ps.ntiles, d_count);
+  hipLaunchKernelGGL(k_compact, dim3((ps.items_cap + 3) / 4), dim3(256), 0, stream, ps.stage, ps.counts, ps.excl,
+                     ps.tiles, ps.items_cap, d_out);
+  S4_HIP(hipGetLastError());
+  return S4_OK;
+}
+
+int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream) {
+  const uint32_t end = first + count;
+  const uint32_t full = end > L.nb ? (L.nb > first ? L.nb - first : 0) : count;
+  // passes per wave: keep at least ~4 waves per CU in flight
+  const uint32_t target_waves = uint32_t(cu_count()) * 4u;
+  uint32_t passes = 8;
+  while (passes > 1 && (full + 4 * passes - 1) / (4 * passes) < target_waves) passes >>= 1;
+  const uint32_t block_waves = (full + 4 * passes - 1) / (4 * passes);
+  const bool tail = end > L.nb && L.t > 0;
+  const uint32_t waves = block_waves + (tail ? 1 : 0);
+  if (waves == 0) return S4_OK;
+  hipLaunchKernelGGL(k_decode, dim3((waves + 3) / 4), dim3(256), 0, stream, L, first, count, passes, block_waves,
+                     d_out);
+  S4_HIP(hipGetLastError());
+  return S4_OK;
+}
+
+}  // namespace s4
+
+using namespace s4;
+
+static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" {
+
+int s4_get_tuning(s4_tuning *t) {
+  if (!t) return fail(S4_EINVAL, "null tuning");
+  *t = tuning();
+  return S4_OK;
+}
+
+int s4_set_tuning(const s4_tuning *t) {
+  if (!t) return fail(S4_EINVAL, "null tuning");
+  if (t->gallop_blocks < 1 || t->gallop_blocks > kMaxGallopBlocks)
+    return fail(S4_EINVAL, "gallop_blocks must be in [1, 512]");
+  if (t->waves_per_group != 1 && t->waves_per_group != 2 && t->waves_per_group != 4 && t->waves_per_group != 8)
+    return fail(S4_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+  if (t->groups_per_cu < 1 || t->groups_per_cu > 32) return fail(S4_EINVAL, "groups_per_cu must be in [1, 32]");
+  if (t->items_per_grab < 1 || t->items_per_grab > 64) return fail(S4_EINVAL, "items_per_grab must be in [1, 64]");
+  tuning() = *t;
+  return S4_OK;
+}
+
+int s4_list_upload(const uint8_t *enc, size_t bytes, void *stream, s4_list **out) {
+  if (!out) return fail(S4_EINVAL, "null out");
+  Upload u;
+  u.views.resize(1);
+  int rc = parse_stream(enc, bytes, &u.views[0]);
+  if (rc) return rc;
+  s4_list *l = new (std::nothrow) s4_list;
+  if (!l) return fail(S4_ENOMEM, "handle allocation failed");
+  std::vector<DList> descs;
+  rc = build_arena(u, as_stream(stream), &l->arena, &descs);
+  if (rc) {
+    delete l;
+    return rc;
+  }
+  const StreamView &v = u.views[0];
+  l->d = descs[0];
+  l->n = v.n;
+  l->nb = v.nb;
+  l->t = v.t;
+  l->pw = v.pw;
+  l->flags = v.flags;
+  l->payload_bytes = uint64_t(v.nb) + 4 * v.pw + 4ull * v.t;
+  l->index_bytes = uint64_t(v.nb) * (4 + 4 + 16);
+  *out = l;
+  return S4_OK;
+}
+
+int s4_list_free(s4_list *list) {
+  if (!list) return S4_OK;
+  if (list->arena) {
+    hipError_t e = hipFree(list->arena);
+    delete list;
+    if (e != hipSuccess) return hip_fail(e, "hipFree");
+    return S4_OK;
+  }
+  delete list;
+  return S4_OK;
+}
+
+int s4_list_info(const s4_list *l, uint64_t *n, uint32_t *nb, uint32_t *flags, uint64_t *payload_bytes,
+                 uint64_t *index_bytes) {
+  if (!l) return fail(S4_EINVAL, "null list");
+  if (n) *n = l->n;
+  if (nb) *nb = l->nb;
+  if (flags) *flags = l->flags;
+  if (payload_bytes) *payload_bytes = l->payload_bytes;
+  if (index_bytes) *index_bytes = l->index_bytes;
+  return S4_OK;
+}
+
+int s4_list_skip_index(const s4_list *l, uint32_t *bmax, uint32_t *seeds, void *stream) {
+  if (!l || (l->nb && (!bmax || !seeds))) return fail(S4_EINVAL, "null argument");
+  if (!l->nb) return S4_OK;
+  S4_HIP(hipMemcpyAsync(bmax, l->d.bmax, 4ull * l->nb, hipMemcpyDeviceToHost, as_stream(stream)));
+  S4_HIP(hipMemcpyAsync(seeds, l->d.seeds, 16ull * l->nb, hipMemcpyDeviceToHost, as_stream(stream)));
+  S4_HIP(hipStreamSynchronize(as_stream(stream)));
+  return S4_OK;
+}
+
+int s4_decode_dev(const s4_list *l, uint32_t *d_out, uint64_t cap, void *stream) {
+  if (!l || (!d_out && l->n)) return fail(S4_EINVAL, "null argument");
+  if (cap < l->n) return fail(S4_ERANGE, "s4_decode_dev: cap < n");
+  if (reinterpret_cast<uintptr_t>(d_out) & 15u) return fail(S4_EINVAL, "d_out must be 16-byte aligned");
+  if (!l->n) return S4_OK;
+  return decode_range(l->d, 0, l->nb + (l->t ? 1 : 0), d_out, as_stream(stream));
+}
+
+int s4_decode_blocks_dev(const s4_list *l, uint32_t first, uint32_t count, uint32_t *d_out, void *stream) {
+  if (!l || (!d_out && count)) return fail(S4_EINVAL, "null argument");
+  const uint32_t pseudo = l->nb + (l->t ? 1 : 0);
+  if (uint64_t(first) + count > pseudo) return fail(S4_ERANGE, "block range beyond the list");
+  if (reinterpret_cast<uintptr_t>(d_out) & 15u) return fail(S4_EINVAL, "d_out must be 16-byte aligned");
+  if (!count) return S4_OK;
+  return decode_range(l->d, first, count, d_out, as_stream(stream));
+}
+
+size_t s4_intersect_scratch_bytes(uint64_t len_a, uint64_t len_b) {
+  return pair_scratch_layout(std::min(len_a, len_b), nullptr, nullptr);
+}
+
+int s4_intersect(const s4_list *a, const s4_list *b, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
+                 void *d_scratch, size_t scratch_bytes, void *stream) {
+  if (!a || !b || !d_count) return fail(S4_EINVAL, "null argument");
+  if (!(a->flags & 1u) || !(b->flags & 1u)) return fail(S4_EUNSORTED, "intersection inputs must be strictly increasing");
+  const s4_list *r = a->n <= b->n ? a : b;
+  const s4_list *f = a->n <= b->n ? b : a;
+  if (cap < r->n) return fail(S4_ERANGE, "cap < min(len a, len b)");
+  const size_t need = pair_scratch_layout(r->n, nullptr, nullptr);
+  if (scratch_bytes < need || (!d_scratch && need)) return fail(S4_ERANGE, "scratch too small");
+  if (r->n && !d_out) return fail(S4_EINVAL, "null d_out");
+  int rc = ensure_device();
+  if (rc) return rc;
+  PairScratch ps;
+  pair_scratch_layout(r->n, static_cast<char *>(d_scratch), &ps);
+  return run_pair(r->d, nullptr, nullptr, f->d, ps, d_out, d_count, as_stream(stream));
+}
+
+size_t s4_intersect_raw_scratch_bytes(uint64_t cap_r) { return pair_scratch_layout(cap_r, nullptr, nullptr); }
+
+int s4_intersect_raw(const uint32_t *d_r, const uint64_t *d_len_r, uint64_t cap_r, const s4_list *f,
+                     uint32_t *d_out, uint64_t cap, uint64_t *d_count, void *d_scratch, size_t scratch_bytes,
+                     void *stream) {
+  if (!f || !d_len_r || !d_count || (cap_r && !d_r)) return fail(S4_EINVAL, "null argument");
+  if (!(f->flags & 1u)) return fail(S4_EUNSORTED, "intersection inputs must be strictly increasing");
+  if (cap < std::min(cap_r, f->n)) return fail(S4_ERANGE, "cap too small");
+  const uint64_t cr = cap_r;
+  const size_t need = pair_scratch_layout(cr, nullptr, nullptr);
+  if (scratch_bytes < need || (!d_scratch && need)) return fail(S4_ERANGE, "scratch too small");
+  int rc = ensure_device();
+  if (rc) return rc;
+  PairScratch ps;
+  pair_scratch_layout(cr, static_cast<char *>(d_scratch), &ps);
+  DList none{};
+  return run_pair(none, d_r, d_len_r, f->d, ps, d_out, d_count, as_stream(stream));
+}
+
+// SvS chain scratch: two intermediates of len_min values, two device
+// counters, and the pair scratch for len_min.
+static size_t chain_layout(uint64_t len_min, char *base, uint32_t **ping, uint32_t **pong, uint64_t **cnt,
+                           char **pair_base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return o;
+  };
+  size_t p0 = take(4 * len_min), p1 = take(4 * len_min), c = take(16), pb = off;
+  off += pair_scratch_layout(len_min, nullptr, nullptr);
+  if (base) {
+    *ping = reinterpret_cast<uint32_t *>(base + p0);
+    *pong = reinterpret_cast<uint32_t *>(base + p1);
+    *cnt = reinterpret_cast<uint64_t *>(base + c);
+    *pair_base = base + pb;
+  }
+  return off;
+}
+
+size_t s4_intersect_k_scratch_bytes(const s4_list *const *lists, uint32_t k) {
+  if (!lists || k == 0) return 0;
+  uint64_t m = UINT64_MAX;
+  for (uint32_t i = 0; i < k; ++i)
+    if (lists[i]) m = std::min(m, lists[i]->n);
+  if (m == UINT64_MAX) return 0;
+  return chain_layout(m, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
+                   void *d_scratch, size_t scratch_bytes, void *stream) {
+  if (!lists || k == 0 || !d_count) return fail(S4_EINVAL, "s4_intersect_k: need k >= 1 lists and d_count");
+  std::vector<const s4_list *> ord(lists, lists + k);
+  for (auto *l : ord)
+    if (!l) return fail(S4_EINVAL, "null list");
+  // SvS: shortest first (stable, so equal lengths keep their given order)
+  std::stable_sort(ord.begin(), ord.end(), [](const s4_list *x, const s4_list *y) { return x->n < y->n; });
+  const uint64_t m = ord[0]->n;
+  if (cap < m) return fail(S4_ERANGE, "cap < length of the shortest list");
+  if (m && !d_out) return fail(S4_EINVAL, "null d_out");
+  hipStream_t st = as_stream(stream);
+  int rc = ensure_device();
+  if (rc) return rc;
+  if (k == 1) {
+    if (reinterpret_cast<uintptr_t>(d_out) & 15u) return fail(S4_EINVAL, "d_out must be 16-byte aligned");
+    if (m) {
+      rc = decode_range(ord[0]->d, 0, ord[0]->nb + (ord[0]->t ? 1 : 0), d_out, st);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, d_count, m);
+    S4_HIP(hipGetLastError());
+    return S4_OK;
+  }
+  for (auto *l : ord)
+    if (!(l->flags & 1u)) return fail(S4_EUNSORTED, "intersection inputs must be strictly increasing");
+  const size_t need = chain_layout(m, nullptr, nullptr, nullptr, nullptr, nullptr);
+  if (scratch_bytes < need || !d_scratch) return fail(S4_ERANGE, "scratch too small");
+  uint32_t *ping, *pong;
+  uint64_t *cnt;
+  char *pair_base;
+  chain_layout(m, static_cast<char *>(d_scratch), &ping, &pong, &cnt, &pair_base);
+  PairScratch ps;
+  pair_scratch_layout(m, pair_base, &ps);
+  // level 0: both compressed
+  uint32_t *dst = (k == 2) ? d_out : ping;
+  uint64_t *dcnt = (k == 2) ? d_count : cnt;
+  rc = run_pair(ord[0]->d, nullptr, nullptr, ord[1]->d, ps, dst, dcnt, st);
+  if (rc) return rc;
+  uint32_t *cur = ping, *nxt = pong;
+  uint64_t *cur_cnt = cnt, *nxt_cnt = cnt + 1;
+  for (uint32_t i = 2; i < k; ++i) {
+    const bool last = (i == k - 1);
+    uint32_t *o = last ? d_out : nxt;
+    uint64_t *oc = last ? d_count : nxt_cnt;
+    DList none{};
+    rc = run_pair(none, cur, cur_cnt, ord[i]->d, ps, o, oc, st);
+    if (rc) return rc;
+    std::swap(cur, nxt);
+    std::swap(cur_cnt, nxt_cnt);
+  }
+  return S4_OK;
+}
+
+}  // extern "C"

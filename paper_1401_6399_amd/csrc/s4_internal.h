@@ -1,0 +1,87 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/s4.h"
+
+namespace s4 {
+
+constexpr uint32_t kMagic = 0x34443453u;  // "S4D4"
+constexpr uint32_t kVersion = 1;
+constexpr uint32_t kHeaderBytes = 32;
+constexpr uint32_t kBlock = 128;          // integers per block (Sec. 4.3)
+constexpr uint32_t kPayloadPadBytes = 64; // lets extraction read 3 rows past any block
+constexpr uint32_t kMaxGallopBlocks = 512;
+
+// Device view of one list: structure of arrays in HBM.
+struct DList {
+  const uint8_t *widths;    // [nb]
+  const uint32_t *offs;     // [nb]  word offset of block k in payload (multiple of 4)
+  const uint32_t *payload;  // [pw] + padding, 16-byte aligned
+  const uint32_t *bmax;     // [nb]  x[128k + 127]
+  const uint4 *seeds;       // [nb]  x[128k-4 .. 128k-1]
+  const uint32_t *tail;     // [t]
+  uint64_t n;
+  uint32_t nb;
+  uint32_t t;
+};
+
+// Parsed header of a serialized stream (host).
+struct StreamView {
+  uint64_t n = 0, pw = 0;
+  uint32_t nb = 0, t = 0;
+  uint16_t flags = 0;
+  const uint8_t *widths = nullptr;
+  const uint8_t *payload = nullptr;  // byte pointer (4-byte aligned within the stream)
+  const uint8_t *tail = nullptr;
+};
+
+// error reporting
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+#define S4_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return ::s4::hip_fail(e_, #call); \
+  } while (0)
+
+// format (s4_format.cpp)
+int parse_stream(const uint8_t *enc, size_t bytes, StreamView *v);
+size_t stream_bound(uint64_t n);
+int encode_one(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes);
+
+// device (s4_device.hip)
+int ensure_device();
+int cu_count();
+s4_tuning &tuning();
+
+// Host-side layout of a device arena holding `count` lists.
+struct ArenaLayout {
+  size_t widths_off = 0, offs_off = 0, bmax_off = 0, seeds_off = 0, payload_off = 0, tail_off = 0,
+         desc_off = 0, blkpre_off = 0, total = 0;
+};
+
+}  // namespace s4
+
+struct s4_list {
+  s4::DList d{};
+  uint64_t n = 0, pw = 0;
+  uint32_t nb = 0, t = 0, flags = 0;
+  void *arena = nullptr;  // owned device memory (null for index views)
+  uint64_t payload_bytes = 0, index_bytes = 0;
+};
+
+struct s4_index {
+  void *arena = nullptr;
+  uint64_t count = 0, total_ints = 0, payload_bytes = 0, index_bytes = 0;
+  std::vector<s4::DList> lists;    // host copy of the descriptors
+  std::vector<uint64_t> lengths;
+  std::vector<uint32_t> flags;
+  const s4::DList *d_lists = nullptr;  // device copy
+};

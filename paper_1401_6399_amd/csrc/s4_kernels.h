@@ -1,0 +1,284 @@
+// Device building blocks for gfx950 (64-lane wavefronts).
+//
+// Notation follows the paper: a block holds 128 integers; integer 4q + j of
+// a block is the q-th value of lane j (Sec. 4.2, Fig. 2); b is the block's
+// bit width (Sec. 4.3); D4 deltas are x_i - x_{i-4} (Sec. 5).  r is the
+// shorter list of a pair and f the longer one (Sec. 6).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "s4_internal.h"
+
+namespace s4 {
+
+constexpr uint32_t kInvalid = 0xFFFFFFFFu;
+
+// ----------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Number of set bits of `mask` in lanes below this one.
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// LDS written by some lanes of a wave and read by others: DS instructions of
+// one wave execute in order, so only the compiler must be kept from moving
+// accesses across this point.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// DPP move with zero fill: lanes whose source is outside the row (or in a
+// row disabled by ROW_MASK) receive 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp0(uint32_t v) {
+  return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+// Inclusive scans.  DPP row_shr:n = 0x110 + n, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143.
+__device__ __forceinline__ uint32_t scan_row16(uint32_t v) {
+  v += dpp0<0x111>(v);
+  v += dpp0<0x112>(v);
+  v += dpp0<0x114>(v);
+  v += dpp0<0x118>(v);
+  return v;
+}
+__device__ __forceinline__ uint32_t scan_half32(uint32_t v) {
+  v = scan_row16(v);
+  v += dpp0<0x142, 0xa>(v);  // row 1 += lane 15, row 3 += lane 47
+  return v;
+}
+__device__ __forceinline__ uint32_t scan_wave64(uint32_t v) {
+  v = scan_half32(v);
+  v += dpp0<0x143, 0xc>(v);  // rows 2, 3 += lane 31
+  return v;
+}
+
+// ------------------------------------------------------------ extraction
+
+__device__ __forceinline__ uint32_t width_mask(uint32_t b) { return b >= 32u ? 0xFFFFFFFFu : ((1u << b) - 1u); }
+
+// Low 32 bits of (hi:lo) >> s, s in [0, 31] (v_alignbit_b32).
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s) {
+  return __builtin_amdgcn_alignbit(hi, lo, s);
+}
+
+// Row layout (16 lanes per block): lane i of the row extracts the D4 deltas
+// of positions q = 2i and 2i + 1 for all four lanes j, i.e. block integers
+// 8i .. 8i + 7.  Word rows m = floor(q b / 32) .. m + 2 are read as 16-byte
+// vectors (word 4m + j of lane j sits in component j).
+__device__ __forceinline__ void extract_row(const uint32_t *__restrict__ blk, uint32_t b, uint32_t i,
+                                            uint32_t d0[4], uint32_t d1[4]) {
+  const uint32_t bit0 = 2u * i * b;
+  const uint32_t m0 = bit0 >> 5, s0 = bit0 & 31u;
+  const uint32_t bit1 = bit0 + b;
+  const uint32_t s1 = bit1 & 31u;
+  const bool step = (bit1 >> 5) != m0;
+  const uint4 *p = reinterpret_cast<const uint4 *>(blk) + m0;
+  const uint4 r0 = p[0], r1 = p[1], r2 = p[2];
+  const uint32_t mask = width_mask(b);
+  d0[0] = funnel(r1.x, r0.x, s0) & mask;
+  d0[1] = funnel(r1.y, r0.y, s0) & mask;
+  d0[2] = funnel(r1.z, r0.z, s0) & mask;
+  d0[3] = funnel(r1.w, r0.w, s0) & mask;
+  const uint4 lo = step ? r1 : r0;
+  const uint4 hi = step ? r2 : r1;
+  d1[0] = funnel(hi.x, lo.x, s1) & mask;
+  d1[1] = funnel(hi.y, lo.y, s1) & mask;
+  d1[2] = funnel(hi.z, lo.z, s1) & mask;
+  d1[3] = funnel(hi.w, lo.w, s1) & mask;
+}
+
+// Decode block k of L with one 16-lane row per block: extract, scan each
+// lane j over q within the row (integrated D4 prefix sum, Alg. 1 with
+// P(t, v) = t + v), add the block's seed from the skip index.  Rows whose
+// `active` is false compute zeros.  All 64 lanes must call this together.
+__device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool active, uint32_t i,
+                                           uint32_t x0[4], uint32_t x1[4]) {
+  uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
+  uint4 seed = make_uint4(0, 0, 0, 0);
+  if (active) {
+    extract_row(L.payload + L.offs[k], L.widths[k], i, d0, d1);
+    seed = L.seeds[k];
+  }
+  const uint32_t sv[4] = {seed.x, seed.y, seed.z, seed.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t s = scan_row16(d0[j] + d1[j]);
+    x1[j] = sv[j] + s;
+    x0[j] = x1[j] - d1[j];
+  }
+}
+
+// Decode block k of L with the whole wave (half-wave layout): lane l takes
+// q = l mod 32 and lanes j0 = 2 (l div 32), j0 + 1; the two half-waves scan
+// over q.  Writes the 128 values to dst[0..127].
+__device__ __forceinline__ void decode_block_wave(const DList &L, uint32_t k, uint32_t *dst) {
+  const uint32_t l = lane_id();
+  const uint32_t q = l & 31u, j0 = (l >> 5) * 2u;
+  const uint32_t b = L.widths[k];
+  const uint32_t *w = L.payload + L.offs[k];
+  const uint32_t bit = q * b, m = bit >> 5, s = bit & 31u;
+  const uint2 lo = *reinterpret_cast<const uint2 *>(w + 4u * m + j0);
+  const uint2 hi = *reinterpret_cast<const uint2 *>(w + 4u * m + 4u + j0);
+  const uint32_t mask = width_mask(b);
+  const uint32_t d0 = funnel(hi.x, lo.x, s) & mask;
+  const uint32_t d1 = funnel(hi.y, lo.y, s) & mask;
+  const uint4 seed = L.seeds[k];
+  const uint32_t s0 = j0 ? seed.z : seed.x, s1 = j0 ? seed.w : seed.y;
+  const uint32_t x0 = s0 + scan_half32(d0);
+  const uint32_t x1 = s1 + scan_half32(d1);
+  *reinterpret_cast<uint2 *>(dst + 4u * q + j0) = make_uint2(x0, x1);
+}
+
+// First index c in [lo, hi) with v[c] >= key, else hi.
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ v, uint32_t lo, uint32_t hi,
+                                                    uint32_t key) {
+  uint32_t len = hi - lo;
+  while (len > 0) {
+    const uint32_t half = len >> 1;
+    if (v[lo + half] < key) {
+      lo += half + 1;
+      len -= half + 1;
+    } else {
+      len = half;
+    }
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------ pair items
+
+// Per-wave LDS of the intersection kernels.
+struct ItemLds {
+  uint32_t r[kBlock];          // the 128-value chunk of r
+  uint32_t f[4][kBlock];       // four decoded candidate blocks of f
+  uint32_t cand[kBlock];       // distinct candidate blocks of f
+  uint32_t bm[kMaxGallopBlocks];  // staged bmax entries (merge regime)
+};
+
+// The short side of a pair: a compressed list, or raw values on the device.
+struct RSide {
+  DList L;
+  const uint32_t *raw;  // null when compressed
+  uint64_t len;         // number of values of r
+};
+
+// Intersect chunk `item` of r (values 128 item .. 128 item + 127) with f.
+// Matches are written in increasing order to out[0 ..], their number to
+// *count.  The whole wave calls this with the same arguments.
+__device__ __forceinline__ void pair_item(const RSide &r, const DList &f, uint32_t item, ItemLds &s,
+                                          uint32_t *__restrict__ out, uint32_t *__restrict__ count,
+                                          uint32_t gallop_blocks) {
+  const uint32_t lane = lane_id();
+  // ---- the chunk of r
+  uint32_t cnt;
+  if (r.raw) {
+    const uint64_t base = uint64_t(item) * kBlock;
+    const uint64_t left = r.len - base;
+    cnt = left < kBlock ? uint32_t(left) : kBlock;
+    if (lane < cnt) s.r[lane] = r.raw[base + lane];
+    if (lane + 64 < cnt) s.r[lane + 64] = r.raw[base + 64 + lane];
+  } else if (item < r.L.nb) {
+    cnt = kBlock;
+    decode_block_wave(r.L, item, s.r);
+  } else {
+    cnt = r.L.t;
+    if (lane < cnt) s.r[lane] = r.L.tail[lane];
+    if (lane + 64 < cnt) s.r[lane + 64] = r.L.tail[lane + 64];
+  }
+  wave_sync();
+  const bool v0 = lane < cnt, v1 = lane + 64 < cnt;
+  const uint32_t a0 = v0 ? s.r[lane] : 0u;
+  const uint32_t a1 = v1 ? s.r[lane + 64] : 0u;
+  const uint32_t first = uniform(s.r[0]);
+  const uint32_t last = uniform(s.r[cnt ? cnt - 1 : 0]);
+
+  // ---- span of f blocks that can hold [first, last]; index nb stands for
+  // the raw tail (bmax taken as +infinity there)
+  const uint32_t nbf = f.nb;
+  const bool ftail = f.t > 0;
+  uint32_t fmax = 0;
+  if (f.n > 0) fmax = ftail ? f.tail[f.t - 1] : f.bmax[nbf - 1];
+  const bool any = cnt > 0 && f.n > 0 && first <= fmax;
+  bool f0 = false, f1 = false;
+  if (any) {
+    const uint32_t lo = uniform(lower_bound_u32(f.bmax, 0, nbf, first));
+    const uint32_t hi = uniform(lower_bound_u32(f.bmax, lo, nbf, last));
+    const uint32_t span = hi - lo + 1;
+    // ---- candidate block of each value: first c in [lo, hi] with bmax[c] >= a
+    uint32_t c0, c1;
+    if (span <= gallop_blocks) {
+      for (uint32_t e = lane; e < span; e += 64) s.bm[e] = (lo + e < nbf) ? f.bmax[lo + e] : kInvalid;
+      wave_sync();
+      c0 = lo + lower_bound_u32(s.bm, 0, span - 1, a0);
+      c1 = lo + lower_bound_u32(s.bm, 0, span - 1, a1);
+    } else {
+      c0 = lower_bound_u32(f.bmax, lo, hi, a0);
+      c1 = lower_bound_u32(f.bmax, lo, hi, a1);
+    }
+    const bool ok0 = v0 && a0 <= fmax;
+    const bool ok1 = v1 && a1 <= fmax;
+    // ---- distinct candidates (c is non-decreasing over the chunk)
+    uint32_t p0 = __shfl_up(c0, 1);
+    uint32_t p1 = __shfl_up(c1, 1);
+    const uint32_t c0_last = __shfl(c0, 63);
+    if (lane == 0) p1 = c0_last;
+    const bool n0 = ok0 && (lane == 0 || c0 != p0);
+    const bool n1 = ok1 && (c1 != p1);
+    const uint64_t m0 = __ballot(n0), m1 = __ballot(n1);
+    const uint32_t u0 = uint32_t(__popcll(m0));
+    const uint32_t U = u0 + uint32_t(__popcll(m1));
+    if (n0) s.cand[mbcnt64(m0)] = c0;
+    if (n1) s.cand[u0 + mbcnt64(m1)] = c1;
+    const uint32_t slot0 = ok0 ? mbcnt64(m0) + (n0 ? 1u : 0u) - 1u : kInvalid;
+    const uint32_t slot1 = ok1 ? u0 + mbcnt64(m1) + (n1 ? 1u : 0u) - 1u : kInvalid;
+    wave_sync();
+    // ---- decode candidate blocks four at a time (one row each) and search
+    const uint32_t row = lane >> 4, ri = lane & 15u;
+    for (uint32_t g = 0; g < U; g += 4) {
+      const uint32_t cs = g + row;
+      const uint32_t blk = cs < U ? s.cand[cs] : kInvalid;
+      uint32_t x0[4], x1[4];
+      decode_row(f, blk, blk < nbf, ri, x0, x1);
+      if (blk < nbf) {
+        *reinterpret_cast<uint4 *>(&s.f[row][8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
+        *reinterpret_cast<uint4 *>(&s.f[row][8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
+      } else if (blk == nbf) {
+        for (uint32_t e = 0; e < 8; ++e)
+          if (8 * ri + e < f.t) s.f[row][8 * ri + e] = f.tail[8 * ri + e];
+      }
+      wave_sync();
+      if (slot0 - g < 4u) {
+        const uint32_t n = (c0 == nbf) ? f.t : kBlock;
+        const uint32_t *v = s.f[slot0 - g];
+        const uint32_t p = lower_bound_u32(v, 0, n, a0);
+        f0 = p < n && v[p] == a0;
+      }
+      if (slot1 - g < 4u) {
+        const uint32_t n = (c1 == nbf) ? f.t : kBlock;
+        const uint32_t *v = s.f[slot1 - g];
+        const uint32_t p = lower_bound_u32(v, 0, n, a1);
+        f1 = p < n && v[p] == a1;
+      }
+      wave_sync();
+    }
+  }
+  // ---- ordered compaction of the matches (ballot + mbcnt)
+  const uint64_t mm0 = __ballot(f0), mm1 = __ballot(f1);
+  const uint32_t k0 = uint32_t(__popcll(mm0));
+  if (f0) out[mbcnt64(mm0)] = a0;
+  if (f1) out[k0 + mbcnt64(mm1)] = a1;
+  if (lane == 0) *count = k0 + uint32_t(__popcll(mm1));
+}
+
+}  // namespace s4

@@ -1,0 +1,90 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared
+symbol, and its host encoder writes the same bytes as the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_1401_6399_amd as s4
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "s4.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(s4_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = s4.require_library()
+    names = declared_functions()
+    assert len(names) >= 30
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(s4.SIGNATURES), set(names) ^ set(s4.SIGNATURES)
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 4, 5, 127, 128, 129, 2047, 2048, 2049, 65536 + 5])
+@pytest.mark.parametrize("kind", [workloads.UNIFORM, workloads.CLUSTERED])
+def test_encode_bytes_match_oracle(n, kind):
+    x = workloads.sorted_list(kind, 300 + n, 1 << 26, n)
+    assert np.array_equal(s4.encode(x), oracle.encode(x))
+
+
+def test_encode_plain_pair_matches_oracle():
+    a, b = workloads.plain_pair()
+    assert np.array_equal(s4.encode(a), oracle.encode(a))
+    assert np.array_equal(s4.encode(b), oracle.encode(b))
+
+
+def test_encode_extreme_values_and_duplicates():
+    xs = [np.array([0, 2**32 - 1] * 1, np.uint32),
+          np.sort(np.random.default_rng(1).integers(0, 2**32, size=1000, dtype=np.uint64)).astype(np.uint32),
+          np.repeat(np.arange(300, dtype=np.uint32), 3),
+          np.full(1000, 7, np.uint32)]
+    for x in xs:
+        assert np.array_equal(s4.encode(x), oracle.encode(x))
+
+
+def test_encode_many_matches_single():
+    kinds, lens = workloads.bulk_lengths(16)
+    lens = (lens // 64).astype(np.uint64)
+    flat, offs = workloads.lists(kinds, lens, 99, 1 << 26)
+    buf, soffs = s4.encode_many(flat, offs, nthreads=4)
+    for i in range(len(lens)):
+        x = flat[int(offs[i]): int(offs[i + 1])]
+        assert np.array_equal(buf[int(soffs[i]): int(soffs[i + 1])], oracle.encode(x))
+
+
+def test_encode_rejects_unsorted():
+    with pytest.raises(s4.S4Error) as e:
+        s4.encode(np.array([5, 4], np.uint32))
+    assert e.value.code == s4.EUNSORTED
+
+
+def test_decoded_length_rejects_corrupt():
+    x = workloads.sorted_list(workloads.UNIFORM, 3, 1 << 20, 1000)
+    enc = s4.encode(x)
+    assert s4.decoded_length(enc) == 1000
+    for bad in (enc[:-4], np.concatenate([enc, np.zeros(4, np.uint8)])):
+        with pytest.raises(s4.S4Error) as e:
+            s4.decoded_length(bad)
+        assert e.value.code == s4.ECORRUPT
+    bad = enc.copy()
+    bad[32] = 40
+    with pytest.raises(s4.S4Error):
+        s4.decoded_length(bad)
+
+
+def test_tuning_validation():
+    t = s4.get_tuning()
+    with pytest.raises(s4.S4Error):
+        s4.set_tuning(gallop_blocks=0)
+    with pytest.raises(s4.S4Error):
+        s4.set_tuning(waves_per_group=3)
+    s4.set_tuning(**t.as_dict())
+    assert s4.get_tuning().as_dict() == t.as_dict()

@@ -175,3 +175,23 @@ def multiterm_queries(lens, nq: int = 1 << 18):
 
 def serving_queries(lens, nq: int, level: int = 0):
     return queries(config_seed(4, 10 + level), lens, nq, 2, 8)
+
+
+def planted_pair(seed: int, n: int, m: int, frac: float, universe: int = 1 << 26, kind: int = CLUSTERED):
+    """A long list f (n values) and a short list r (m values) sharing
+    round(frac * m) values: the shared values are drawn from f uniformly,
+    the rest of r from outside f, then r is sorted."""
+    f = sorted_list(kind, seed, universe, n)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    k = min(int(round(frac * m)), n, m)
+    shared = rng.choice(f, size=k, replace=False) if k else np.zeros(0, np.uint32)
+    need = m - k
+    others = np.zeros(0, np.uint32)
+    while others.size < need:
+        cand = rng.integers(0, universe, size=2 * (need - others.size) + 16, dtype=np.uint64).astype(np.uint32)
+        cand = cand[~np.isin(cand, f)]
+        others = np.unique(np.concatenate([others, cand]))
+    if others.size > need:
+        others = rng.choice(others, size=need, replace=False)
+    r = np.sort(np.concatenate([shared.astype(np.uint32), others.astype(np.uint32)]))
+    return r, f
