@@ -127,6 +127,31 @@ int s4_decode_dev(const s4_list *list, uint32_t *d_out, uint64_t cap, void *stre
 int s4_decode_blocks_dev(const s4_list *list, uint32_t first, uint32_t count, uint32_t *d_out,
                          void *stream);
 
+/* Decode `count` lists with one kernel launch per list (the same kernel as
+ * s4_decode_dev): list i into d_outs[i] (capacity caps[i], 16-byte
+ * aligned).  Launches are spread over up to `nstreams` (1..8) streams
+ * forked from `stream` and joined back into it before the call's work is
+ * complete in `stream` order, so independent lists overlap on the device;
+ * the call is capturable into a hipGraph on `stream`. */
+int s4_decode_lists_dev(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
+                        uint32_t count, uint32_t nstreams, void *stream);
+
+/* A reusable multi-list decode: one kernel launch decodes every list of
+ * the plan (workgroups are laid out over the concatenated blocks of all
+ * lists).  The plan holds a device table of the lists and output
+ * pointers, built once; the lists must outlive it. */
+typedef struct s4_decode_plan s4_decode_plan;
+int s4_decode_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
+                          uint32_t count, void *stream, s4_decode_plan **out);
+int s4_decode_plan_run(const s4_decode_plan *plan, void *stream);
+int s4_decode_plan_free(s4_decode_plan *plan);
+
+/* Benchmarking aid: enqueue a kernel that busy-waits on the device's
+ * constant-rate clock for about `ns` nanoseconds (always terminates), so a
+ * host can enqueue timed work behind it without its own launch latency
+ * showing in event timings. */
+int s4_spin_dev(uint64_t ns, void *stream);
+
 /* --------------------------------------------------------- intersections
  *
  * Inputs must have been encoded from strictly increasing lists (flag bit 0),
@@ -174,6 +199,7 @@ typedef struct {
   uint32_t waves_per_group;
   uint32_t groups_per_cu;
   uint32_t items_per_grab;
+  uint32_t decode_passes; /* bulk decode: 4 * decode_passes blocks per wave (1, 2, 4, 8) */
 } s4_tuning;
 
 int s4_get_tuning(s4_tuning *t);

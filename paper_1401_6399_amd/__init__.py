@@ -31,7 +31,8 @@ _u64 = ctypes.c_uint64
 
 class Tuning(ctypes.Structure):
     _fields_ = [("gallop_blocks", ctypes.c_uint32), ("waves_per_group", ctypes.c_uint32),
-                ("groups_per_cu", ctypes.c_uint32), ("items_per_grab", ctypes.c_uint32)]
+                ("groups_per_cu", ctypes.c_uint32), ("items_per_grab", ctypes.c_uint32),
+                ("decode_passes", ctypes.c_uint32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -65,6 +66,12 @@ SIGNATURES = {
     "s4_list_skip_index": (_i, [_vp, _u32p, _u32p, _vp]),
     "s4_decode_dev": (_i, [_vp, _vp, _u64, _vp]),
     "s4_decode_blocks_dev": (_i, [_vp, _u32, _u32, _vp, _vp]),
+    "s4_decode_lists_dev": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u64p, _u32, _u32, _vp]),
+    "s4_decode_plan_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u64p, _u32, _vp,
+                                   ctypes.POINTER(_vp)]),
+    "s4_decode_plan_run": (_i, [_vp, _vp]),
+    "s4_decode_plan_free": (_i, [_vp]),
+    "s4_spin_dev": (_i, [_u64, _vp]),
     "s4_intersect_scratch_bytes": (_sz, [_u64, _u64]),
     "s4_intersect": (_i, [_vp, _vp, _vp, _u64, _vp, _vp, _sz, _vp]),
     "s4_intersect_k_scratch_bytes": (_sz, [ctypes.POINTER(_vp), _u32]),
@@ -255,6 +262,47 @@ class DeviceList:
     def decode_blocks_into(self, first, count, out, stream=None):
         _check(require_library().s4_decode_blocks_dev(self.h, first, count, _dptr(out), _stream(stream)),
                "s4_decode_blocks_dev")
+
+
+def _out_arrays(lists, outs):
+    hs = _handles(lists)
+    ptrs = (ctypes.c_void_p * max(1, len(outs)))(*[o.data_ptr() for o in outs])
+    caps = np.array([o.numel() for o in outs] or [0], dtype=np.uint64)
+    return hs, ptrs, caps
+
+
+def decode_lists(lists, outs, nstreams=1, stream=None):
+    """One decode launch per list, spread over nstreams forked streams."""
+    hs, ptrs, caps = _out_arrays(lists, outs)
+    _check(require_library().s4_decode_lists_dev(hs, ptrs, _ptr(caps, ctypes.c_uint64), len(lists), nstreams,
+                                                 _stream(stream)), "s4_decode_lists_dev")
+
+
+class DecodePlan:
+    """Single-launch decode of many lists (s4_decode_plan)."""
+
+    def __init__(self, lists, outs, stream=None):
+        hs, ptrs, caps = _out_arrays(lists, outs)
+        self._keep = (lists, outs)
+        self.h = ctypes.c_void_p()
+        _check(require_library().s4_decode_plan_create(hs, ptrs, _ptr(caps, ctypes.c_uint64), len(lists),
+                                                       _stream(stream), ctypes.byref(self.h)),
+               "s4_decode_plan_create")
+
+    def run(self, stream=None):
+        _check(require_library().s4_decode_plan_run(self.h, _stream(stream)), "s4_decode_plan_run")
+
+    def __del__(self):
+        try:
+            if self.h:
+                require_library().s4_decode_plan_free(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+def spin(ns, stream=None):
+    _check(require_library().s4_spin_dev(int(ns), _stream(stream)), "s4_spin_dev")
 
 
 def _device_u64():

@@ -3,6 +3,7 @@
 // k-way (SvS) decode-fused intersection.
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <numeric>
 #include <vector>
@@ -16,7 +17,7 @@ namespace s4 {
 static std::mutex g_dev_mu;
 static int g_dev_checked = -1;  // device id verified, -1 none
 static int g_cus = 0;
-static s4_tuning g_tuning = {64u, 4u, 8u, 1u};
+static s4_tuning g_tuning = {64u, 4u, 8u, 1u, 4u};
 
 int ensure_device() {
   int dev = -1;
@@ -34,8 +35,41 @@ int ensure_device() {
 
 int cu_count() { return g_cus > 0 ? g_cus : 256; }
 s4_tuning &tuning() { return g_tuning; }
+static uint32_t tuning_decode_passes() {
+  const uint32_t p = g_tuning.decode_passes;
+  return (p == 1 || p == 2 || p == 4 || p == 8) ? p : 4u;
+}
 
 static inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Library-owned helper streams (default priority) and events used to fork
+// independent launches off a caller's stream and join them back.
+constexpr uint32_t kMaxStreams = 8;
+struct StreamPool {
+  hipStream_t streams[kMaxStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxStreams] = {};
+};
+static std::mutex g_pool_mu;
+static std::map<int, StreamPool> g_pools;
+
+// Caller holds g_pool_mu.
+static int get_pool(StreamPool **out) {
+  int dev = 0;
+  S4_HIP(hipGetDevice(&dev));
+  auto it = g_pools.find(dev);
+  if (it == g_pools.end()) {
+    StreamPool p;
+    for (uint32_t s = 1; s < kMaxStreams; ++s) {
+      S4_HIP(hipStreamCreateWithFlags(&p.streams[s], hipStreamNonBlocking));
+      S4_HIP(hipEventCreateWithFlags(&p.join[s], hipEventDisableTiming));
+    }
+    S4_HIP(hipEventCreateWithFlags(&p.fork, hipEventDisableTiming));
+    it = g_pools.emplace(dev, p).first;
+  }
+  *out = &it->second;
+  return S4_OK;
+}
 
 // ----------------------------------------------------------------- kernels
 
@@ -99,52 +133,124 @@ __global__ __launch_bounds__(256) void k_seed_scan(const uint64_t *__restrict__ 
   }
 }
 
-// Bulk decode of blocks [first, first + count) of L (index nb = raw tail).
-// Each wave decodes 4 consecutive blocks per pass (one 16-lane row each)
-// for `passes` passes; the D4 prefix runs across the whole wave (row scans
-// joined by row broadcasts), so only the wave's first block reads a seed
-// from the skip index and later blocks carry it in registers.
-__global__ __launch_bounds__(256) void k_decode(DList L, uint32_t first, uint32_t count, uint32_t passes,
-                                                uint32_t block_waves, uint32_t *__restrict__ out) {
+// LDS words one wave uses to transpose one pass (4 blocks) of output.
+constexpr uint32_t kPassWords = 4u * kBlock;
+
+// Bulk decode by one wave: blocks [kbase, min(kbase + 4 P, full_end)) of L,
+// block k written at out + 128 (k - first).
+//  1. Lane l reads the width of block kbase + l; a wave scan of 4 b gives
+//     every block's payload offset from the one offset of block kbase, so
+//     the payload loads of all P passes are independent and issue together
+//     (the passes are unrolled).
+//  2. Each pass decodes 4 consecutive blocks (one 16-lane row each); the D4
+//     prefix runs across the whole wave (row scans joined by row
+//     broadcasts) and is carried from pass to pass in registers, so only
+//     the wave's first block reads a seed from the skip index.
+//  3. The pass's 512 values go through the wave's LDS slice so that each
+//     store instruction writes 1 KiB of contiguous output (lane l stores
+//     values 4l .. 4l + 3 of each half): whole cache lines per instruction.
+template <int P>
+__device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
+                                            uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
+  static_assert(P >= 1 && P <= 16, "4 P blocks per wave must fit 64 lanes");
   const uint32_t lane = lane_id();
-  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const uint32_t end = first + count;
-  const uint32_t full_end = min(end, L.nb);
-  if (wave >= block_waves) {
-    // the raw tail, when the range covers it
-    if (wave == block_waves && end > L.nb && L.t > 0) {
-      uint32_t *dst = out + uint64_t(L.nb - first) * kBlock;
-      if (lane < L.t) dst[lane] = L.tail[lane];
-      if (lane + 64 < L.t) dst[lane + 64] = L.tail[lane + 64];
-    }
-    return;
-  }
   const uint32_t row = lane >> 4, i = lane & 15u;
-  const uint32_t kbase = first + wave * 4u * passes;
+  kbase = uniform(kbase);
+  const uint32_t kl = kbase + lane;
+  const bool vl = lane < 4u * P && kl < full_end;
+  const uint32_t bl = vl ? uint32_t(L.widths[kl]) : 0u;
+  const uint32_t base_off = L.offs[kbase];
+  const uint32_t wl = 4u * bl;
+  const uint32_t ol = base_off + scan_wave64(wl) - wl;
   const uint4 s = L.seeds[kbase];
   uint32_t c[4] = {s.x, s.y, s.z, s.w};
-  for (uint32_t p = 0; p < passes; ++p) {
+  uint32_t d0[P][4], d1[P][4];
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const uint32_t src = 4u * p + row;
+    const uint32_t b = uint32_t(__shfl(int(bl), int(src)));
+    const uint32_t off = uint32_t(__shfl(int(ol), int(src)));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) d0[p][j] = d1[p][j] = 0;
+    if (kbase + src < full_end) extract_row(L.payload + off, b, i, d0[p], d1[p]);
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
     const uint32_t k0 = kbase + 4u * p;
-    if (k0 >= full_end) break;
-    const uint32_t k = k0 + row;
-    const bool valid = k < full_end;
-    uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
-    if (valid) extract_row(L.payload + L.offs[k], L.widths[k], i, d0, d1);
     uint32_t x0[4], x1[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const uint32_t sc = scan_wave64(d0[j] + d1[j]);
+      const uint32_t sc = scan_wave64(d0[p][j] + d1[p][j]);
       x1[j] = c[j] + sc;
-      x0[j] = x1[j] - d1[j];
-    }
-    if (valid) {
-      uint4 *dst = reinterpret_cast<uint4 *>(out + uint64_t(k - first) * kBlock + 8u * i);
-      dst[0] = make_uint4(x0[0], x0[1], x0[2], x0[3]);
-      dst[1] = make_uint4(x1[0], x1[1], x1[2], x1[3]);
+      x0[j] = x1[j] - d1[p][j];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) c[j] = uint32_t(__builtin_amdgcn_readlane(int(x1[j]), 63));
+    u32x4 *t = reinterpret_cast<u32x4 *>(tb + row * kBlock + 8u * i);
+    t[0] = u32x4{x0[0], x0[1], x0[2], x0[3]};
+    t[1] = u32x4{x1[0], x1[1], x1[2], x1[3]};
+    wave_sync();
+    const u32x4 y0 = reinterpret_cast<const u32x4 *>(tb)[lane];
+    const u32x4 y1 = reinterpret_cast<const u32x4 *>(tb)[64 + lane];
+    wave_sync();
+    uint32_t *dst = out + uint64_t(k0 - first) * kBlock + 4u * lane;
+    if (k0 + (lane >> 5) < full_end) store4(dst, y0);
+    if (k0 + 2u + (lane >> 5) < full_end) store4(dst + 256, y1);
   }
+}
+
+__device__ __forceinline__ void copy_tail(const DList &L, uint32_t *__restrict__ dst) {
+  const uint32_t lane = lane_id();
+  if (lane < L.t) dst[lane] = L.tail[lane];
+  if (lane + 64 < L.t) dst[lane + 64] = L.tail[lane + 64];
+}
+
+// Bulk decode of blocks [first, first + count) of L (index nb = raw tail):
+// waves [0, block_waves) decode 4 passes-worth of blocks each, the next
+// wave copies the tail when the range covers it.
+template <int P>
+__global__ __launch_bounds__(256) void k_decode(DList L, uint32_t first, uint32_t count, uint32_t block_waves,
+                                                uint32_t *__restrict__ out) {
+  __shared__ __align__(16) uint32_t stage[4][kPassWords];
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + w;
+  const uint32_t end = first + count;
+  if (wave >= block_waves) {
+    if (wave == block_waves && end > L.nb && L.t > 0) copy_tail(L, out + uint64_t(L.nb - first) * kBlock);
+    return;
+  }
+  decode_wave<P>(L, first, min(end, L.nb), first + wave * 4u * P, out, stage[w]);
+}
+
+// Multi-list decode in one launch: wave w decodes for list wave_list[w];
+// wave_prefix[l] is the first wave of list l.  Within a list the waves are
+// laid out as in k_decode (blocks, then one tail wave when the list has a
+// tail).
+template <int P>
+__global__ __launch_bounds__(256) void k_decode_multi(const DList *__restrict__ lists,
+                                                      uint32_t *const *__restrict__ outs,
+                                                      const uint32_t *__restrict__ wave_prefix,
+                                                      const uint32_t *__restrict__ wave_list, uint32_t waves) {
+  __shared__ __align__(16) uint32_t stage[4][kPassWords];
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t wave = uniform(blockIdx.x * (blockDim.x >> 6) + w);
+  if (wave >= waves) return;
+  const uint32_t l = uniform(wave_list[wave]);
+  const DList L = lists[l];
+  uint32_t *out = outs[l];
+  const uint32_t local = wave - wave_prefix[l];
+  const uint32_t block_waves = (L.nb + 4 * P - 1) / (4 * P);
+  if (local >= block_waves) {
+    copy_tail(L, out + uint64_t(L.nb) * kBlock);
+    return;
+  }
+  decode_wave<P>(L, 0, L.nb, local * 4u * P, out, stage[w]);
+}
+
+// Busy-wait on the constant-rate device clock for `ticks` ticks.
+__global__ void k_spin(uint64_t ticks) {
+  const uint64_t t0 = wall_clock64();
+  while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
 }
 
 // One wave per chunk of r: decode-fused pairwise intersection.  Writes the
@@ -422,24 +528,44 @@ static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len
   return S4_OK;
 }
 
+template <int P>
+static void launch_decode(const DList &L, uint32_t first, uint32_t count, uint32_t block_waves, uint32_t waves,
+                          uint32_t *d_out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, L, first, count, block_waves, d_out);
+}
+
 int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream) {
   const uint32_t end = first + count;
   const uint32_t full = end > L.nb ? (L.nb > first ? L.nb - first : 0) : count;
-  // passes per wave: keep at least ~4 waves per CU in flight
-  const uint32_t target_waves = uint32_t(cu_count()) * 4u;
-  uint32_t passes = 8;
-  while (passes > 1 && (full + 4 * passes - 1) / (4 * passes) < target_waves) passes >>= 1;
-  const uint32_t block_waves = (full + 4 * passes - 1) / (4 * passes);
+  // blocks per wave (4 P): the largest P that still gives ~8 waves per CU
+  const uint32_t target_waves = uint32_t(cu_count()) * 8u;
+  uint32_t P = tuning_decode_passes();
+  while (P > 1 && (full + 4 * P - 1) / (4 * P) < target_waves) P >>= 1;
+  const uint32_t block_waves = (full + 4 * P - 1) / (4 * P);
   const bool tail = end > L.nb && L.t > 0;
   const uint32_t waves = block_waves + (tail ? 1 : 0);
   if (waves == 0) return S4_OK;
-  hipLaunchKernelGGL(k_decode, dim3((waves + 3) / 4), dim3(256), 0, stream, L, first, count, passes, block_waves,
-                     d_out);
+  switch (P) {
+    case 8: launch_decode<8>(L, first, count, block_waves, waves, d_out, stream); break;
+    case 4: launch_decode<4>(L, first, count, block_waves, waves, d_out, stream); break;
+    case 2: launch_decode<2>(L, first, count, block_waves, waves, d_out, stream); break;
+    default: launch_decode<1>(L, first, count, block_waves, waves, d_out, stream); break;
+  }
   S4_HIP(hipGetLastError());
   return S4_OK;
 }
 
 }  // namespace s4
+
+struct s4_decode_plan {
+  void *table = nullptr;
+  const s4::DList *lists = nullptr;
+  uint32_t *const *outs = nullptr;
+  const uint32_t *prefix = nullptr;
+  const uint32_t *wave_list = nullptr;
+  uint32_t count = 0, passes = 4, waves = 0;
+  uint64_t ints = 0;
+};
 
 using namespace s4;
 
@@ -461,6 +587,8 @@ int s4_set_tuning(const s4_tuning *t) {
     return fail(S4_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
   if (t->groups_per_cu < 1 || t->groups_per_cu > 32) return fail(S4_EINVAL, "groups_per_cu must be in [1, 32]");
   if (t->items_per_grab < 1 || t->items_per_grab > 64) return fail(S4_EINVAL, "items_per_grab must be in [1, 64]");
+  if (t->decode_passes != 1 && t->decode_passes != 2 && t->decode_passes != 4 && t->decode_passes != 8)
+    return fail(S4_EINVAL, "decode_passes must be 1, 2, 4 or 8");
   tuning() = *t;
   return S4_OK;
 }
@@ -539,6 +667,161 @@ int s4_decode_blocks_dev(const s4_list *l, uint32_t first, uint32_t count, uint3
   if (reinterpret_cast<uintptr_t>(d_out) & 15u) return fail(S4_EINVAL, "d_out must be 16-byte aligned");
   if (!count) return S4_OK;
   return decode_range(l->d, first, count, d_out, as_stream(stream));
+}
+
+int s4_decode_lists_dev(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
+                        uint32_t count, uint32_t nstreams, void *stream) {
+  if (!count) return S4_OK;
+  if (!lists || !d_outs || !caps) return fail(S4_EINVAL, "null argument");
+  if (nstreams < 1 || nstreams > kMaxStreams) return fail(S4_EINVAL, "nstreams must be in [1, 8]");
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!lists[i] || (!d_outs[i] && lists[i]->n)) return fail(S4_EINVAL, "null list or output");
+    if (caps[i] < lists[i]->n) return fail(S4_ERANGE, "cap < n for list " + std::to_string(i));
+    if (reinterpret_cast<uintptr_t>(d_outs[i]) & 15u) return fail(S4_EINVAL, "outputs must be 16-byte aligned");
+  }
+  int rc = ensure_device();
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  if (nstreams == 1) {
+    for (uint32_t i = 0; i < count; ++i) {
+      const s4_list *l = lists[i];
+      if (!l->n) continue;
+      rc = decode_range(l->d, 0, l->nb + (l->t ? 1 : 0), d_outs[i], st);
+      if (rc) return rc;
+    }
+    return S4_OK;
+  }
+  // longest-processing-time assignment of lists to streams by bytes moved
+  std::vector<uint32_t> order(count);
+  std::iota(order.begin(), order.end(), 0u);
+  std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return lists[a]->n > lists[b]->n; });
+  std::vector<uint64_t> load(nstreams, 0);
+  std::vector<uint32_t> owner(count);
+  for (uint32_t i : order) {
+    uint32_t best = 0;
+    for (uint32_t s = 1; s < nstreams; ++s)
+      if (load[s] < load[best]) best = s;
+    owner[i] = best;
+    load[best] += lists[i]->payload_bytes + 4 * lists[i]->n + 4096;
+  }
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  StreamPool *pool = nullptr;
+  rc = get_pool(&pool);
+  if (rc) return rc;
+  S4_HIP(hipEventRecord(pool->fork, st));
+  for (uint32_t s = 1; s < nstreams; ++s) S4_HIP(hipStreamWaitEvent(pool->streams[s], pool->fork, 0));
+  for (uint32_t i : order) {
+    const s4_list *l = lists[i];
+    if (!l->n) continue;
+    hipStream_t target = owner[i] == 0 ? st : pool->streams[owner[i]];
+    rc = decode_range(l->d, 0, l->nb + (l->t ? 1 : 0), d_outs[i], target);
+    if (rc) return rc;
+  }
+  for (uint32_t s = 1; s < nstreams; ++s) {
+    S4_HIP(hipEventRecord(pool->join[s], pool->streams[s]));
+    S4_HIP(hipStreamWaitEvent(st, pool->join[s], 0));
+  }
+  return S4_OK;
+}
+
+int s4_decode_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
+                          uint32_t count, void *stream, s4_decode_plan **out) {
+  if (!out || (count && (!lists || !d_outs || !caps))) return fail(S4_EINVAL, "null argument");
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!lists[i] || (!d_outs[i] && lists[i]->n)) return fail(S4_EINVAL, "null list or output");
+    if (caps[i] < lists[i]->n) return fail(S4_ERANGE, "cap < n for list " + std::to_string(i));
+    if (reinterpret_cast<uintptr_t>(d_outs[i]) & 15u) return fail(S4_EINVAL, "outputs must be 16-byte aligned");
+  }
+  int rc = ensure_device();
+  if (rc) return rc;
+  s4_decode_plan *p = new (std::nothrow) s4_decode_plan;
+  if (!p) return fail(S4_ENOMEM, "plan allocation failed");
+  p->count = count;
+  p->passes = tuning_decode_passes();
+  std::vector<uint32_t> prefix(count + 1, 0);
+  for (uint32_t i = 0; i < count; ++i) {
+    const s4_list *l = lists[i];
+    const uint32_t bw = (l->nb + 4 * p->passes - 1) / (4 * p->passes);
+    prefix[i + 1] = prefix[i] + bw + (l->t ? 1u : 0u);
+    p->ints += l->n;
+  }
+  p->waves = prefix[count];
+  const size_t desc_b = align_up(sizeof(DList) * std::max<uint32_t>(1, count), 256);
+  const size_t outs_b = align_up(sizeof(uint32_t *) * std::max<uint32_t>(1, count), 256);
+  const size_t pre_b = align_up(4 * size_t(count + 1), 256);
+  const size_t wl_b = align_up(4 * size_t(std::max<uint32_t>(1, p->waves)), 256);
+  hipError_t e = hipMalloc(&p->table, desc_b + outs_b + pre_b + wl_b);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(S4_ENOMEM, "plan table allocation failed");
+  }
+  std::vector<char> img(desc_b + outs_b + pre_b + wl_b, 0);
+  uint32_t *wl = reinterpret_cast<uint32_t *>(img.data() + desc_b + outs_b + pre_b);
+  for (uint32_t i = 0; i < count; ++i)
+    for (uint32_t w = prefix[i]; w < prefix[i + 1]; ++w) wl[w] = i;
+  for (uint32_t i = 0; i < count; ++i) {
+    std::memcpy(img.data() + sizeof(DList) * i, &lists[i]->d, sizeof(DList));
+    std::memcpy(img.data() + desc_b + sizeof(uint32_t *) * i, &d_outs[i], sizeof(uint32_t *));
+  }
+  std::memcpy(img.data() + desc_b + outs_b, prefix.data(), 4 * size_t(count + 1));
+  e = hipMemcpyAsync(p->table, img.data(), img.size(), hipMemcpyHostToDevice, as_stream(stream));
+  if (e == hipSuccess) e = hipStreamSynchronize(as_stream(stream));
+  if (e != hipSuccess) {
+    (void)hipFree(p->table);
+    delete p;
+    return hip_fail(e, "plan upload");
+  }
+  p->lists = static_cast<const DList *>(p->table);
+  p->outs = reinterpret_cast<uint32_t *const *>(static_cast<char *>(p->table) + desc_b);
+  p->prefix = reinterpret_cast<const uint32_t *>(static_cast<char *>(p->table) + desc_b + outs_b);
+  p->wave_list = reinterpret_cast<const uint32_t *>(static_cast<char *>(p->table) + desc_b + outs_b + pre_b);
+  *out = p;
+  return S4_OK;
+}
+
+int s4_decode_plan_run(const s4_decode_plan *p, void *stream) {
+  if (!p) return fail(S4_EINVAL, "null plan");
+  if (!p->waves) return S4_OK;
+  switch (p->passes) {
+    case 8:
+      hipLaunchKernelGGL(k_decode_multi<8>, dim3((p->waves + 3) / 4), dim3(256), 0, as_stream(stream), p->lists,
+                         p->outs, p->prefix, p->wave_list, p->waves);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_decode_multi<2>, dim3((p->waves + 3) / 4), dim3(256), 0, as_stream(stream), p->lists,
+                         p->outs, p->prefix, p->wave_list, p->waves);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_decode_multi<1>, dim3((p->waves + 3) / 4), dim3(256), 0, as_stream(stream), p->lists,
+                         p->outs, p->prefix, p->wave_list, p->waves);
+      break;
+    default:
+      hipLaunchKernelGGL(k_decode_multi<4>, dim3((p->waves + 3) / 4), dim3(256), 0, as_stream(stream), p->lists,
+                         p->outs, p->prefix, p->wave_list, p->waves);
+      break;
+  }
+  S4_HIP(hipGetLastError());
+  return S4_OK;
+}
+
+int s4_decode_plan_free(s4_decode_plan *p) {
+  if (!p) return S4_OK;
+  hipError_t e = hipFree(p->table);
+  delete p;
+  if (e != hipSuccess) return hip_fail(e, "hipFree");
+  return S4_OK;
+}
+
+int s4_spin_dev(uint64_t ns, void *stream) {
+  int rc = ensure_device();
+  if (rc) return rc;
+  int khz = 0;
+  S4_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g_dev_checked));
+  if (khz <= 0) khz = 100000;
+  const uint64_t ticks = ns * uint64_t(khz) / 1000000ull;
+  hipLaunchKernelGGL(k_spin, dim3(1), dim3(64), 0, as_stream(stream), ticks);
+  S4_HIP(hipGetLastError());
+  return S4_OK;
 }
 
 size_t s4_intersect_scratch_bytes(uint64_t len_a, uint64_t len_b) {

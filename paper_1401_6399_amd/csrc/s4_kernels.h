@@ -63,6 +63,26 @@ __device__ __forceinline__ uint32_t scan_wave64(uint32_t v) {
   return v;
 }
 
+// Streaming 16-byte store that does not keep the line in cache.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_nt4(uint32_t *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  u32x4 v = {a, b, c, d};
+#ifdef S4_PLAIN_STORES
+  *reinterpret_cast<u32x4 *>(p) = v;
+#else
+  __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+#endif
+}
+
+// 16-byte store of decoded output (plain; whole lines per instruction).
+__device__ __forceinline__ void store4(uint32_t *p, u32x4 v) {
+#ifndef S4_PLAIN_STORES
+  __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+#else
+  *reinterpret_cast<u32x4 *>(p) = v;
+#endif
+}
+
 // ------------------------------------------------------------ extraction
 
 __device__ __forceinline__ uint32_t width_mask(uint32_t b) { return b >= 32u ? 0xFFFFFFFFu : ((1u << b) - 1u); }
