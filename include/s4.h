@@ -169,7 +169,10 @@ int s4_intersect(const s4_list *a, const s4_list *b, uint32_t *d_out, uint64_t c
 /* k-way conjunction (SvS, Sec. 6): lists are ordered by length, the two
  * shortest are intersected (both compressed), then the uncompressed
  * intermediate is intersected with each next list in turn, decoding only
- * the blocks it needs.  k = 0 is S4_EINVAL; k = 1 decodes the list. */
+ * the blocks it needs.  The work is split by 128-value chunks of the
+ * shortest list, each chunk carried through all the lists by one wavefront
+ * (one launch in all), which gives the same set.  k = 0 or k > 33 is
+ * S4_EINVAL; k = 1 decodes the list. */
 size_t s4_intersect_k_scratch_bytes(const s4_list *const *lists, uint32_t k);
 int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap,
                    uint64_t *d_count, void *d_scratch, size_t scratch_bytes, void *stream);

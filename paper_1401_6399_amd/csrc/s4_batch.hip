@@ -1,16 +1,437 @@
-// placeholder translation unit, replaced by the batch engine
-#include "s4_internal.h"
-using namespace s4;
-extern "C" {
-int s4_index_build(const uint8_t *, const uint64_t *, uint64_t, void *, s4_index **) { return fail(S4_EINVAL, "index not built"); }
-int s4_index_free(s4_index *) { return S4_OK; }
-int s4_index_lengths(const s4_index *, uint64_t *) { return fail(S4_EINVAL, "index not built"); }
-int s4_index_info(const s4_index *, uint64_t *, uint64_t *, uint64_t *, uint64_t *) { return fail(S4_EINVAL, "index not built"); }
-int s4_index_list(const s4_index *, uint64_t, s4_list **) { return fail(S4_EINVAL, "index not built"); }
-int s4_batch_plan(const s4_index *, const uint32_t *, const uint64_t *, uint64_t, void *, s4_batch **) { return fail(S4_EINVAL, "batch not built"); }
-int s4_batch_free(s4_batch *) { return S4_OK; }
-uint64_t s4_batch_results_bound(const s4_batch *) { return 0; }
-int s4_batch_run(s4_batch *, uint64_t *, uint64_t *, uint32_t *, uint64_t, int, void *) { return fail(S4_EINVAL, "batch not built"); }
-int s4_batch_query_ticks(const s4_batch *, uint64_t *, void *) { return fail(S4_EINVAL, "batch not built"); }
-int s4_batch_autotune(s4_batch *, uint64_t *, uint64_t *, uint32_t *, uint64_t, int, void *, s4_tuning *, double *) { return fail(S4_EINVAL, "batch not built"); }
+// Device-resident index of many lists, and batches of conjunctive queries
+// run as one persistent decode-fused launch (plus scan and compaction),
+// optionally replayed from a captured hipGraph; autotuning of the launch
+// parameters.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "s4_kernels.h"
+
+namespace s4 {
+
+// Reset the work queue and the per-query completion stamps.
+__global__ void k_batch_begin(BatchDev b) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    *b.head = 0;
+    *b.start = wall_clock64();
+  }
+  for (uint32_t q = t; q < b.nq; q += gridDim.x * blockDim.x) b.qtick[q] = 0;
 }
+
+// Persistent chunk kernel: every wave takes `grab` chunks at a time from
+// the queue until it is empty; a chunk of query q is 128 values of q's
+// shortest list carried through all of q's other lists (SvS per chunk).
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_t grab, uint32_t gallop_blocks) {
+  __shared__ ItemLds lds[WAVES];
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  const uint64_t t0 = *b.start;
+  for (;;) {
+    uint32_t it0 = 0;
+    if (lane == 0) it0 = atomicAdd(b.head, grab);
+    it0 = uint32_t(__shfl(int(it0), 0));
+    if (it0 >= b.items) break;
+    const uint32_t it1 = min(it0 + grab, b.items);
+    for (uint32_t item = it0; item < it1; ++item) {
+      const uint32_t q = uniform(b.item_query[item]);
+      const uint32_t local = item - b.item_base[q];
+      const uint32_t tq = b.qoff[q];
+      const uint32_t k = b.qoff[q + 1] - tq;
+      RSide r;
+      r.L = b.lists[b.sterms[tq]];
+      r.raw = nullptr;
+      r.len = r.L.n;
+      const uint32_t cnt = chain_chunk(
+          r, local, [&](uint32_t j) -> DList { return b.lists[b.sterms[tq + 1 + j]]; }, k - 1, lds[w],
+          gallop_blocks);
+      store_chunk(cnt, lds[w], b.stage + uint64_t(item) * kBlock, b.counts + item);
+      if (lane == 0) atomicMax(reinterpret_cast<unsigned long long *>(b.qtick + q),
+                               static_cast<unsigned long long>(wall_clock64() - t0));
+    }
+  }
+}
+
+// Per-query counts and CSR offsets from the global exclusive scan.
+__global__ void k_batch_finish(BatchDev b, uint64_t *__restrict__ d_counts, uint64_t *__restrict__ d_offs) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t total = *b.total;
+  if (q > b.nq) return;
+  auto gex = [&](uint32_t i) -> uint64_t {
+    return i < b.items ? uint64_t(b.excl[i]) + b.tiles[i >> 10] : total;
+  };
+  if (q == b.nq) {
+    d_offs[b.nq] = total;
+    return;
+  }
+  const uint64_t o0 = gex(b.item_base[q]), o1 = gex(b.item_base[q + 1]);
+  d_counts[q] = o1 - o0;
+  d_offs[q] = o0;
+}
+
+}  // namespace s4
+
+using namespace s4;
+
+struct s4_batch {
+  const s4_index *index = nullptr;
+  void *mem = nullptr;
+  BatchDev dev{};
+  uint64_t nq = 0, results_bound = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void *g_counts = nullptr, *g_offs = nullptr, *g_results = nullptr;
+  s4_tuning g_tuning{};
+};
+
+static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <int W>
+static void launch_chunks(const BatchDev &d, const s4_tuning &t, hipStream_t st) {
+  const uint32_t per_group = W * t.items_per_grab;
+  uint32_t groups = uint32_t(cu_count()) * t.groups_per_cu;
+  groups = std::max<uint32_t>(1, std::min<uint32_t>(groups, (d.items + per_group - 1) / per_group));
+  hipLaunchKernelGGL(k_batch_chunks<W>, dim3(groups), dim3(W * 64), 0, st, d, t.items_per_grab,
+                     std::min(t.gallop_blocks, kMaxGallopBlocks));
+}
+
+namespace s4 {
+// Enqueue one run of a batch described by d on st.
+int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st) {
+  const s4_tuning t = tuning();
+  const uint32_t begin_groups = std::max<uint32_t>(1, std::min<uint32_t>(1024, (d.nq + 255) / 256));
+  hipLaunchKernelGGL(k_batch_begin, dim3(begin_groups), dim3(256), 0, st, d);
+  if (d.items) {
+    switch (t.waves_per_group) {
+      case 1: launch_chunks<1>(d, t, st); break;
+      case 2: launch_chunks<2>(d, t, st); break;
+      case 8: launch_chunks<8>(d, t, st); break;
+      default: launch_chunks<4>(d, t, st); break;
+    }
+  }
+  S4_HIP(hipGetLastError());
+  int rc = scan_and_compact(d.stage, d.counts, d.items, d.excl, d.tiles, d.ntiles, d.total, d_results, st);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_batch_finish, dim3(uint32_t((d.nq + 1 + 255) / 256)), dim3(256), 0, st, d, d_counts, d_offs);
+  S4_HIP(hipGetLastError());
+  return S4_OK;
+}
+}  // namespace s4
+
+static int enqueue_batch(s4_batch *b, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st) {
+  return enqueue_batch_dev(b->dev, d_counts, d_offs, d_results, st);
+}
+
+static void drop_graph(s4_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+extern "C" {
+
+int s4_index_build(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count, void *stream,
+                   s4_index **out) {
+  if (!out || !enc_offsets || (count && !encs)) return fail(S4_EINVAL, "null argument");
+  if (count > 0xFFFFFFFFull) return fail(S4_EINVAL, "too many lists");
+  Upload u;
+  u.views.resize(count);
+  for (uint64_t i = 0; i < count; ++i) {
+    if (enc_offsets[i + 1] < enc_offsets[i]) return fail(S4_EINVAL, "offsets decrease");
+    int rc = parse_stream(encs + enc_offsets[i], size_t(enc_offsets[i + 1] - enc_offsets[i]), &u.views[i]);
+    if (rc) return fail(rc, "list " + std::to_string(i) + ": " + s4_last_error());
+  }
+  s4_index *ix = new (std::nothrow) s4_index;
+  if (!ix) return fail(S4_ENOMEM, "handle allocation failed");
+  int rc = build_arena(u, as_stream(stream), &ix->arena, &ix->lists);
+  if (rc) {
+    delete ix;
+    return rc;
+  }
+  hipError_t e = hipStreamSynchronize(as_stream(stream));
+  if (e != hipSuccess) {
+    (void)hipFree(ix->arena);
+    delete ix;
+    return hip_fail(e, "index build");
+  }
+  ix->count = count;
+  ix->d_lists = reinterpret_cast<const DList *>(static_cast<char *>(ix->arena) + u.lay.desc_off);
+  ix->lengths.resize(count);
+  ix->flags.resize(count);
+  ix->pw.resize(count);
+  for (uint64_t i = 0; i < count; ++i) {
+    const StreamView &v = u.views[i];
+    ix->lengths[i] = v.n;
+    ix->pw[i] = v.pw;
+    ix->flags[i] = v.flags;
+    ix->total_ints += v.n;
+    ix->payload_bytes += uint64_t(v.nb) + 4 * v.pw + 4ull * v.t;
+    ix->index_bytes += uint64_t(v.nb) * (4 + 4 + 16);
+  }
+  *out = ix;
+  return S4_OK;
+}
+
+int s4_index_free(s4_index *ix) {
+  if (!ix) return S4_OK;
+  hipError_t e = ix->arena ? hipFree(ix->arena) : hipSuccess;
+  delete ix;
+  if (e != hipSuccess) return hip_fail(e, "hipFree");
+  return S4_OK;
+}
+
+int s4_index_lengths(const s4_index *ix, uint64_t *lengths) {
+  if (!ix || (ix->count && !lengths)) return fail(S4_EINVAL, "null argument");
+  std::copy(ix->lengths.begin(), ix->lengths.end(), lengths);
+  return S4_OK;
+}
+
+int s4_index_info(const s4_index *ix, uint64_t *count, uint64_t *total_ints, uint64_t *payload_bytes,
+                  uint64_t *index_bytes) {
+  if (!ix) return fail(S4_EINVAL, "null index");
+  if (count) *count = ix->count;
+  if (total_ints) *total_ints = ix->total_ints;
+  if (payload_bytes) *payload_bytes = ix->payload_bytes;
+  if (index_bytes) *index_bytes = ix->index_bytes;
+  return S4_OK;
+}
+
+int s4_index_list(const s4_index *ix, uint64_t i, s4_list **out) {
+  if (!ix || !out) return fail(S4_EINVAL, "null argument");
+  if (i >= ix->count) return fail(S4_ERANGE, "list id out of range");
+  s4_list *l = new (std::nothrow) s4_list;
+  if (!l) return fail(S4_ENOMEM, "handle allocation failed");
+  const DList &d = ix->lists[i];
+  l->d = d;
+  l->n = d.n;
+  l->nb = d.nb;
+  l->t = d.t;
+  l->flags = ix->flags[i];
+  l->arena = nullptr;
+  l->pw = ix->pw[i];
+  l->payload_bytes = uint64_t(d.nb) + 4 * l->pw + 4ull * d.t;
+  l->index_bytes = uint64_t(d.nb) * (4 + 4 + 16);
+  *out = l;
+  return S4_OK;
+}
+
+int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
+                  void *stream, s4_batch **out) {
+  if (!ix || !h_q_offsets || !out || (nq && !h_terms)) return fail(S4_EINVAL, "null argument");
+  if (nq >= 0xFFFFFFFFull) return fail(S4_EINVAL, "too many queries");
+  int rc = ensure_device();
+  if (rc) return rc;
+  const uint64_t nterms = h_q_offsets[nq];
+  if (nterms >= 0xFFFFFFFFull) return fail(S4_EINVAL, "too many terms");
+  std::vector<uint32_t> sterms(nterms);
+  std::vector<uint32_t> qoff(nq + 1), item_base(nq + 1);
+  uint64_t items = 0, bound = 0;
+  for (uint64_t q = 0; q < nq; ++q) {
+    const uint64_t a = h_q_offsets[q], b = h_q_offsets[q + 1];
+    if (b < a || b > nterms) return fail(S4_EINVAL, "query offsets not increasing");
+    const uint64_t k = b - a;
+    if (k == 0 || k > kMaxTerms + 1) return fail(S4_EINVAL, "query " + std::to_string(q) + ": need 1..33 terms");
+    for (uint64_t t = a; t < b; ++t) {
+      if (h_terms[t] >= ix->count) return fail(S4_EINVAL, "query " + std::to_string(q) + ": term out of range");
+      if (k > 1 && !(ix->flags[h_terms[t]] & 1u))
+        return fail(S4_EUNSORTED, "list " + std::to_string(h_terms[t]) + " is not strictly increasing");
+      sterms[t] = h_terms[t];
+    }
+    std::stable_sort(sterms.begin() + a, sterms.begin() + b,
+                     [&](uint32_t x, uint32_t y) { return ix->lengths[x] < ix->lengths[y]; });
+    qoff[q] = uint32_t(a);
+    item_base[q] = uint32_t(items);
+    const uint64_t m = ix->lengths[sterms[a]];
+    items += (m + kBlock - 1) / kBlock;
+    bound += m;
+    if (items >= 0xFFFFFFFFull / kBlock || bound >= 0xFFFFFFFFull)
+      return fail(S4_EINVAL, "batch too large for one plan; split it");
+  }
+  qoff[nq] = uint32_t(nterms);
+  item_base[nq] = uint32_t(items);
+  std::vector<uint32_t> item_query(items);
+  for (uint64_t q = 0; q < nq; ++q)
+    for (uint32_t i = item_base[q]; i < item_base[q + 1]; ++i) item_query[i] = uint32_t(q);
+  const uint32_t ntiles = uint32_t((items + 1023) / 1024);
+  // one device allocation for every table
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 4), 256);
+    return o;
+  };
+  const size_t o_sterms = take(4 * nterms), o_qoff = take(4 * (nq + 1)), o_ib = take(4 * (nq + 1)),
+               o_iq = take(4 * items), o_stage = take(4 * kBlock * items), o_counts = take(4 * items),
+               o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)), o_ctrl = take(64),
+               o_qtick = take(8 * nq);
+  s4_batch *bt = new (std::nothrow) s4_batch;
+  if (!bt) return fail(S4_ENOMEM, "handle allocation failed");
+  if (hipMalloc(&bt->mem, off) != hipSuccess) {
+    delete bt;
+    return fail(S4_ENOMEM, "batch tables: hipMalloc of " + std::to_string(off) + " bytes failed");
+  }
+  char *m = static_cast<char *>(bt->mem);
+  hipStream_t st = as_stream(stream);
+  hipError_t e = hipSuccess;
+  auto up = [&](size_t o, const void *src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpyAsync(m + o, src, bytes, hipMemcpyHostToDevice, st);
+  };
+  up(o_sterms, sterms.data(), 4 * nterms);
+  up(o_qoff, qoff.data(), 4 * (nq + 1));
+  up(o_ib, item_base.data(), 4 * (nq + 1));
+  up(o_iq, item_query.data(), 4 * items);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    (void)hipFree(bt->mem);
+    delete bt;
+    return hip_fail(e, "batch plan upload");
+  }
+  BatchDev &d = bt->dev;
+  d.lists = ix->d_lists;
+  d.sterms = reinterpret_cast<const uint32_t *>(m + o_sterms);
+  d.qoff = reinterpret_cast<const uint32_t *>(m + o_qoff);
+  d.item_base = reinterpret_cast<const uint32_t *>(m + o_ib);
+  d.item_query = reinterpret_cast<const uint32_t *>(m + o_iq);
+  d.stage = reinterpret_cast<uint32_t *>(m + o_stage);
+  d.counts = reinterpret_cast<uint32_t *>(m + o_counts);
+  d.excl = reinterpret_cast<uint32_t *>(m + o_excl);
+  d.tiles = reinterpret_cast<uint32_t *>(m + o_tiles);
+  d.head = reinterpret_cast<uint32_t *>(m + o_ctrl);
+  d.total = reinterpret_cast<uint64_t *>(m + o_ctrl + 8);
+  d.start = reinterpret_cast<uint64_t *>(m + o_ctrl + 16);
+  d.qtick = reinterpret_cast<uint64_t *>(m + o_qtick);
+  d.items = uint32_t(items);
+  d.nq = uint32_t(nq);
+  d.ntiles = ntiles;
+  bt->index = ix;
+  bt->nq = nq;
+  bt->results_bound = bound;
+  *out = bt;
+  return S4_OK;
+}
+
+int s4_batch_free(s4_batch *b) {
+  if (!b) return S4_OK;
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  hipError_t e = b->mem ? hipFree(b->mem) : hipSuccess;
+  delete b;
+  if (e != hipSuccess) return hip_fail(e, "hipFree");
+  return S4_OK;
+}
+
+uint64_t s4_batch_results_bound(const s4_batch *b) { return b ? b->results_bound : 0; }
+
+int s4_batch_run(s4_batch *b, uint64_t *d_counts, uint64_t *d_res_offsets, uint32_t *d_results, uint64_t results_cap,
+                 int use_graph, void *stream) {
+  if (!b || !d_counts || !d_res_offsets || (!d_results && b->results_bound))
+    return fail(S4_EINVAL, "null argument");
+  if (results_cap < b->results_bound) return fail(S4_ERANGE, "results_cap below s4_batch_results_bound");
+  int rc = ensure_device();
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  if (!use_graph) return enqueue_batch(b, d_counts, d_res_offsets, d_results, st);
+  const s4_tuning t = tuning();
+  const bool stale = !b->exec || b->g_counts != d_counts || b->g_offs != d_res_offsets ||
+                     b->g_results != d_results || std::memcmp(&b->g_tuning, &t, sizeof t) != 0;
+  if (stale) {
+    drop_graph(b);
+    if (!b->cap_stream) S4_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    S4_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    rc = enqueue_batch(b, d_counts, d_res_offsets, d_results, b->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    b->graph = g;
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(b);
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->g_counts = d_counts;
+    b->g_offs = d_res_offsets;
+    b->g_results = d_results;
+    b->g_tuning = t;
+  }
+  S4_HIP(hipGraphLaunch(b->exec, st));
+  return S4_OK;
+}
+
+int s4_batch_query_ticks(const s4_batch *b, uint64_t *ticks, void *stream) {
+  if (!b || (b->nq && !ticks)) return fail(S4_EINVAL, "null argument");
+  if (!b->nq) return S4_OK;
+  S4_HIP(hipMemcpyAsync(ticks, b->dev.qtick, 8 * b->nq, hipMemcpyDeviceToHost, as_stream(stream)));
+  S4_HIP(hipStreamSynchronize(as_stream(stream)));
+  return S4_OK;
+}
+
+int s4_batch_autotune(s4_batch *b, uint64_t *d_counts, uint64_t *d_res_offsets, uint32_t *d_results,
+                      uint64_t results_cap, int reps, void *stream, s4_tuning *best, double *best_ms) {
+  if (!b || !best) return fail(S4_EINVAL, "null argument");
+  if (reps < 1) reps = 1;
+  hipStream_t st = as_stream(stream);
+  hipEvent_t e0, e1;
+  S4_HIP(hipEventCreate(&e0));
+  S4_HIP(hipEventCreate(&e1));
+  auto measure = [&](const s4_tuning &t, double *ms) -> int {
+    int rc = s4_set_tuning(&t);
+    if (rc) return rc;
+    rc = s4_batch_run(b, d_counts, d_res_offsets, d_results, results_cap, 0, stream);  // warm-up
+    if (rc) return rc;
+    S4_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) {
+      rc = s4_batch_run(b, d_counts, d_res_offsets, d_results, results_cap, 0, stream);
+      if (rc) return rc;
+    }
+    S4_HIP(hipEventRecord(e1, st));
+    S4_HIP(hipEventSynchronize(e1));
+    float f = 0;
+    S4_HIP(hipEventElapsedTime(&f, e0, e1));
+    *ms = double(f) / reps;
+    return S4_OK;
+  };
+  s4_tuning cur = tuning();
+  double cur_ms = 0;
+  int rc = measure(cur, &cur_ms);
+  const std::vector<uint32_t> gallops = {4, 16, 64, 256, 512};
+  const std::vector<uint32_t> waves = {1, 2, 4, 8};
+  const std::vector<uint32_t> groups = {2, 4, 8, 16};
+  const std::vector<uint32_t> grabs = {1, 2, 4};
+  for (int round = 0; round < 2 && rc == S4_OK; ++round) {
+    for (int dim = 0; dim < 4 && rc == S4_OK; ++dim) {
+      const std::vector<uint32_t> &vals = dim == 0 ? gallops : dim == 1 ? waves : dim == 2 ? groups : grabs;
+      for (uint32_t v : vals) {
+        s4_tuning t = cur;
+        (dim == 0 ? t.gallop_blocks : dim == 1 ? t.waves_per_group : dim == 2 ? t.groups_per_cu : t.items_per_grab) = v;
+        if (std::memcmp(&t, &cur, sizeof t) == 0) continue;
+        double ms = 0;
+        rc = measure(t, &ms);
+        if (rc) break;
+        if (ms < cur_ms) {
+          cur = t;
+          cur_ms = ms;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  rc = s4_set_tuning(&cur);
+  if (rc) return rc;
+  *best = cur;
+  if (best_ms) *best_ms = cur_ms;
+  return S4_OK;
+}
+
+}  // extern "C"

@@ -40,7 +40,6 @@ static uint32_t tuning_decode_passes() {
   return (p == 1 || p == 2 || p == 4 || p == 8) ? p : 4u;
 }
 
-static inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Library-owned helper streams (default priority) and events used to fork
 // independent launches off a caller's stream and join them back.
@@ -253,14 +252,21 @@ __global__ void k_spin(uint64_t ticks) {
   while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
 }
 
-// One wave per chunk of r: decode-fused pairwise intersection.  Writes the
-// chunk's matches to stage[128 item ..] and their number to counts[item];
-// chunks past the end of r (its length may live on the device) get 0.
+// Lists of one conjunction passed by value (the shortest first).
+struct ChainArgs {
+  DList f[kMaxTerms];
+  uint32_t nf;  // lists after the short side
+};
+
+// One wave per chunk of r: decode-fused SvS over the chunk.  r is either a
+// compressed list or raw values whose length lives on the device.  Writes
+// the chunk's survivors to stage[128 item ..] and their number to
+// counts[item]; chunks past the end of r get 0.
 template <int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void k_pair(DList rl, const uint32_t *__restrict__ r_raw,
-                                                     const uint64_t *__restrict__ r_len_dev, DList f,
-                                                     uint32_t items_cap, uint32_t *__restrict__ stage,
-                                                     uint32_t *__restrict__ counts, uint32_t gallop_blocks) {
+__global__ __launch_bounds__(WAVES * 64) void k_chain(DList rl, const uint32_t *__restrict__ r_raw,
+                                                      const uint64_t *__restrict__ r_len_dev, ChainArgs args,
+                                                      uint32_t items_cap, uint32_t *__restrict__ stage,
+                                                      uint32_t *__restrict__ counts, uint32_t gallop_blocks) {
   __shared__ ItemLds lds[WAVES];
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t item = blockIdx.x * WAVES + w;
@@ -274,7 +280,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_pair(DList rl, const uint32_t *_
     if (lane_id() == 0) counts[item] = 0;
     return;
   }
-  pair_item(r, f, item, lds[w], stage + uint64_t(item) * kBlock, counts + item, gallop_blocks);
+  const uint32_t cnt = chain_chunk(r, item, [&](uint32_t j) -> const DList & { return args.f[j]; }, args.nf,
+                                   lds[w], gallop_blocks);
+  store_chunk(cnt, lds[w], stage + uint64_t(item) * kBlock, counts + item);
 }
 
 // Exclusive scan of counts[n] in tiles of 1024 (256 threads x 4): local
@@ -348,14 +356,6 @@ __global__ void k_copy_u64(uint64_t *dst, const uint64_t *src) { *dst = *src; }
 
 // ------------------------------------------------------------ arena build
 
-// Parsed streams to be placed in one device arena.
-struct Upload {
-  std::vector<StreamView> views;
-  std::vector<uint64_t> blk_prefix, pay_base, tail_base;
-  uint64_t total_blocks = 0, total_words = 0, total_tail = 0;
-  ArenaLayout lay;
-};
-
 static void plan_arena(Upload &u) {
   const size_t L = u.views.size();
   u.blk_prefix.assign(L + 1, 0);
@@ -405,7 +405,7 @@ static DList make_desc(const Upload &u, size_t i, char *base) {
 
 // Copy the parsed streams into a new device arena and build the skip
 // index.  Synchronous with respect to `stream` only through the staging copy.
-static int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DList> *descs) {
+int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DList> *descs) {
   int rc = ensure_device();
   if (rc) return rc;
   plan_arena(u);
@@ -499,33 +499,46 @@ static size_t pair_scratch_layout(uint64_t cap_r, char *base, PairScratch *ps) {
 }
 
 template <int WAVES>
-static void launch_pair_w(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const DList &f,
-                          const PairScratch &ps, hipStream_t stream) {
+static void launch_chain_w(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const ChainArgs &args,
+                           const PairScratch &ps, hipStream_t stream) {
   const uint32_t groups = std::max<uint32_t>(1, (ps.items_cap + WAVES - 1) / WAVES);
-  hipLaunchKernelGGL(k_pair<WAVES>, dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len, f, ps.items_cap,
+  hipLaunchKernelGGL(k_chain<WAVES>, dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len, args, ps.items_cap,
                      ps.stage, ps.counts, std::min(tuning().gallop_blocks, kMaxGallopBlocks));
 }
 
-// match -> tile scan -> top scan -> ordered compaction; count to d_count.
-static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const DList &f,
-                    const PairScratch &ps, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
+// chunk kernel -> tile scan -> top scan -> ordered compaction; count to d_count.
+static int run_chain(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const ChainArgs &args,
+                     const PairScratch &ps, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
   if (ps.items_cap == 0) {
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, stream, d_count, uint64_t(0));
     S4_HIP(hipGetLastError());
     return S4_OK;
   }
   switch (tuning().waves_per_group) {
-    case 1: launch_pair_w<1>(r, r_raw, r_len, f, ps, stream); break;
-    case 2: launch_pair_w<2>(r, r_raw, r_len, f, ps, stream); break;
-    case 8: launch_pair_w<8>(r, r_raw, r_len, f, ps, stream); break;
-    default: launch_pair_w<4>(r, r_raw, r_len, f, ps, stream); break;
+    case 1: launch_chain_w<1>(r, r_raw, r_len, args, ps, stream); break;
+    case 2: launch_chain_w<2>(r, r_raw, r_len, args, ps, stream); break;
+    case 8: launch_chain_w<8>(r, r_raw, r_len, args, ps, stream); break;
+    default: launch_chain_w<4>(r, r_raw, r_len, args, ps, stream); break;
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3(ps.ntiles), dim3(256), 0, stream, ps.counts, ps.items_cap, ps.excl, ps.tiles);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, stream, ps.tiles, ps.ntiles, d_count);
-  hipLaunchKernelGGL(k_compact, dim3((ps.items_cap + 3) / 4), dim3(256), 0, stream, ps.stage, ps.counts, ps.excl,
-                     ps.tiles, ps.items_cap, d_out);
+  S4_HIP(hipGetLastError());
+  return scan_and_compact(ps.stage, ps.counts, ps.items_cap, ps.excl, ps.tiles, ps.ntiles, d_count, d_out, stream);
+}
+
+int scan_and_compact(const uint32_t *stage, const uint32_t *counts, uint32_t n, uint32_t *excl, uint32_t *tiles,
+                     uint32_t ntiles, uint64_t *total, uint32_t *out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_scan_tiles, dim3(std::max<uint32_t>(1, ntiles)), dim3(256), 0, stream, counts, n, excl, tiles);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, stream, tiles, ntiles, total);
+  if (n) hipLaunchKernelGGL(k_compact, dim3((n + 3) / 4), dim3(256), 0, stream, stage, counts, excl, tiles, n, out);
   S4_HIP(hipGetLastError());
   return S4_OK;
+}
+
+static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const DList &f,
+                    const PairScratch &ps, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
+  ChainArgs args;
+  args.f[0] = f;
+  args.nf = 1;
+  return run_chain(r, r_raw, r_len, args, ps, d_out, d_count, stream);
 }
 
 template <int P>
@@ -864,39 +877,19 @@ int s4_intersect_raw(const uint32_t *d_r, const uint64_t *d_len_r, uint64_t cap_
   return run_pair(none, d_r, d_len_r, f->d, ps, d_out, d_count, as_stream(stream));
 }
 
-// SvS chain scratch: two intermediates of len_min values, two device
-// counters, and the pair scratch for len_min.
-static size_t chain_layout(uint64_t len_min, char *base, uint32_t **ping, uint32_t **pong, uint64_t **cnt,
-                           char **pair_base) {
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off = align_up(off + bytes, 256);
-    return o;
-  };
-  size_t p0 = take(4 * len_min), p1 = take(4 * len_min), c = take(16), pb = off;
-  off += pair_scratch_layout(len_min, nullptr, nullptr);
-  if (base) {
-    *ping = reinterpret_cast<uint32_t *>(base + p0);
-    *pong = reinterpret_cast<uint32_t *>(base + p1);
-    *cnt = reinterpret_cast<uint64_t *>(base + c);
-    *pair_base = base + pb;
-  }
-  return off;
-}
-
 size_t s4_intersect_k_scratch_bytes(const s4_list *const *lists, uint32_t k) {
   if (!lists || k == 0) return 0;
   uint64_t m = UINT64_MAX;
   for (uint32_t i = 0; i < k; ++i)
     if (lists[i]) m = std::min(m, lists[i]->n);
   if (m == UINT64_MAX) return 0;
-  return chain_layout(m, nullptr, nullptr, nullptr, nullptr, nullptr);
+  return pair_scratch_layout(m, nullptr, nullptr);
 }
 
 int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
                    void *d_scratch, size_t scratch_bytes, void *stream) {
   if (!lists || k == 0 || !d_count) return fail(S4_EINVAL, "s4_intersect_k: need k >= 1 lists and d_count");
+  if (k > kMaxTerms + 1) return fail(S4_EINVAL, "s4_intersect_k: at most 33 lists");
   std::vector<const s4_list *> ord(lists, lists + k);
   for (auto *l : ord)
     if (!l) return fail(S4_EINVAL, "null list");
@@ -920,32 +913,14 @@ int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uin
   }
   for (auto *l : ord)
     if (!(l->flags & 1u)) return fail(S4_EUNSORTED, "intersection inputs must be strictly increasing");
-  const size_t need = chain_layout(m, nullptr, nullptr, nullptr, nullptr, nullptr);
+  const size_t need = pair_scratch_layout(m, nullptr, nullptr);
   if (scratch_bytes < need || !d_scratch) return fail(S4_ERANGE, "scratch too small");
-  uint32_t *ping, *pong;
-  uint64_t *cnt;
-  char *pair_base;
-  chain_layout(m, static_cast<char *>(d_scratch), &ping, &pong, &cnt, &pair_base);
   PairScratch ps;
-  pair_scratch_layout(m, pair_base, &ps);
-  // level 0: both compressed
-  uint32_t *dst = (k == 2) ? d_out : ping;
-  uint64_t *dcnt = (k == 2) ? d_count : cnt;
-  rc = run_pair(ord[0]->d, nullptr, nullptr, ord[1]->d, ps, dst, dcnt, st);
-  if (rc) return rc;
-  uint32_t *cur = ping, *nxt = pong;
-  uint64_t *cur_cnt = cnt, *nxt_cnt = cnt + 1;
-  for (uint32_t i = 2; i < k; ++i) {
-    const bool last = (i == k - 1);
-    uint32_t *o = last ? d_out : nxt;
-    uint64_t *oc = last ? d_count : nxt_cnt;
-    DList none{};
-    rc = run_pair(none, cur, cur_cnt, ord[i]->d, ps, o, oc, st);
-    if (rc) return rc;
-    std::swap(cur, nxt);
-    std::swap(cur_cnt, nxt_cnt);
-  }
-  return S4_OK;
+  pair_scratch_layout(m, static_cast<char *>(d_scratch), &ps);
+  ChainArgs args;
+  args.nf = k - 1;
+  for (uint32_t i = 1; i < k; ++i) args.f[i - 1] = ord[i]->d;
+  return run_chain(ord[0]->d, nullptr, nullptr, args, ps, d_out, d_count, st);
 }
 
 }  // extern "C"

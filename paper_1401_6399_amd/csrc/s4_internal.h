@@ -18,6 +18,7 @@ constexpr uint32_t kHeaderBytes = 32;
 constexpr uint32_t kBlock = 128;          // integers per block (Sec. 4.3)
 constexpr uint32_t kPayloadPadBytes = 64; // lets extraction read 3 rows past any block
 constexpr uint32_t kMaxGallopBlocks = 512;
+constexpr uint32_t kMaxTerms = 32;  // lists after the shortest one in a conjunction
 
 // Device view of one list: structure of arrays in HBM.
 struct DList {
@@ -67,6 +68,46 @@ struct ArenaLayout {
          desc_off = 0, blkpre_off = 0, total = 0;
 };
 
+// Parsed streams to be placed in one device arena.
+struct Upload {
+  std::vector<StreamView> views;
+  std::vector<uint64_t> blk_prefix, pay_base, tail_base;
+  uint64_t total_blocks = 0, total_words = 0, total_tail = 0;
+  ArenaLayout lay;
+};
+
+// Copy parsed streams into a new device arena (descriptor table at
+// lay.desc_off) and build the skip index on `stream`.
+int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DList> *descs);
+// Decode blocks [first, first + count) of L into d_out (index nb = tail).
+int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream);
+// Exclusive scan of counts[n] (tiles of 1024), grand total to *total, then
+// ordered gather of stage[128 i .. 128 i + counts[i]) into out.
+int scan_and_compact(const uint32_t *stage, const uint32_t *counts, uint32_t n, uint32_t *excl, uint32_t *tiles,
+                     uint32_t ntiles, uint64_t *total, uint32_t *out, hipStream_t stream);
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Device tables of a batch of conjunctive queries (planned on the host).
+struct BatchDev {
+  const DList *lists;         // index descriptors
+  const uint32_t *sterms;     // terms of every query, shortest list first
+  const uint32_t *qoff;       // [nq + 1] term offsets
+  const uint32_t *item_base;  // [nq + 1] first chunk of each query
+  const uint32_t *item_query; // [items] query of each chunk
+  uint32_t *stage;            // [items * 128] survivors of each chunk
+  uint32_t *counts;           // [items]
+  uint32_t *excl;             // [items]
+  uint32_t *tiles;            // [ntiles + 1]
+  uint32_t *head;             // work-queue head
+  uint64_t *total;            // number of results
+  uint64_t *start;            // device clock at the start of the run
+  uint64_t *qtick;            // [nq] completion time of each query
+  uint32_t items, nq, ntiles;
+};
+// Enqueue one run of a batch on st: persistent chunk kernel, scan,
+// compaction into d_results, per-query counts / CSR offsets.
+int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st);
+
 }  // namespace s4
 
 struct s4_list {
@@ -81,7 +122,7 @@ struct s4_index {
   void *arena = nullptr;
   uint64_t count = 0, total_ints = 0, payload_bytes = 0, index_bytes = 0;
   std::vector<s4::DList> lists;    // host copy of the descriptors
-  std::vector<uint64_t> lengths;
+  std::vector<uint64_t> lengths, pw;
   std::vector<uint32_t> flags;
   const s4::DList *d_lists = nullptr;  // device copy
 };

@@ -193,18 +193,14 @@ struct RSide {
   uint64_t len;         // number of values of r
 };
 
-// Intersect chunk `item` of r (values 128 item .. 128 item + 127) with f.
-// Matches are written in increasing order to out[0 ..], their number to
-// *count.  The whole wave calls this with the same arguments.
-__device__ __forceinline__ void pair_item(const RSide &r, const DList &f, uint32_t item, ItemLds &s,
-                                          uint32_t *__restrict__ out, uint32_t *__restrict__ count,
-                                          uint32_t gallop_blocks) {
+// Load chunk `item` of r (values 128 item .. 128 item + 127) into s.r;
+// returns how many values it has.  The whole wave calls this.
+__device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, ItemLds &s) {
   const uint32_t lane = lane_id();
-  // ---- the chunk of r
   uint32_t cnt;
   if (r.raw) {
     const uint64_t base = uint64_t(item) * kBlock;
-    const uint64_t left = r.len - base;
+    const uint64_t left = r.len > base ? r.len - base : 0;
     cnt = left < kBlock ? uint32_t(left) : kBlock;
     if (lane < cnt) s.r[lane] = r.raw[base + lane];
     if (lane + 64 < cnt) s.r[lane + 64] = r.raw[base + 64 + lane];
@@ -212,19 +208,28 @@ __device__ __forceinline__ void pair_item(const RSide &r, const DList &f, uint32
     cnt = kBlock;
     decode_block_wave(r.L, item, s.r);
   } else {
-    cnt = r.L.t;
+    cnt = item == r.L.nb ? r.L.t : 0u;
     if (lane < cnt) s.r[lane] = r.L.tail[lane];
     if (lane + 64 < cnt) s.r[lane + 64] = r.L.tail[lane + 64];
   }
   wave_sync();
+  return cnt;
+}
+
+// Intersect the sorted values s.r[0 .. cnt) with list f; the values found
+// in f are compacted in order to the front of s.r and their number is
+// returned (uniform).  Only candidate blocks of f are decoded: for every
+// value the first block whose bmax is >= the value (Sec. 6: the search of
+// the long list for each value of the short one, done here per lane over
+// the skip index), each distinct candidate once.
+__device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f, ItemLds &s,
+                                                    uint32_t gallop_blocks) {
+  const uint32_t lane = lane_id();
   const bool v0 = lane < cnt, v1 = lane + 64 < cnt;
   const uint32_t a0 = v0 ? s.r[lane] : 0u;
   const uint32_t a1 = v1 ? s.r[lane + 64] : 0u;
   const uint32_t first = uniform(s.r[0]);
   const uint32_t last = uniform(s.r[cnt ? cnt - 1 : 0]);
-
-  // ---- span of f blocks that can hold [first, last]; index nb stands for
-  // the raw tail (bmax taken as +infinity there)
   const uint32_t nbf = f.nb;
   const bool ftail = f.t > 0;
   uint32_t fmax = 0;
@@ -232,23 +237,26 @@ __device__ __forceinline__ void pair_item(const RSide &r, const DList &f, uint32
   const bool any = cnt > 0 && f.n > 0 && first <= fmax;
   bool f0 = false, f1 = false;
   if (any) {
+    // span of f blocks that can hold [first, last]; index nb stands for the
+    // raw tail (bmax taken as +infinity there)
     const uint32_t lo = uniform(lower_bound_u32(f.bmax, 0, nbf, first));
     const uint32_t hi = uniform(lower_bound_u32(f.bmax, lo, nbf, last));
     const uint32_t span = hi - lo + 1;
-    // ---- candidate block of each value: first c in [lo, hi] with bmax[c] >= a
     uint32_t c0, c1;
     if (span <= gallop_blocks) {
+      // merge regime: stage the spanned bmax entries in LDS, search there
       for (uint32_t e = lane; e < span; e += 64) s.bm[e] = (lo + e < nbf) ? f.bmax[lo + e] : kInvalid;
       wave_sync();
       c0 = lo + lower_bound_u32(s.bm, 0, span - 1, a0);
       c1 = lo + lower_bound_u32(s.bm, 0, span - 1, a1);
     } else {
+      // galloping regime: each lane searches the skip index in memory
       c0 = lower_bound_u32(f.bmax, lo, hi, a0);
       c1 = lower_bound_u32(f.bmax, lo, hi, a1);
     }
     const bool ok0 = v0 && a0 <= fmax;
     const bool ok1 = v1 && a1 <= fmax;
-    // ---- distinct candidates (c is non-decreasing over the chunk)
+    // distinct candidates (c is non-decreasing over the chunk)
     uint32_t p0 = __shfl_up(c0, 1);
     uint32_t p1 = __shfl_up(c1, 1);
     const uint32_t c0_last = __shfl(c0, 63);
@@ -263,7 +271,7 @@ __device__ __forceinline__ void pair_item(const RSide &r, const DList &f, uint32
     const uint32_t slot0 = ok0 ? mbcnt64(m0) + (n0 ? 1u : 0u) - 1u : kInvalid;
     const uint32_t slot1 = ok1 ? u0 + mbcnt64(m1) + (n1 ? 1u : 0u) - 1u : kInvalid;
     wave_sync();
-    // ---- decode candidate blocks four at a time (one row each) and search
+    // decode candidate blocks four at a time (one row each) and search
     const uint32_t row = lane >> 4, ri = lane & 15u;
     for (uint32_t g = 0; g < U; g += 4) {
       const uint32_t cs = g + row;
@@ -293,12 +301,35 @@ __device__ __forceinline__ void pair_item(const RSide &r, const DList &f, uint32
       wave_sync();
     }
   }
-  // ---- ordered compaction of the matches (ballot + mbcnt)
+  // ordered compaction of the survivors (ballot + mbcnt), in place
   const uint64_t mm0 = __ballot(f0), mm1 = __ballot(f1);
   const uint32_t k0 = uint32_t(__popcll(mm0));
-  if (f0) out[mbcnt64(mm0)] = a0;
-  if (f1) out[k0 + mbcnt64(mm1)] = a1;
-  if (lane == 0) *count = k0 + uint32_t(__popcll(mm1));
+  wave_sync();
+  if (f0) s.r[mbcnt64(mm0)] = a0;
+  if (f1) s.r[k0 + mbcnt64(mm1)] = a1;
+  wave_sync();
+  return k0 + uint32_t(__popcll(mm1));
+}
+
+// Write s.r[0 .. cnt) to out and cnt to *count.
+__device__ __forceinline__ void store_chunk(uint32_t cnt, const ItemLds &s, uint32_t *__restrict__ out,
+                                            uint32_t *__restrict__ count) {
+  const uint32_t lane = lane_id();
+  if (lane < cnt) out[lane] = s.r[lane];
+  if (lane + 64 < cnt) out[lane + 64] = s.r[lane + 64];
+  if (lane == 0) *count = cnt;
+}
+
+// SvS over one chunk: intersect chunk `item` of r with lists f[0 .. nf) in
+// order, stopping early when nothing survives (Sec. 6: "intersect them
+// two-by-two, starting with the smallest").  Intersection distributes over
+// a partition of the shortest list, so chunks are independent.
+template <class FList>
+__device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, FList f, uint32_t nf, ItemLds &s,
+                                                uint32_t gallop_blocks) {
+  uint32_t cnt = load_chunk(r, item, s);
+  for (uint32_t j = 0; j < nf && cnt > 0; ++j) cnt = intersect_chunk(cnt, f(j), s, gallop_blocks);
+  return cnt;
 }
 
 }  // namespace s4
