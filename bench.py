@@ -47,7 +47,14 @@ def parse():
     ap.add_argument("--nstreams", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--cpu-passes", type=int, default=2)
+    ap.add_argument("--cpu-passes", type=int, default=16)
+    ap.add_argument("--decode-only", action="store_true", help="skip the batched and CPU legs (for profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB three times with a plain copy kernel (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs into profiles/decode_traffic.json")
+    ap.add_argument("--calib-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="rocprofv3 CSVs of --calibrate-copy, for the counter scale factors")
     ap.add_argument("--batch-queries", type=int, default=1 << 18)
     ap.add_argument("--plain-sample", type=int, default=4096)
     return ap.parse_args()
@@ -194,8 +201,66 @@ def batched(s4, workloads, torch, nq, plain_sample):
     return out
 
 
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("s4_kernels.h", "s4_device.hip"):
+        with open(os.path.join(ROOT, "paper_1401_6399_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_values(path, kernel_substr, counter):
+    import csv
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter:
+                out.append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic_json(args):
+    """Per-launch HBM traffic of the decode kernel from two counter passes,
+    scaled by what the same counters read for a copy of 1 GiB."""
+    import numpy as np
+    one_gib_kib = float(1 << 20)
+    cf = np.mean(pmc_values(args.calib_from[0], "copyBuffer", "FETCH_SIZE"))
+    cw = np.mean(pmc_values(args.calib_from[1], "copyBuffer", "WRITE_SIZE"))
+    sf, sw = one_gib_kib / cf, one_gib_kib / cw
+    fetch = np.array(pmc_values(args.traffic_from[0], "k_decode<", "FETCH_SIZE"))
+    write = np.array(pmc_values(args.traffic_from[1], "k_decode<", "WRITE_SIZE"))
+    n = min(fetch.size, write.size)
+    per_launch = float((fetch[:n].mean() * sf + write[:n].mean() * sw) * 1024.0)
+    res = {"bytes_per_launch": round(per_launch, 1), "launches": int(n),
+           "fetch_kib_per_launch": round(float(fetch[:n].mean()), 2),
+           "write_kib_per_launch": round(float(write[:n].mean()), 2),
+           "fetch_scale": round(float(sf), 4), "write_scale": round(float(sw), 4),
+           "kernel_source_sha": kernel_source_sha()}
+    path = os.path.join(ROOT, "profiles", "decode_traffic.json")
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+def calibrate_copy():
+    import torch
+    torch.cuda.set_device(0)
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copied_bytes": 4 * n, "times": 3}))
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        return traffic_json(args)
+    if args.calibrate_copy:
+        return calibrate_copy()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
                                    "and not implemented", "n_gpus": args.gpus}))
@@ -245,11 +310,15 @@ def main():
             raise SystemExit(f"decoded list {i} differs from its input")
         p += (l.n + 63) // 64 * 64 + 64
 
+    # counter-measured HBM bytes per launch, valid only for the kernel
+    # source the counters were taken on
     traffic = None
     tf = os.path.join(ROOT, "profiles", "decode_traffic.json")
     if os.path.exists(tf):
         with open(tf) as f:
-            traffic = json.load(f).get("bytes_per_launch")
+            tj = json.load(f)
+        if tj.get("kernel_source_sha") == kernel_source_sha():
+            traffic = tj.get("bytes_per_launch")
 
     result = {
         "metric": METRIC,
@@ -289,12 +358,12 @@ def main():
         "whole_job_hbm_frac": round(abytes.sum() / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "paper_context": "0.7 cycles/int, 5.4 Gint/s: Xeon E5-1620 3.6 GHz, 1 thread, cache-resident",
     }
-    if not args.no_batched:
+    if not args.no_batched and not args.decode_only:
         try:
             result["batched"] = batched(s4, workloads, torch, args.batch_queries, args.plain_sample)
         except Exception as ex:  # reported, never hidden
             result["batched"] = {"error": str(ex)}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.decode_only:
         result["cpu_baseline"] = cpu_baseline(flat, offs, args.cpu_passes)
     print(json.dumps(result), flush=True)
 
