@@ -53,6 +53,12 @@ def parse():
                     help="only copy 1 GiB three times with a plain copy kernel (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs into profiles/decode_traffic.json")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the serving workload instead (index of 2^20 lists, Poisson arrivals at 3 levels)")
+    ap.add_argument("--serve-queries", type=int, default=1 << 16)
+    ap.add_argument("--serve-lists", type=int, default=1 << 20)
+    ap.add_argument("--serve-check", type=int, default=1 << 12,
+                    help="queries per level checked against the oracle (0: none)")
     ap.add_argument("--calib-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="rocprofv3 CSVs of --calibrate-copy, for the counter scale factors")
     ap.add_argument("--batch-queries", type=int, default=1 << 18)
@@ -255,8 +261,78 @@ def calibrate_copy():
     print(json.dumps({"copied_bytes": 4 * n, "times": 3}))
 
 
+def serving(args):
+    """Serving workload: device-resident index of 2^20 clustered lists over
+    [0, 2^31) (length max(128, 2^28 / (t + 1))), 2..8-term queries, open-loop
+    Poisson arrivals at 0.5, 0.8 and 0.95 of the saturated rate."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1401_6399_amd as s4
+
+    s4.require_library()
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    nl = args.serve_lists
+    lens = workloads.index_lengths(nl, 28 - (20 - nl.bit_length() + 1))
+    kinds = np.full(nl, workloads.CLUSTERED, dtype=np.int32)
+    flat, offs = workloads.lists(kinds, lens, workloads.config_seed(4, 0), 1 << 31)
+    log(f"serving index: {nl} lists, {int(offs[-1])} ints generated in {time.time() - t0:.1f} s")
+    buf, soffs = s4.encode_many(flat, offs)
+    ix = s4.Index(buf, soffs)
+    del buf, soffs
+    log(f"index resident: {ix.payload_bytes / 2**30:.2f} GiB payload + {ix.index_bytes / 2**30:.2f} GiB skip "
+        f"index, {8 * ix.payload_bytes / ix.total_ints:.2f} bits/int; built in {time.time() - t0:.1f} s")
+    srv = s4.Server(ix, max_slots=1 << 15, pool_bytes=24 << 30, result_bytes=3 << 28, max_terms=8)
+    nq = args.serve_queries
+    terms, qoffs = workloads.serving_queries(ix.lengths, nq, level=0)
+    sat = srv.replay(terms, qoffs, np.zeros(nq, np.uint64))
+    qstar = nq / sat["elapsed_s"]
+    log(f"saturated: {qstar:.0f} queries/s over {nq} queries")
+    levels = []
+    for lv, frac in enumerate((0.5, 0.8, 0.95)):
+        terms, qoffs = workloads.serving_queries(ix.lengths, nq, level=lv + 1)
+        arr = (workloads.arrivals(workloads.config_seed(4, 20 + lv), frac * qstar, nq) * 1e9).astype(np.uint64)
+        chk = args.serve_check > 0
+        r = srv.replay(terms, qoffs, arr, with_results=chk, results_cap=1 << 28)
+        lat = r["latency_ns"].astype(np.float64) / 1e3
+        span = (float(arr[-1]) / 1e9) if nq else 0.0
+        lev = {"offered_qps": round(frac * qstar, 1), "achieved_qps": round(nq / max(r["elapsed_s"], 1e-9), 1),
+               "queries": nq, "trace_s": round(span, 3),
+               "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
+               "p999_us": round(float(np.percentile(lat, 99.9)), 1)}
+        if chk:
+            import oracle
+            rng = np.random.default_rng(lv)
+            sample = rng.choice(nq, size=min(args.serve_check, nq), replace=False)
+            bad = 0
+            for q in sample:
+                ts = sorted(terms[int(qoffs[q]): int(qoffs[q + 1])], key=lambda t: int(lens[t]))
+                want = oracle.intersect_k([flat[int(offs[t]): int(offs[t + 1])] for t in ts])
+                got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
+                bad += not np.array_equal(got, want)
+            lev["oracle_checked"] = int(sample.size)
+            lev["oracle_mismatches"] = int(bad)
+        levels.append(lev)
+        log(f"level {lv}: {lev}")
+    st = srv.stats()
+    srv.close()
+    print(json.dumps({"metric": "served queries/s + p50/p99/p999 latency", "unit": "queries/s",
+                      "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": f"serving: {nl} clustered lists over [0,2^31), "
+                                             f"{int(offs[-1])} ints, 2..8-term queries, sqrt(len) term sampling, "
+                                             "open-loop Poisson arrivals", "queries_per_level": nq},
+                      "saturated_qps": round(qstar, 1), "levels": levels,
+                      "index": {"payload_gib": round(ix.payload_bytes / 2**30, 3),
+                                "skip_index_gib": round(ix.index_bytes / 2**30, 3),
+                                "bits_per_int": round(8 * ix.payload_bytes / ix.total_ints, 3)},
+                      "server_stats": st}), flush=True)
+
+
 def main():
     args = parse()
+    if args.serve:
+        return serving(args)
     if args.traffic_from:
         return traffic_json(args)
     if args.calibrate_copy:

@@ -274,8 +274,10 @@ int s4_batch_autotune(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offse
 typedef struct s4_server s4_server;
 typedef struct {
   uint32_t max_slots;       /* concurrent queries on the device */
-  uint64_t pool_bytes;      /* intermediate memory for admitted queries */
-  uint64_t result_bytes;    /* device memory for results of one iteration */
+  uint64_t pool_bytes;      /* device memory for admitted queries' chunk results (split over
+                               the in-flight iterations; each query needs 512 bytes per
+                               128-value chunk of its shortest list) */
+  uint64_t result_bytes;    /* pinned host memory for results in flight (0: 64 MiB) */
   uint32_t max_terms;       /* longest query accepted */
 } s4_server_config;
 
@@ -302,6 +304,20 @@ typedef struct {
 int s4_server_stats_get(const s4_server *srv, s4_server_stats *st);
 /* Stop accepting, finish every admitted query, join the dispatcher. */
 int s4_server_destroy(s4_server *srv);
+
+/* Benchmarking aid: replay an open-loop arrival trace.  Query q (host terms
+ * h_terms[h_q_offsets[q] .. h_q_offsets[q+1])) is submitted h_arrival_ns[q]
+ * nanoseconds after the call starts (non-decreasing; the host spins on its
+ * steady clock), whatever the state of earlier queries; completions are
+ * drained concurrently.  latency_ns[q] receives the time from the scheduled
+ * arrival to the result on the host, counts[q] the result size; when
+ * results is not null, result q is copied to results + res_offsets[q]
+ * (res_offsets has nq + 1 entries) if everything fits results_cap.  Returns
+ * S4_ERANGE after timeout_s seconds without every result; *elapsed_s
+ * receives the wall time from the first arrival to the last result. */
+int s4_server_replay(s4_server *srv, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
+                     const uint64_t *h_arrival_ns, uint64_t *latency_ns, uint64_t *counts, uint32_t *results,
+                     uint64_t results_cap, uint64_t *res_offsets, double timeout_s, double *elapsed_s);
 
 #ifdef __cplusplus
 }

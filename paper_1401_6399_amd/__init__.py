@@ -97,6 +97,8 @@ SIGNATURES = {
     "s4_server_poll": (_i, [_vp, _u64p, _u64p, _u64p, _u32p, _u64, _u64p, _u32, _u32p]),
     "s4_server_stats_get": (_i, [_vp, ctypes.POINTER(ServerStats)]),
     "s4_server_destroy": (_i, [_vp]),
+    "s4_server_replay": (_i, [_vp, _u32p, _u64p, _u64, _u64p, _u64p, _u64p, _u32p, _u64, _u64p,
+                              ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -521,6 +523,29 @@ class Server:
         out = []
         for i in range(d):
             out.append((int(ids[i]), res[int(roffs[i]): int(roffs[i + 1])].copy(), int(lat[i])))
+        return out
+
+    def replay(self, terms, q_offsets, arrival_ns, with_results=False, results_cap=1 << 26, timeout_s=600.0):
+        """Open-loop replay of an arrival trace (s4_server_replay)."""
+        terms = np.ascontiguousarray(terms, dtype=np.uint32)
+        q_offsets = np.ascontiguousarray(q_offsets, dtype=np.uint64)
+        arrival_ns = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+        nq = q_offsets.size - 1
+        lat = np.zeros(max(1, nq), np.uint64)
+        counts = np.zeros(max(1, nq), np.uint64)
+        res = np.zeros(results_cap if with_results else 1, np.uint32)
+        roffs = np.zeros(nq + 1, np.uint64)
+        el = ctypes.c_double(0)
+        _check(require_library().s4_server_replay(
+            self.h, _ptr(terms if terms.size else np.zeros(1, np.uint32), ctypes.c_uint32),
+            _ptr(q_offsets, ctypes.c_uint64), nq, _ptr(arrival_ns, ctypes.c_uint64), _ptr(lat, ctypes.c_uint64),
+            _ptr(counts, ctypes.c_uint64), _ptr(res, ctypes.c_uint32) if with_results else None,
+            results_cap if with_results else 0, _ptr(roffs, ctypes.c_uint64), timeout_s, ctypes.byref(el)),
+            "s4_server_replay")
+        out = {"latency_ns": lat[:nq], "counts": counts[:nq], "elapsed_s": el.value}
+        if with_results:
+            out["results"] = res
+            out["res_offsets"] = roffs
         return out
 
     def stats(self):

@@ -15,8 +15,9 @@
 //      chunk kernel + scan + compaction) on that context's stream.
 // Queries that arrive while earlier ones run on the device are admitted into
 // the next free context and launched at once, so iterations overlap on the
-// device.  Results are written by the compaction kernel straight into
-// pinned, device-mapped host memory.
+// device.  Per-query counts and offsets are written by the device straight
+// into pinned, device-mapped host memory; the results themselves are copied
+// back with one asynchronous copy of exactly their total size.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -25,6 +26,7 @@
 #include <deque>
 #include <mutex>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "s4_internal.h"
@@ -53,12 +55,13 @@ struct Context {
   s4::BatchDev dev{};
   // pinned host: tables (uploaded) and outputs (written by the device)
   uint32_t *h_sterms = nullptr, *h_qoff = nullptr, *h_ib = nullptr, *h_iq = nullptr;
-  uint32_t *h_results = nullptr;
-  uint64_t *h_counts = nullptr, *h_offs = nullptr;
-  uint32_t *d_results = nullptr;
-  uint64_t *d_counts = nullptr, *d_offs = nullptr;
+  uint32_t *h_results = nullptr;  // pinned, results_per_ctx values
+  uint64_t *h_counts = nullptr, *h_offs = nullptr;  // pinned, device-mapped
+  uint32_t *d_results = nullptr;  // device, one value per staged slot
+  uint64_t *d_counts = nullptr, *d_offs = nullptr;  // device views of h_counts / h_offs
   std::vector<Query> queries;
   bool busy = false;
+  int phase = 0;  // 1: kernels running, 2: results copy running
   uint64_t reserved_stage = 0;
 };
 
@@ -73,6 +76,7 @@ struct s4_server {
   std::condition_variable cv;
   std::deque<Query> waiting;
   std::deque<Done> completed;
+  std::deque<Clock::time_point> completed_at;
   std::atomic<bool> stop{false};
   std::thread worker;
   int device = 0;
@@ -99,7 +103,7 @@ int alloc_context(s4_server *s, Context &c) {
   const size_t o_sterms = take(4 * nt), o_qoff = take(4 * (nq + 1)), o_ib = take(4 * (nq + 1)),
                o_iq = take(4 * items), o_stage = take(4 * s4::kBlock * items), o_counts = take(4 * items),
                o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)), o_ctrl = take(64),
-               o_qtick = take(8 * nq);
+               o_qtick = take(8 * nq), o_res = take(4 * s4::kBlock * items);
   if (hipMalloc(&c.dmem, off) != hipSuccess) return s4::fail(S4_ENOMEM, "server context: device allocation failed");
   char *m = static_cast<char *>(c.dmem);
   s4::BatchDev &d = c.dev;
@@ -116,6 +120,7 @@ int alloc_context(s4_server *s, Context &c) {
   d.total = reinterpret_cast<uint64_t *>(m + o_ctrl + 8);
   d.start = reinterpret_cast<uint64_t *>(m + o_ctrl + 16);
   d.qtick = reinterpret_cast<uint64_t *>(m + o_qtick);
+  c.d_results = reinterpret_cast<uint32_t *>(m + o_res);
   auto hmalloc = [&](void **p, size_t bytes, unsigned flags) {
     return hipHostMalloc(p, std::max<size_t>(bytes, 64), flags) == hipSuccess;
   };
@@ -123,11 +128,10 @@ int alloc_context(s4_server *s, Context &c) {
             hmalloc(reinterpret_cast<void **>(&c.h_qoff), 4 * (nq + 1), hipHostMallocDefault) &&
             hmalloc(reinterpret_cast<void **>(&c.h_ib), 4 * (nq + 1), hipHostMallocDefault) &&
             hmalloc(reinterpret_cast<void **>(&c.h_iq), 4 * items, hipHostMallocDefault) &&
-            hmalloc(reinterpret_cast<void **>(&c.h_results), 4 * s->results_per_ctx, hipHostMallocMapped) &&
+            hmalloc(reinterpret_cast<void **>(&c.h_results), 4 * s->results_per_ctx, hipHostMallocDefault) &&
             hmalloc(reinterpret_cast<void **>(&c.h_counts), 8 * nq, hipHostMallocMapped) &&
             hmalloc(reinterpret_cast<void **>(&c.h_offs), 8 * (nq + 1), hipHostMallocMapped);
   if (!ok) return s4::fail(S4_ENOMEM, "server context: pinned host allocation failed");
-  S4_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&c.d_results), c.h_results, 0));
   S4_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&c.d_counts), c.h_counts, 0));
   S4_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&c.d_offs), c.h_offs, 0));
   return S4_OK;
@@ -174,11 +178,29 @@ int launch_context(s4_server *s, Context &c) {
   if (rc) return rc;
   S4_HIP(hipEventRecord(c.done, c.stream));
   c.busy = true;
+  c.phase = 1;
   return S4_OK;
 }
 
+// Kernels done: copy exactly the results back (asynchronously when they
+// fit the pinned buffer).  Returns true when the context can retire now.
+bool start_copy(s4_server *s, Context &c, std::vector<uint32_t> *spill) {
+  const uint64_t total = c.h_offs[c.queries.size()];
+  if (total == 0) return true;
+  if (total <= s->results_per_ctx) {
+    if (hipMemcpyAsync(c.h_results, c.d_results, 4 * total, hipMemcpyDeviceToHost, c.stream) == hipSuccess &&
+        hipEventRecord(c.done, c.stream) == hipSuccess) {
+      c.phase = 2;
+      return false;
+    }
+  }
+  spill->resize(total);
+  (void)hipMemcpy(spill->data(), c.d_results, 4 * total, hipMemcpyDeviceToHost);
+  return true;
+}
+
 // Move a finished context's results to the completed queue.
-void retire_context(s4_server *s, Context &c) {
+void retire_context(s4_server *s, Context &c, const uint32_t *res) {
   const auto now = Clock::now();
   std::vector<Done> out;
   out.reserve(c.queries.size());
@@ -188,17 +210,21 @@ void retire_context(s4_server *s, Context &c) {
     d.id = c.queries[q].id;
     d.count = cnt;
     d.latency_ns = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(now - c.queries[q].submitted).count());
-    d.result.assign(c.h_results + o0, c.h_results + o0 + cnt);
+    d.result.assign(res + o0, res + o0 + cnt);
     out.push_back(std::move(d));
   }
   std::lock_guard<std::mutex> lock(s->mu);
-  for (auto &d : out) s->completed.push_back(std::move(d));
+  for (auto &d : out) {
+    s->completed.push_back(std::move(d));
+    s->completed_at.push_back(now);
+  }
   s->st.completed += out.size();
   s->active -= c.queries.size();
   s->pool_in_use -= c.reserved_stage;
   c.queries.clear();
   c.reserved_stage = 0;
   c.busy = false;
+  c.phase = 0;
 }
 
 void dispatcher(s4_server *s) {
@@ -207,7 +233,12 @@ void dispatcher(s4_server *s) {
     bool progressed = false;
     for (Context &c : s->ctx) {
       if (c.busy && hipEventQuery(c.done) == hipSuccess) {
-        retire_context(s, c);
+        if (c.phase == 1) {
+          std::vector<uint32_t> spill;
+          if (start_copy(s, c, &spill)) retire_context(s, c, spill.empty() ? c.h_results : spill.data());
+        } else {
+          retire_context(s, c, c.h_results);
+        }
         progressed = true;
       }
     }
@@ -222,18 +253,16 @@ void dispatcher(s4_server *s) {
       Context &c = *free_ctx;
       {
         std::unique_lock<std::mutex> lock(s->mu);
-        uint64_t items = 0, results = 0, terms = 0;
+        uint64_t items = 0, terms = 0;
         while (!s->waiting.empty() && c.queries.size() < s->slots_per_ctx) {
           const Query &q = s->waiting.front();
-          const bool fits = items + q.items <= s->items_per_ctx && results + q.bound <= s->results_per_ctx &&
-                            terms + q.terms.size() <= s->terms_per_ctx &&
+          const bool fits = items + q.items <= s->items_per_ctx && terms + q.terms.size() <= s->terms_per_ctx &&
                             s->pool_in_use + 4 * s4::kBlock * (items + q.items) <= s->cfg.pool_bytes;
           if (!fits) {
             if (c.queries.empty()) ++s->st.waits_for_memory;
             break;
           }
           items += q.items;
-          results += q.bound;
           terms += q.terms.size();
           c.queries.push_back(std::move(s->waiting.front()));
           s->waiting.pop_front();
@@ -292,7 +321,7 @@ int s4_server_create(const s4_index *index, const s4_server_config *cfg, s4_serv
   (void)hipGetDevice(&s->device);
   s->slots_per_ctx = std::max<uint64_t>(1, cfg->max_slots / kContexts);
   s->items_per_ctx = std::max<uint64_t>(1, cfg->pool_bytes / kContexts / (4 * kBlock));
-  const uint64_t rb = cfg->result_bytes ? cfg->result_bytes : cfg->pool_bytes / 4;
+  const uint64_t rb = cfg->result_bytes ? cfg->result_bytes : (64ull << 20);
   s->results_per_ctx = std::max<uint64_t>(kBlock, rb / kContexts / 4);
   s->terms_per_ctx = s->slots_per_ctx * cfg->max_terms;
   if (s->items_per_ctx >= 0xFFFFFFFFull / kBlock) {
@@ -329,7 +358,7 @@ int s4_server_submit(s4_server *s, const uint32_t *terms, uint32_t k, uint64_t *
   std::lock_guard<std::mutex> lock(s->mu);
   if (s->stop) return fail(S4_EINVAL, "server is stopping");
   if (s->worker_error) return fail(s->worker_error, "server failed: " + s->worker_msg);
-  if (q.items > s->items_per_ctx || q.bound > s->results_per_ctx || q.terms.size() > s->terms_per_ctx ||
+  if (q.items > s->items_per_ctx || q.terms.size() > s->terms_per_ctx ||
       4 * kBlock * q.items > s->cfg.pool_bytes) {
     ++s->st.rejected;
     return fail(S4_ERANGE, "query needs more intermediate memory than one iteration holds");
@@ -362,6 +391,7 @@ int s4_server_poll(s4_server *s, uint64_t *ids, uint64_t *counts, uint64_t *late
     used += d.count;
     res_offsets[n + 1] = used;
     s->completed.pop_front();
+    s->completed_at.pop_front();
     ++n;
   }
   *done = n;
@@ -373,6 +403,70 @@ int s4_server_stats_get(const s4_server *s, s4_server_stats *st) {
   if (!s || !st) return fail(S4_EINVAL, "null argument");
   std::lock_guard<std::mutex> lock(const_cast<s4_server *>(s)->mu);
   *st = s->st;
+  return S4_OK;
+}
+
+int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
+                     const uint64_t *h_arrival_ns, uint64_t *latency_ns, uint64_t *counts, uint32_t *results,
+                     uint64_t results_cap, uint64_t *res_offsets, double timeout_s, double *elapsed_s) {
+  if (!s || !h_q_offsets || !h_arrival_ns || !latency_ns || !counts || (nq && !h_terms))
+    return fail(S4_EINVAL, "null argument");
+  if (results && !res_offsets) return fail(S4_EINVAL, "results need res_offsets");
+  std::vector<std::vector<uint32_t>> res(results ? nq : 0);
+  uint64_t ndone = 0, next = 0;
+  std::unordered_map<uint64_t, uint64_t> pending;
+  const auto t0 = Clock::now();
+  auto now_ns = [&]() { return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count()); };
+  uint64_t last_done_ns = 0;
+  while (ndone < nq) {
+    const uint64_t t = now_ns();
+    // submit everything due
+    while (next < nq && h_arrival_ns[next] <= t) {
+      const uint64_t a = h_q_offsets[next], b = h_q_offsets[next + 1];
+      uint64_t id = 0;
+      int rc = s4_server_submit(s, h_terms + a, uint32_t(b - a), &id);
+      if (rc == S4_EAGAIN) break;
+      if (rc) return rc;
+      pending.emplace(id, next);
+      ++next;
+    }
+    // drain completions
+    {
+      std::lock_guard<std::mutex> lock(s->mu);
+      while (!s->completed.empty()) {
+        Done &d = s->completed.front();
+        auto it = pending.find(d.id);
+        if (it != pending.end()) {
+          const uint64_t q = it->second;
+          const uint64_t fin = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                                            s->completed_at.front() - t0).count());
+          latency_ns[q] = fin > h_arrival_ns[q] ? fin - h_arrival_ns[q] : 0;
+          last_done_ns = std::max(last_done_ns, fin);
+          counts[q] = d.count;
+          if (results) res[q] = std::move(d.result);
+          ++ndone;
+          pending.erase(it);
+        }
+        s->completed.pop_front();
+        s->completed_at.pop_front();
+      }
+      if (s->worker_error) return fail(s->worker_error, "server failed: " + s->worker_msg);
+    }
+    if (double(now_ns()) * 1e-9 > timeout_s) return fail(S4_ERANGE, "replay timed out");
+    if (next < nq && h_arrival_ns[next] > now_ns() + 50000)
+      std::this_thread::sleep_for(std::chrono::microseconds(10));
+  }
+  if (elapsed_s) *elapsed_s = double(last_done_ns - (nq ? h_arrival_ns[0] : 0)) * 1e-9;
+  if (results) {
+    uint64_t used = 0;
+    res_offsets[0] = 0;
+    for (uint64_t q = 0; q < nq; ++q) {
+      if (used + res[q].size() > results_cap) return fail(S4_ERANGE, "results_cap too small");
+      std::copy(res[q].begin(), res[q].end(), results + used);
+      used += res[q].size();
+      res_offsets[q + 1] = used;
+    }
+  }
   return S4_OK;
 }
 

@@ -102,3 +102,48 @@ def test_memory_admission(gpu, served):
         assert tiny.stats()["rejected"] == 1
     finally:
         tiny.close()
+
+
+def test_replay_open_loop(gpu, served):
+    ix, flat, offs = served
+    nq = 2000
+    terms, qoffs = workloads.queries(31, ix.lengths, nq, 2, 8)
+    arr = (workloads.arrivals(32, 20000.0, nq) * 1e9).astype(np.uint64)
+    srv = gpu.Server(ix, max_slots=1024, pool_bytes=256 << 20)
+    try:
+        r = srv.replay(terms, qoffs, arr, with_results=True, results_cap=1 << 24)
+    finally:
+        srv.close()
+    assert (r["latency_ns"] > 0).all() and r["elapsed_s"] > 0
+    for q in range(0, nq, 13):
+        ts = terms[int(qoffs[q]): int(qoffs[q + 1])]
+        got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
+        assert np.array_equal(got, want(flat, offs, ts)), q
+        assert int(r["counts"][q]) == got.size
+
+
+@pytest.mark.timeout(900)
+def test_full_size_serving_sampled(gpu):
+    """The serving workload at full size (2^20 clustered lists over
+    [0, 2^31), 3.9e9 integers, device-resident), 2^12 queries of 2..8 terms
+    replayed open-loop at saturation; every result checked with the oracle."""
+    t0 = time.time()
+    lens = workloads.index_lengths(1 << 20, 28)
+    kinds = np.full(lens.size, workloads.CLUSTERED, dtype=np.int32)
+    flat, offs = workloads.lists(kinds, lens, workloads.config_seed(4, 0), 1 << 31)
+    buf, soffs = gpu.encode_many(flat, offs)
+    ix = gpu.Index(buf, soffs)
+    del buf, soffs
+    print(f"serving index built in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    nq = 1 << 12
+    terms, qoffs = workloads.serving_queries(ix.lengths, nq, level=7)
+    srv = gpu.Server(ix, max_slots=1 << 14, pool_bytes=24 << 30, result_bytes=3 << 28)
+    try:
+        r = srv.replay(terms, qoffs, np.zeros(nq, np.uint64), with_results=True, results_cap=1 << 28)
+    finally:
+        srv.close()
+    for q in range(nq):
+        ts = sorted(terms[int(qoffs[q]): int(qoffs[q + 1])], key=lambda t: int(lens[t]))
+        w = oracle.intersect_k([flat[int(offs[t]): int(offs[t + 1])] for t in ts])
+        got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
+        assert np.array_equal(got, w), q
