@@ -55,7 +55,7 @@ def parse():
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs into profiles/decode_traffic.json")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving workload instead (index of 2^20 lists, Poisson arrivals at 3 levels)")
-    ap.add_argument("--serve-queries", type=int, default=1 << 16)
+    ap.add_argument("--serve-queries", type=int, default=1 << 20)
     ap.add_argument("--serve-lists", type=int, default=1 << 20)
     ap.add_argument("--serve-check", type=int, default=1 << 12,
                     help="queries per level checked against the oracle (0: none)")
@@ -109,19 +109,22 @@ def time_graph(torch, fn, stream, steps, warmup):
 
 
 def per_launch_ms(torch, s4, lists, outs, stream, reps=3):
-    """Duration of every decode launch, from HIP events recorded on the
-    launch stream right around it; a clock-bounded spin kernel first holds
-    the stream so the host has queued every launch before any runs."""
+    """Duration of every decode launch, from HIP events on the launch stream
+    that the launch itself records at the kernel's start and end
+    (hipExtLaunchKernel); a clock-bounded spin kernel first holds the stream
+    so the host has queued every launch before any runs."""
     import numpy as np
     acc = np.zeros(len(lists))
     for _ in range(reps):
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in lists]
         with torch.cuda.stream(stream):
+            for a, b in evs:  # create the events
+                a.record()
+                b.record()
+            torch.cuda.synchronize()
             s4.spin(40_000_000)
             for (a, b), l, o in zip(evs, lists, outs):
-                a.record()
-                l.decode_into(o)
-                b.record()
+                l.decode_timed_into(o, a, b)
         torch.cuda.synchronize()
         acc += np.array([a.elapsed_time(b) for a, b in evs])
     return acc / reps

@@ -121,6 +121,14 @@ int s4_list_skip_index(const s4_list *list, uint32_t *bmax, uint32_t *seeds, voi
  * copied.  S4_ERANGE if cap < n. */
 int s4_decode_dev(const s4_list *list, uint32_t *d_out, uint64_t cap, void *stream);
 
+/* s4_decode_dev with timing: the kernel is launched so that the caller's
+ * HIP events start_event / stop_event (hipEvent_t, created with timing) are
+ * recorded by the launch itself at the kernel's start and end, so their
+ * elapsed time is the kernel's execution without the dispatch of the
+ * launch.  For an empty list both events are recorded back to back. */
+int s4_decode_timed_dev(const s4_list *list, uint32_t *d_out, uint64_t cap, void *start_event, void *stop_event,
+                        void *stream);
+
 /* Decode blocks [first, first + count) into d_out (128 values per block);
  * block index nb denotes the tail (t values).  Each block is seeded from
  * the skip index, so any range decodes alone. */

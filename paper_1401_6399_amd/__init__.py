@@ -66,6 +66,7 @@ SIGNATURES = {
     "s4_list_skip_index": (_i, [_vp, _u32p, _u32p, _vp]),
     "s4_decode_dev": (_i, [_vp, _vp, _u64, _vp]),
     "s4_decode_blocks_dev": (_i, [_vp, _u32, _u32, _vp, _vp]),
+    "s4_decode_timed_dev": (_i, [_vp, _vp, _u64, _vp, _vp, _vp]),
     "s4_decode_lists_dev": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u64p, _u32, _u32, _vp]),
     "s4_decode_plan_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u64p, _u32, _vp,
                                    ctypes.POINTER(_vp)]),
@@ -254,6 +255,15 @@ class DeviceList:
 
     def decode_into(self, out, stream=None):
         _check(require_library().s4_decode_dev(self.h, _dptr(out), out.numel(), _stream(stream)), "s4_decode_dev")
+
+    def decode_timed_into(self, out, start_event, stop_event, stream=None):
+        """Decode with torch timing events recorded by the launch itself at
+        the kernel's start and end (the events must have been recorded once,
+        so that they exist)."""
+        _check(require_library().s4_decode_timed_dev(self.h, _dptr(out), out.numel(),
+                                                     ctypes.c_void_p(start_event.cuda_event),
+                                                     ctypes.c_void_p(stop_event.cuda_event), _stream(stream)),
+               "s4_decode_timed_dev")
 
     def decode(self, stream=None):
         import torch

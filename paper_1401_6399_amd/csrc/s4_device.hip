@@ -8,6 +8,8 @@
 #include <numeric>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "s4_kernels.h"
 
 namespace s4 {
@@ -543,11 +545,20 @@ static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len
 
 template <int P>
 static void launch_decode(const DList &L, uint32_t first, uint32_t count, uint32_t block_waves, uint32_t waves,
-                          uint32_t *d_out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, L, first, count, block_waves, d_out);
+                          uint32_t *d_out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, ev0, ev1, 0, L, first, count,
+                          block_waves, d_out);
+  else
+    hipLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, L, first, count, block_waves, d_out);
 }
 
 int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream) {
+  return decode_range_timed(L, first, count, d_out, stream, nullptr, nullptr);
+}
+
+int decode_range_timed(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream,
+                       hipEvent_t ev0, hipEvent_t ev1) {
   const uint32_t end = first + count;
   const uint32_t full = end > L.nb ? (L.nb > first ? L.nb - first : 0) : count;
   // blocks per wave (4 P): the largest P that still gives ~8 waves per CU
@@ -559,10 +570,10 @@ int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out
   const uint32_t waves = block_waves + (tail ? 1 : 0);
   if (waves == 0) return S4_OK;
   switch (P) {
-    case 8: launch_decode<8>(L, first, count, block_waves, waves, d_out, stream); break;
-    case 4: launch_decode<4>(L, first, count, block_waves, waves, d_out, stream); break;
-    case 2: launch_decode<2>(L, first, count, block_waves, waves, d_out, stream); break;
-    default: launch_decode<1>(L, first, count, block_waves, waves, d_out, stream); break;
+    case 8: launch_decode<8>(L, first, count, block_waves, waves, d_out, stream, ev0, ev1); break;
+    case 4: launch_decode<4>(L, first, count, block_waves, waves, d_out, stream, ev0, ev1); break;
+    case 2: launch_decode<2>(L, first, count, block_waves, waves, d_out, stream, ev0, ev1); break;
+    default: launch_decode<1>(L, first, count, block_waves, waves, d_out, stream, ev0, ev1); break;
   }
   S4_HIP(hipGetLastError());
   return S4_OK;
@@ -671,6 +682,20 @@ int s4_decode_dev(const s4_list *l, uint32_t *d_out, uint64_t cap, void *stream)
   if (reinterpret_cast<uintptr_t>(d_out) & 15u) return fail(S4_EINVAL, "d_out must be 16-byte aligned");
   if (!l->n) return S4_OK;
   return decode_range(l->d, 0, l->nb + (l->t ? 1 : 0), d_out, as_stream(stream));
+}
+
+int s4_decode_timed_dev(const s4_list *l, uint32_t *d_out, uint64_t cap, void *start_event, void *stop_event,
+                        void *stream) {
+  if (!l || (!d_out && l->n) || !start_event || !stop_event) return fail(S4_EINVAL, "null argument");
+  if (cap < l->n) return fail(S4_ERANGE, "s4_decode_timed_dev: cap < n");
+  if (reinterpret_cast<uintptr_t>(d_out) & 15u) return fail(S4_EINVAL, "d_out must be 16-byte aligned");
+  hipEvent_t e0 = static_cast<hipEvent_t>(start_event), e1 = static_cast<hipEvent_t>(stop_event);
+  if (!l->n) {
+    S4_HIP(hipEventRecord(e0, as_stream(stream)));
+    S4_HIP(hipEventRecord(e1, as_stream(stream)));
+    return S4_OK;
+  }
+  return decode_range_timed(l->d, 0, l->nb + (l->t ? 1 : 0), d_out, as_stream(stream), e0, e1);
 }
 
 int s4_decode_blocks_dev(const s4_list *l, uint32_t first, uint32_t count, uint32_t *d_out, void *stream) {

@@ -81,6 +81,9 @@ struct Upload {
 int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DList> *descs);
 // Decode blocks [first, first + count) of L into d_out (index nb = tail).
 int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream);
+// The same, the kernel launched so that ev0 / ev1 record its start and end.
+int decode_range_timed(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream,
+                       hipEvent_t ev0, hipEvent_t ev1);
 // Exclusive scan of counts[n] (tiles of 1024), grand total to *total, then
 // ordered gather of stage[128 i .. 128 i + counts[i]) into out.
 int scan_and_compact(const uint32_t *stage, const uint32_t *counts, uint32_t n, uint32_t *excl, uint32_t *tiles,

@@ -148,3 +148,18 @@ def test_bulk_workload_full_size(gpu):
         assert np.array_equal(got, x), i
         if i in sample:
             assert np.array_equal(got, oracle.decode(oracle.encode(x))), i
+
+
+def test_decode_timed_matches_and_times(gpu):
+    import torch
+    x = workloads.sorted_list(workloads.CLUSTERED, 12, 1 << 26, (1 << 20) + 3)
+    enc = oracle.encode(x)
+    lst = gpu.DeviceList.upload(enc)
+    out = torch.zeros(x.size + 4, dtype=torch.int32, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    e1.record()
+    lst.decode_timed_into(out, e0, e1)
+    torch.cuda.synchronize()
+    assert e0.elapsed_time(e1) > 0
+    assert np.array_equal(out[: x.size].cpu().numpy().view(np.uint32), oracle.decode(enc))
