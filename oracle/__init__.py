@@ -21,6 +21,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 OK, EINVAL, EUNSORTED, ERANGE, ECORRUPT, ENOMEM = 0, -1, -2, -3, -4, -5
+D4, DM, D2, D1 = 0, 1, 2, 3  # differential forms (stream flag bits 1-2)
 HEADER_BYTES = 32
 MAGIC = 0x34443453
 
@@ -52,6 +53,7 @@ def _bind(path):
     u64p = ctypes.POINTER(ctypes.c_uint64)
     sz = ctypes.c_size_t
     lib.orc_encode.argtypes = [u32p, ctypes.c_uint64, u8p, sz, ctypes.POINTER(sz)]
+    lib.orc_encode_mode.argtypes = [u32p, ctypes.c_uint64, ctypes.c_uint32, u8p, sz, ctypes.POINTER(sz)]
     lib.orc_decode.argtypes = [u8p, sz, u32p, ctypes.c_uint64, u64p]
     lib.orc_decode_alg1.argtypes = [u8p, sz, u32p, ctypes.c_uint64, u64p]
     lib.orc_decoded_length.argtypes = [u8p, sz, u64p]
@@ -61,7 +63,7 @@ def _bind(path):
     lib.orc_intersect.argtypes = [u32p, ctypes.c_uint64, u32p, ctypes.c_uint64, u32p, u64p]
     lib.orc_intersect_k.argtypes = [ctypes.POINTER(u32p), u64p, ctypes.c_uint32, u32p,
                                     ctypes.c_uint64, u64p]
-    for f in (lib.orc_encode, lib.orc_decode, lib.orc_decode_alg1, lib.orc_decoded_length,
+    for f in (lib.orc_encode, lib.orc_encode_mode, lib.orc_decode, lib.orc_decode_alg1, lib.orc_decoded_length,
               lib.orc_widths, lib.orc_intersect, lib.orc_intersect_k):
         f.restype = ctypes.c_int
     return lib
@@ -115,16 +117,17 @@ def _u8(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
 
 
-def encode(x) -> np.ndarray:
-    """Serialized S4-BP128-D4 stream of a non-decreasing uint32 list."""
+def encode(x, mode: int = D4) -> np.ndarray:
+    """Serialized S4-BP128 stream of a non-decreasing uint32 list with the
+    given differential form (D4 by default)."""
     lib = _active()
     x, xp = _u32(x)
     n = x.size
     bound = HEADER_BYTES + ((n // 128 + 3) & ~3) + 512 * (n // 128) + 4 * (n % 128) + 16
     out = np.zeros(bound, dtype=np.uint8)
     nbytes = ctypes.c_size_t(0)
-    rc = lib.orc_encode(xp, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), bound,
-                        ctypes.byref(nbytes))
+    rc = lib.orc_encode_mode(xp, n, mode, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), bound,
+                             ctypes.byref(nbytes))
     if rc:
         raise OracleError(rc, "encode")
     return out[: nbytes.value].copy()

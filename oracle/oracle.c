@@ -19,8 +19,11 @@
  *     lane j is an LSB-first stream of 32 values of b bits stored in words
  *     j, 4+j, 8+j, ...; a value that straddles a word boundary continues in
  *     the same lane's next word (Sec. 4.2, Fig. 2).
- *   - D4 differential coding: delta_i = x_i - x_{i-4}, prefix sum seeded
- *     with (0,0,0,0) and carried from block to block (Sec. 5, Alg. 1).
+ *   - Differential coding (Sec. 5), one of four forms recorded in the
+ *     stream: D4 delta_i = x_i - x_{i-4}; DM delta_{4i+j} = x_{4i+j} -
+ *     x_{4i-1}; D2 delta_i = x_i - x_{i-2}; D1 delta_i = x_i - x_{i-1};
+ *     values before the list are 0.  The inverse ("prefix sum") runs over
+ *     the whole list, seeded with zeros (Alg. 1).
  *   - Intersection: the textbook two-pointer merge ("scalar", Sec. 6) and
  *     SvS folding of k lists (Sec. 6).
  *
@@ -37,7 +40,8 @@
  * Serialized stream (little-endian), as written and read here:
  *   0  u32 magic 0x34443453 ("S4D4")
  *   4  u16 version (1)
- *   6  u16 flags  (bit 0: input strictly increasing; other bits zero)
+ *   6  u16 flags  (bit 0: input strictly increasing; bits 1-2: differential
+ *                  form, 0 = D4, 1 = DM, 2 = D2, 3 = D1; other bits zero)
  *   8  u64 n      (number of integers)
  *   16 u32 nb     (= floor(n / 128), number of packed blocks)
  *   20 u32 t      (= n - 128 nb, raw tail length)
@@ -91,6 +95,21 @@ static uint32_t orc_width(const uint32_t *d, size_t count) {
 
 static size_t pad4(size_t v) { return (v + 3u) & ~(size_t)3u; }
 
+#define ORC_D4 0u
+#define ORC_DM 1u
+#define ORC_D2 2u
+#define ORC_D1 3u
+
+/* The value each form subtracts from x_i (Sec. 5), 0 before the list. */
+static uint32_t orc_reference(const uint32_t *x, uint64_t i, uint32_t mode) {
+  switch (mode) {
+    case ORC_D1: return i >= 1 ? x[i - 1] : 0u;
+    case ORC_D2: return i >= 2 ? x[i - 2] : 0u;
+    case ORC_DM: { uint64_t q = i / 4u; return q >= 1 ? x[4u * q - 1u] : 0u; }
+    default: return i >= 4 ? x[i - 4] : 0u;
+  }
+}
+
 /* Exact serialized size given the block widths (Sec. 4.2: 128 b bits, i.e.
  * 16 b bytes, per block). */
 size_t orc_stream_bytes(uint64_t n, const uint8_t *widths) {
@@ -101,8 +120,9 @@ size_t orc_stream_bytes(uint64_t n, const uint8_t *widths) {
 
 /* Encode a non-decreasing list: D4 deltas (Sec. 5), per-block width
  * (Sec. 4.3), 4-lane interleaved LSB-first packing (Sec. 4.2, Fig. 2). */
-int orc_encode(const uint32_t *x, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes) {
-  if ((!x && n) || !out_bytes) return ORC_EINVAL;
+int orc_encode_mode(const uint32_t *x, uint64_t n, uint32_t mode, uint8_t *out, size_t cap,
+                    size_t *out_bytes) {
+  if ((!x && n) || !out_bytes || mode > 3u) return ORC_EINVAL;
   int strictly = 1;
   for (uint64_t i = 1; i < n; ++i) {
     if (x[i] < x[i - 1]) return ORC_EUNSORTED;
@@ -112,11 +132,11 @@ int orc_encode(const uint32_t *x, uint64_t n, uint8_t *out, size_t cap, size_t *
   if (nb > 0xFFFFFFFFull) return ORC_EINVAL;
   uint64_t packed = nb * 128u;
 
-  /* deltas over the global index: delta_i = x_i - x_{i-4}, x_{-4..-1} = 0 */
+  /* deltas over the global index, values before the list taken as 0 */
   uint32_t *d = (uint32_t *)malloc((packed ? packed : 1) * sizeof(uint32_t));
   uint8_t *w = (uint8_t *)malloc(nb ? nb : 1);
   if (!d || !w) { free(d); free(w); return ORC_ENOMEM; }
-  for (uint64_t i = 0; i < packed; ++i) d[i] = x[i] - (i >= 4 ? x[i - 4] : 0u);
+  for (uint64_t i = 0; i < packed; ++i) d[i] = x[i] - orc_reference(x, i, mode);
   uint64_t pw = 0;
   for (uint64_t k = 0; k < nb; ++k) { w[k] = (uint8_t)orc_width(d + 128u * k, 128u); pw += 4u * w[k]; }
 
@@ -126,7 +146,7 @@ int orc_encode(const uint32_t *x, uint64_t n, uint8_t *out, size_t cap, size_t *
   memset(out, 0, need);
   put32(out, ORC_MAGIC);
   put16(out + 4, 1);
-  put16(out + 6, (uint16_t)(strictly ? 1 : 0));
+  put16(out + 6, (uint16_t)((strictly ? 1u : 0u) | (mode << 1)));
   put64(out + 8, n);
   put32(out + 16, (uint32_t)nb);
   put32(out + 20, (uint32_t)t);
@@ -160,6 +180,10 @@ int orc_encode(const uint32_t *x, uint64_t n, uint8_t *out, size_t cap, size_t *
   return ORC_OK;
 }
 
+int orc_encode(const uint32_t *x, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes) {
+  return orc_encode_mode(x, n, ORC_D4, out, cap, out_bytes);
+}
+
 typedef struct {
   uint64_t n, nb, t, pw;
   uint16_t flags;
@@ -172,7 +196,7 @@ static int orc_parse(const uint8_t *enc, size_t bytes, orc_view *v) {
   if (!enc || bytes < ORC_HEADER) return ORC_ECORRUPT;
   if (get32(enc) != ORC_MAGIC || get16(enc + 4) != 1) return ORC_ECORRUPT;
   v->flags = get16(enc + 6);
-  if (v->flags & ~1u) return ORC_ECORRUPT;
+  if (v->flags & ~7u) return ORC_ECORRUPT;
   v->n = get64(enc + 8);
   v->nb = get32(enc + 16);
   v->t = get32(enc + 20);
@@ -228,9 +252,9 @@ static uint32_t orc_extract(const uint8_t *w, uint32_t b, uint32_t p) {
   return (uint32_t)((window >> s) & mask);
 }
 
-/* Decode: unpack every delta by random access, then the D4 inverse as one
- * running sum per residue class mod 4 over the whole list (Sec. 5), then
- * copy the raw tail. */
+/* Decode: unpack every delta by random access, then invert the stream's
+ * differential form over the whole list in index order, x_i = delta_i +
+ * (the value the form subtracted) (Sec. 5), then copy the raw tail. */
 int orc_decode(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, uint64_t *n_out) {
   orc_view v;
   int rc = orc_parse(enc, bytes, &v);
@@ -244,9 +268,34 @@ int orc_decode(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, ui
       out[128u * k + p] = orc_extract(v.payload + 4u * word_base, b, p);
     word_base += 4u * b;
   }
-  for (uint64_t i = 4; i < 128u * v.nb; ++i) out[i] += out[i - 4];
+  const uint32_t mode = (v.flags >> 1) & 3u;
+  for (uint64_t i = 0; i < 128u * v.nb; ++i) out[i] += orc_reference(out, i, mode);
   for (uint64_t i = 0; i < v.t; ++i) out[128u * v.nb + i] = get32(v.tail + 4u * i);
   return ORC_OK;
+}
+
+/* The vector prefix function P(t, v) of each differential form, for a
+ * 4-vector t of deltas and the previous decoded 4-vector v, following the
+ * SIMD steps Sec. 5 lists (shifts by whole integers, broadcasts, adds). */
+static void orc_prefix(uint32_t mode, uint32_t t[4], const uint32_t v[4]) {
+  uint32_t u[4];
+  switch (mode) {
+    case ORC_DM: /* broadcast v's last integer, add */
+      for (int c = 0; c < 4; ++c) t[c] += v[3];
+      break;
+    case ORC_D2: /* t + (t shifted by two integers), then + (v3, v4, v3, v4) */
+      u[0] = t[0]; u[1] = t[1]; u[2] = t[2] + t[0]; u[3] = t[3] + t[1];
+      t[0] = u[0] + v[2]; t[1] = u[1] + v[3]; t[2] = u[2] + v[2]; t[3] = u[3] + v[3];
+      break;
+    case ORC_D1: /* the D2 steps, then + (shifted by one integer), then + v's last */
+      u[0] = t[0]; u[1] = t[1]; u[2] = t[2] + t[0]; u[3] = t[3] + t[1];
+      t[0] = u[0]; t[1] = u[1] + u[0]; t[2] = u[2] + u[1]; t[3] = u[3] + u[2];
+      for (int c = 0; c < 4; ++c) t[c] += v[3];
+      break;
+    default: /* D4: t + v */
+      for (int c = 0; c < 4; ++c) t[c] += v[c];
+      break;
+  }
 }
 
 /* Second, structurally different decoder that follows the steps of the
@@ -254,34 +303,36 @@ int orc_decode(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, ui
  * (four lanes each) with a running bit offset i; while a whole value fits
  * in the current vector, shift it out and mask; otherwise complete it with
  * the low bits of the next vector shifted left by 32-i; after each
- * 4-vector apply the D4 prefix P(t,v) = t + v and make t the new seed. */
-static void orc_alg1_block(const uint8_t *y, uint32_t b, uint32_t v[4], uint32_t *w) {
+ * 4-vector apply the form's prefix P(t,v) and make the result the new v. */
+static void orc_alg1_block(const uint8_t *y, uint32_t b, uint32_t mode, uint32_t v[4], uint32_t *w) {
   uint32_t M = (b == 32u) ? 0xFFFFFFFFu : ((1u << b) - 1u);
   uint32_t produced = 0;
+  uint32_t t[4];
   if (b == 0) {
-    /* no input vectors: 128 zero deltas, so each output is the seed */
-    for (uint32_t r = 0; r < 32u; ++r)
-      for (uint32_t c = 0; c < 4u; ++c) w[4u * r + c] = v[c];
+    /* no input vectors: 128 zero deltas */
+    for (uint32_t r = 0; r < 32u; ++r) {
+      t[0] = t[1] = t[2] = t[3] = 0;
+      orc_prefix(mode, t, v);
+      for (uint32_t c = 0; c < 4u; ++c) { v[c] = t[c]; w[4u * r + c] = t[c]; }
+    }
     return;
   }
   uint32_t i = 0;
   for (uint32_t k = 0; k < b; ++k) {
     while (i + b <= 32u) {
-      for (uint32_t c = 0; c < 4u; ++c) {
-        uint32_t t = (get32(y + 4u * (4u * k + c)) >> i) & M;
-        v[c] = t + v[c];
-        w[4u * produced + c] = v[c];
-      }
+      for (uint32_t c = 0; c < 4u; ++c) t[c] = (get32(y + 4u * (4u * k + c)) >> i) & M;
+      orc_prefix(mode, t, v);
+      for (uint32_t c = 0; c < 4u; ++c) { v[c] = t[c]; w[4u * produced + c] = t[c]; }
       ++produced;
       i += b;
     }
     if (i < 32u) {
       for (uint32_t c = 0; c < 4u; ++c) {
         uint32_t z = (get32(y + 4u * (4u * (k + 1u) + c)) << (32u - i)) & M;
-        uint32_t t = (get32(y + 4u * (4u * k + c)) >> i) | z;
-        v[c] = t + v[c];
-        w[4u * produced + c] = v[c];
+        t[c] = (get32(y + 4u * (4u * k + c)) >> i) | z;
       }
+      orc_prefix(mode, t, v);
+      for (uint32_t c = 0; c < 4u; ++c) { v[c] = t[c]; w[4u * produced + c] = t[c]; }
       ++produced;
       i = i + b - 32u;
     } else {
@@ -300,7 +351,7 @@ int orc_decode_alg1(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t ca
   uint64_t word_base = 0;
   for (uint64_t k = 0; k < v.nb; ++k) {
     uint32_t b = v.widths[k];
-    orc_alg1_block(v.payload + 4u * word_base, b, seed, out + 128u * k);
+    orc_alg1_block(v.payload + 4u * word_base, b, (v.flags >> 1) & 3u, seed, out + 128u * k);
     word_base += 4u * b;
   }
   for (uint64_t i = 0; i < v.t; ++i) out[128u * v.nb + i] = get32(v.tail + 4u * i);

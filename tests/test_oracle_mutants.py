@@ -14,19 +14,28 @@ import test_oracle_pins as pins
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
 MUTANTS = {
-    "delta_stride": ("x[i] - (i >= 4 ? x[i - 4] : 0u)", "x[i] - (i >= 4 ? x[i - 3] : 0u)"),
-    "inverse_stride": ("out[i] += out[i - 4];", "out[i] += out[i - 1];"),
+    "d4_stride": ("default: return i >= 4 ? x[i - 4] : 0u;", "default: return i >= 4 ? x[i - 3] : 0u;"),
+    "d1_stride": ("case ORC_D1: return i >= 1 ? x[i - 1] : 0u;", "case ORC_D1: return i >= 2 ? x[i - 2] : 0u;"),
+    "d2_stride": ("case ORC_D2: return i >= 2 ? x[i - 2] : 0u;", "case ORC_D2: return i >= 1 ? x[i - 1] : 0u;"),
+    "dm_reference": ("return q >= 1 ? x[4u * q - 1u] : 0u;", "return q >= 1 ? x[4u * q - 2u] : 0u;"),
+    "inverse_dropped": ("out[i] += orc_reference(out, i, mode);", "out[i] += orc_reference(out, i, ORC_D4);"),
+    "d2_steps": ("u[2] = t[2] + t[0]; u[3] = t[3] + t[1];\n      t[0] = u[0] + v[2];",
+                 "u[2] = t[2] + t[1]; u[3] = t[3] + t[1];\n      t[0] = u[0] + v[2];"),
+    "d1_steps": ("t[0] = u[0]; t[1] = u[1] + u[0]; t[2] = u[2] + u[1]; t[3] = u[3] + u[2];",
+                 "t[0] = u[0]; t[1] = u[1] + u[0]; t[2] = u[2] + u[0]; t[3] = u[3] + u[2];"),
+    "dm_steps": ("for (int c = 0; c < 4; ++c) t[c] += v[3];\n      break;\n    case ORC_D2:",
+                 "for (int c = 0; c < 4; ++c) t[c] += v[c];\n      break;\n    case ORC_D2:"),
     "lane_word_index": ("get32(w + 4u * (4u * m + j))", "get32(w + 4u * (4u * j + m))"),
     "width_compare": ("(uint64_t)d[i] >= ((uint64_t)1 << b)", "(uint64_t)d[i] > ((uint64_t)1 << b)"),
     "width_drops_last": ("orc_width(d + 128u * k, 128u)", "orc_width(d + 128u * k, 127u)"),
     "pack_lane_order": ("d[128u * k + 4u * q + j]", "d[128u * k + 32u * j + q]"),
     "merge_advance": ("else if (b[j] < a[i]) ++j;", "else if (b[j] < a[i]) ++i;"),
     "alg1_straddle_shift": ("<< (32u - i)) & M;", "<< (31u - i)) & M;"),
-    "alg1_dropped_prefix": ("v[c] = t + v[c];\n        w[4u * produced + c] = v[c];\n      }\n      ++produced;\n      i += b;",
-                            "v[c] = t;\n        w[4u * produced + c] = v[c];\n      }\n      ++produced;\n      i += b;"),
+    "alg1_dropped_prefix": ("default: /* D4: t + v */\n      for (int c = 0; c < 4; ++c) t[c] += v[c];",
+                            "default: /* D4: t + v */\n      for (int c = 0; c < 4; ++c) t[c] += 0;"),
     "b32_mask": ("(b == 32u) ? 0xFFFFFFFFull", "(b == 32u) ? 0x7FFFFFFFull"),
-    "tail_offset": ("out[128u * v.nb + i] = get32(v.tail + 4u * i);\n  return ORC_OK;\n}\n\n/* Second",
-                    "out[128u * v.nb + i] = get32(v.tail);\n  return ORC_OK;\n}\n\n/* Second"),
+    "tail_offset": ("out[128u * v.nb + i] = get32(v.tail + 4u * i);\n  return ORC_OK;\n}\n\n/* The vector",
+                    "out[128u * v.nb + i] = get32(v.tail);\n  return ORC_OK;\n}\n\n/* The vector"),
     "extract_shift": ("(uint32_t)((window >> s) & mask)", "(uint32_t)((window >> (s + 1)) & mask)"),
 }
 
@@ -55,6 +64,12 @@ def battery():
     checks.append(("ap", lambda: pins.test_arithmetic_progression_closed_form(7, 3)))
     for p in (0, 127):
         checks.append((f"jump_{p}", lambda p=p: pins.test_width_reaches_every_position(p)))
+    checks.append(("sec5_steps", pins.test_sec5_worked_prefix_steps))
+    checks.append(("table3", pins.test_table3_relative_delta_sizes))
+    checks.append(("modes_ap", lambda: pins.test_modes_arithmetic_progression_widths(7, 3)))
+    for name in pins.MODES:
+        checks.append((f"modes_alg1_{name}", lambda n=name: pins.test_modes_random_access_matches_alg1_walk(n, 17)))
+        checks.append((f"modes_rt_{name}", lambda n=name: pins.test_modes_round_trip(n, 2049)))
     for name, fn in checks:
         try:
             fn()

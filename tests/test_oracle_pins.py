@@ -345,3 +345,103 @@ def test_intersect_k_invariants():
     assert oracle.intersect_k([lists[0]]).tolist() == lists[0].tolist()
     assert oracle.intersect_k([lists[1], lists[1]]).tolist() == lists[1].tolist()
     assert oracle.intersect_k([lists[2], np.zeros(0, np.uint32)]).tolist() == []
+
+
+# ---------------------------------------------------- other differential forms
+
+MODES = {"D4": oracle.D4, "DM": oracle.DM, "D2": oracle.D2, "D1": oracle.D1}
+
+
+def mode_stream(mode, widths, rng, tail=()):
+    """synthetic_stream with the differential form in flag bits 1-2."""
+    enc = synthetic_stream(widths, rng, tail)
+    enc[6] = (mode << 1) & 0xFF
+    return enc
+
+
+@pytest.mark.parametrize("name", sorted(MODES))
+@pytest.mark.parametrize("b", [0, 1, 5, 17, 31, 32])
+def test_modes_random_access_matches_alg1_walk(name, b):
+    """The definition-based inverse and the Sec. 5 SIMD step lists (applied
+    per 4-vector in the Alg. 1 walk) agree on arbitrary payload bits."""
+    rng = np.random.default_rng(300 + b)
+    enc = mode_stream(MODES[name], [b, (b + 9) % 33, b], rng, tail=[1, 2, 3])
+    assert np.array_equal(oracle.decode(enc), oracle.decode_alg1(enc))
+
+
+def test_sec5_worked_prefix_steps():
+    """The Sec. 5 step lists, instantiated by hand (golden file): a stream
+    whose second 4-vector of deltas is (3, 5, 7, 11) after a first vector
+    decoding to (100, 110, 120, 130)."""
+    rows = {r[0]: [int(v) for v in r[1:]] for r in read_golden("sec5_prefix_steps.txt")}
+    prev, deltas = rows["prev"], rows["deltas"]
+    for name, mode in MODES.items():
+        # the list (x1..x8, then x8 repeated) encoded with the form must
+        # pack exactly the deltas (d5..d8) at positions 4..7 and decode back
+        x = np.array(prev + rows[name] + [rows[name][-1]] * 120, np.uint32)
+        enc = oracle.encode(x, mode)
+        got = oracle.decode(enc)
+        assert list(got[4:8]) == rows[name]
+        # the stream's packed deltas for positions 4..7 are the Sec. 5 deltas
+        d = payload_deltas(enc)
+        assert list(d[4:8]) == deltas, name
+
+
+def payload_deltas(enc, block=0):
+    """Unpack the packed values of one block with the pinned Fig. 2 layout:
+    lane j's words are 4m + j, read as one least-significant-first bit
+    stream."""
+    w = oracle.widths(enc)
+    b = int(w[block])
+    nb = header(enc)["nb"]
+    off = 32 + ((nb + 3) & ~3) + 16 * int(sum(int(v) for v in w[:block]))
+    words = struct.unpack_from(f"<{4 * b}I", enc.tobytes(), off) if b else ()
+    out = [0] * 128
+    for j in range(4):
+        stream = 0
+        for m in range(b):
+            stream |= words[4 * m + j] << (32 * m)
+        for q in range(32):
+            out[4 * q + j] = (stream >> (q * b)) & ((1 << b) - 1)
+    return out
+
+
+@pytest.mark.parametrize("c,s", [(7, 3), (1000, 255), (5, 1 << 20)])
+def test_modes_arithmetic_progression_widths(c, s):
+    """x_i = c + s i: after the first block every D1 delta is s, every D2
+    delta 2s, DM deltas are s, 2s, 3s, 4s within each quad, D4 deltas 4s."""
+    n = 128 * 4 + 3
+    x = (c + s * np.arange(n, dtype=np.uint64)).astype(np.uint32)
+    expect = {"D1": s, "D2": 2 * s, "DM": 4 * s, "D4": 4 * s}
+    for name, mode in MODES.items():
+        enc = oracle.encode(x, mode)
+        w = oracle.widths(enc)
+        assert all(int(b) == expect[name].bit_length() for b in w[1:]), name
+        assert np.array_equal(oracle.decode(enc), x)
+        d = payload_deltas(enc)
+        if name == "DM":
+            assert d[4:8] == [s, 2 * s, 3 * s, 4 * s]
+
+
+def test_table3_relative_delta_sizes():
+    """Table 3: the deltas of D2, DM and D4 are on average 2, 2.5 and 4
+    times those of D1 (a D1 delta spans one gap, D2 two, DM one to four,
+    D4 four), read back from the packed payload of every block."""
+    x = workloads.sorted_list(workloads.UNIFORM, 5, 1 << 30, 128 * 48)
+    mean = {}
+    for name, m in MODES.items():
+        enc = oracle.encode(x, m)
+        d = [v for k in range(1, 48) for v in payload_deltas(enc, k)]
+        mean[name] = float(np.mean(d))
+    for name, ratio in (("D2", 2.0), ("DM", 2.5), ("D4", 4.0)):
+        assert abs(mean[name] / mean["D1"] - ratio) < 0.05 * ratio, (name, mean)
+
+
+@pytest.mark.parametrize("name", sorted(MODES))
+@pytest.mark.parametrize("n", [0, 1, 5, 127, 128, 129, 2049, 70001])
+def test_modes_round_trip(name, n):
+    x = workloads.sorted_list(workloads.CLUSTERED, 900 + n, 1 << 26, n)
+    enc = oracle.encode(x, MODES[name])
+    assert header(enc)["flags"] >> 1 == MODES[name]
+    assert np.array_equal(oracle.decode(enc), x)
+    assert np.array_equal(oracle.decode_alg1(enc), x)
