@@ -153,6 +153,24 @@ def cpu_baseline(flat, offs, passes):
                       f"{threads} threads, {dt:.1f} s wall"}
 
 
+def delta_forms(s4, torch, flat, offs, outs, stream, steps, warmup):
+    """The bulk workload in each differential form (Sec. 5): payload bits per
+    integer and the single-launch decode rate."""
+    import numpy as np
+    res = {}
+    for name, delta in (("D4", s4.DELTA_D4), ("DM", s4.DELTA_DM), ("D2", s4.DELTA_D2), ("D1", s4.DELTA_D1)):
+        buf, soffs = s4.encode_many(flat, offs, delta=delta)
+        lists = [s4.DeviceList.upload(buf[int(soffs[i]): int(soffs[i + 1])]) for i in range(len(offs) - 1)]
+        n = float(sum(l.n for l in lists))
+        pb = float(sum(l.payload_bytes for l in lists))
+        plan = s4.DecodePlan(lists, outs)
+        ms, _ = time_graph(torch, lambda: plan.run(), stream, steps, warmup)
+        res[name] = {"bits_per_int": round(8 * pb / n, 3), "single_launch_gints": round(n / (ms / 1e3) / 1e9, 1),
+                     "single_launch_frac": round((pb + 4 * n) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del plan, lists
+    return res
+
+
 def batched(s4, workloads, torch, nq, plain_sample):
     """Batched pairwise / multi-term queries vs the plain per-query path."""
     import numpy as np
@@ -437,6 +455,9 @@ def main():
         "whole_job_hbm_frac": round(abytes.sum() / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "paper_context": "0.7 cycles/int, 5.4 Gint/s: Xeon E5-1620 3.6 GHz, 1 thread, cache-resident",
     }
+    if not args.decode_only:
+        result["delta_forms"] = delta_forms(s4, torch, flat, offs, outs, stream, 20, 3)
+        log(f"delta forms: {result['delta_forms']}")
     if not args.no_batched and not args.decode_only:
         try:
             result["batched"] = batched(s4, workloads, torch, args.batch_queries, args.plain_sample)

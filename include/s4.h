@@ -54,7 +54,8 @@ int s4_version(void); /* stream format version written by s4_encode (1) */
  *
  * Serialized S4-BP128-D4 stream (little-endian, all offsets in bytes):
  *   0  u32 magic 0x34443453 ("S4D4")      4  u16 version = 1
- *   6  u16 flags (bit 0: strictly increasing; other bits 0)
+ *   6  u16 flags (bit 0: strictly increasing; bits 1-2: differential form
+ *                 S4_DELTA_*; other bits 0)
  *   8  u64 n      16 u32 nb = floor(n/128)  20 u32 t = n - 128 nb
  *   24 u64 pw = sum over blocks of 4 b_k (payload 32-bit words)
  *   32 u8 widths[nb], zero-padded to a multiple of 4 bytes
@@ -64,9 +65,17 @@ int s4_version(void); /* stream format version written by s4_encode (1) */
  *                        least significant bit first (Sec. 4.2, Fig. 2)
  *      u32 tail[t]       the last t < 128 integers, raw (the paper uses
  *                        varint here, Sec. 4.3)
- * Width b_k is the smallest b with every D4 delta of block k below 2^b
- * (Sec. 4.3); D4 delta i is x_i - x_{i-4} with x_{-4..-1} = 0 (Sec. 5).
+ * Width b_k is the smallest b with every delta of block k below 2^b
+ * (Sec. 4.3).  Differential forms (Sec. 5; values before the list are 0):
+ *   S4_DELTA_D4  delta_i = x_i - x_{i-4}          (the default)
+ *   S4_DELTA_DM  delta_{4i+j} = x_{4i+j} - x_{4i-1}
+ *   S4_DELTA_D2  delta_i = x_i - x_{i-2}
+ *   S4_DELTA_D1  delta_i = x_i - x_{i-1}
  */
+#define S4_DELTA_D4 0u
+#define S4_DELTA_DM 1u
+#define S4_DELTA_D2 2u
+#define S4_DELTA_D1 3u
 
 /* Worst-case stream size for n integers (every block at b = 32). */
 size_t s4_encoded_bound(uint64_t n);
@@ -77,11 +86,15 @@ size_t s4_encoded_bound(uint64_t n);
  * decreases. Sec. 4.2-4.3, Sec. 5. */
 int s4_encode(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes);
 
-/* Encode `count` host lists in parallel: list i is in[in_offsets[i] ..
- * in_offsets[i+1]) and its stream is written to out + out_offsets[i], which
- * the caller sizes with s4_encoded_bound; out_bytes[i] receives each size.
- * nthreads <= 0 picks the number of hardware threads. */
-int s4_encode_many(const uint32_t *in, const uint64_t *in_offsets, uint64_t count, uint8_t *out,
+/* s4_encode with an explicit differential form (S4_DELTA_*). */
+int s4_encode_ex(const uint32_t *in, uint64_t n, uint32_t delta, uint8_t *out, size_t cap, size_t *out_bytes);
+
+/* Encode `count` host lists in parallel with differential form `delta`:
+ * list i is in[in_offsets[i] .. in_offsets[i+1]) and its stream is written
+ * to out + out_offsets[i], which the caller sizes with s4_encoded_bound;
+ * out_bytes[i] receives each size.  nthreads <= 0 picks the number of
+ * hardware threads. */
+int s4_encode_many(const uint32_t *in, const uint64_t *in_offsets, uint64_t count, uint32_t delta, uint8_t *out,
                    const uint64_t *out_offsets, uint64_t *out_bytes, int nthreads);
 
 /* Number of integers in a stream; validates the whole header and width
@@ -90,13 +103,17 @@ int s4_decoded_length(const uint8_t *enc, size_t bytes, uint64_t *n);
 
 /* ----------------------------------------------------------- device lists
  *
+ * Every device call below handles all four differential forms; lists of
+ * different forms can be mixed in one index, intersection or batch.
+ *
  * s4_list: one list resident in device memory, structure of arrays:
  * widths u8[nb], block word offsets u32[nb], payload u32[pw] (+32 bytes of
  * padding), raw tail u32[t], and a skip index built on the device at upload:
  * bmax[k] = x[128k + 127] (the block's largest value) and seed[k] =
- * x[128k-4 .. 128k-1] (zeros for k = 0), the D4 prefix seed that lets any
+ * x[128k-4 .. 128k-1] (zeros for k = 0), the prefix seed that lets any
  * block be decoded alone (Alg. 1 seeds each block with the previous
- * block's last four values).  The skip index is not part of the paper.
+ * block's last four values; D2 needs the last two, D1 and DM the last
+ * one).  The skip index is not part of the paper.
  */
 typedef struct s4_list s4_list;
 

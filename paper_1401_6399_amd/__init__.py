@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libs4.so")
 
 OK, EINVAL, EUNSORTED, ERANGE, ECORRUPT, ENOMEM, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
+DELTA_D4, DELTA_DM, DELTA_D2, DELTA_D1 = 0, 1, 2, 3
 
 # every symbol declared in include/s4.h, with (restype, argtypes)
 _vp = ctypes.c_void_p
@@ -58,7 +59,8 @@ SIGNATURES = {
     "s4_version": (_i, []),
     "s4_encoded_bound": (_sz, [_u64]),
     "s4_encode": (_i, [_u32p, _u64, _u8p, _sz, ctypes.POINTER(_sz)]),
-    "s4_encode_many": (_i, [_u32p, _u64p, _u64, _u8p, _u64p, _u64p, _i]),
+    "s4_encode_ex": (_i, [_u32p, _u64, _u32, _u8p, _sz, ctypes.POINTER(_sz)]),
+    "s4_encode_many": (_i, [_u32p, _u64p, _u64, _u32, _u8p, _u64p, _u64p, _i]),
     "s4_decoded_length": (_i, [_u8p, _sz, _u64p]),
     "s4_list_upload": (_i, [_u8p, _sz, _vp, ctypes.POINTER(_vp)]),
     "s4_list_free": (_i, [_vp]),
@@ -158,19 +160,19 @@ def encoded_bound(n: int) -> int:
     return int(require_library().s4_encoded_bound(n))
 
 
-def encode(x) -> np.ndarray:
-    """Host encode of a non-decreasing uint32 list (s4_encode)."""
+def encode(x, delta: int = DELTA_D4) -> np.ndarray:
+    """Host encode of a non-decreasing uint32 list (s4_encode_ex)."""
     lib = require_library()
     x = np.ascontiguousarray(x, dtype=np.uint32)
     cap = encoded_bound(x.size)
     out = np.zeros(cap, dtype=np.uint8)
     nbytes = ctypes.c_size_t(0)
-    _check(lib.s4_encode(_ptr(x, ctypes.c_uint32), x.size, _ptr(out, ctypes.c_uint8), cap,
-                         ctypes.byref(nbytes)), "s4_encode")
+    _check(lib.s4_encode_ex(_ptr(x, ctypes.c_uint32), x.size, delta, _ptr(out, ctypes.c_uint8), cap,
+                            ctypes.byref(nbytes)), "s4_encode_ex")
     return out[: nbytes.value].copy()
 
 
-def encode_many(flat, offsets, nthreads: int = 0):
+def encode_many(flat, offsets, nthreads: int = 0, delta: int = DELTA_D4):
     """Encode many lists at once: returns (streams buffer, stream offsets)."""
     lib = require_library()
     flat = np.ascontiguousarray(flat, dtype=np.uint32)
@@ -183,7 +185,7 @@ def encode_many(flat, offsets, nthreads: int = 0):
     buf = np.zeros(max(1, int(out_offs[-1])), dtype=np.uint8)
     sizes = np.zeros(max(1, count), dtype=np.uint64)
     _check(lib.s4_encode_many(_ptr(flat if flat.size else np.zeros(1, np.uint32), ctypes.c_uint32),
-                              _ptr(offsets, ctypes.c_uint64), count, _ptr(buf, ctypes.c_uint8),
+                              _ptr(offsets, ctypes.c_uint64), count, delta, _ptr(buf, ctypes.c_uint8),
                               _ptr(out_offs, ctypes.c_uint64), _ptr(sizes, ctypes.c_uint64), nthreads),
            "s4_encode_many")
     # compact the streams back to back

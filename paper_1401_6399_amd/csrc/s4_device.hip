@@ -74,21 +74,19 @@ static int get_pool(StreamPool **out) {
 
 // ----------------------------------------------------------------- kernels
 
-// Per-lane sums of the D4 deltas of every block (one 16-lane row per
-// block), written into the seeds array as a first pass of the skip index.
-// Blocks are numbered globally over `nlists` lists; blk_prefix[l] is the
-// first global block of list l, pay_base[l] its first payload word.
-__global__ __launch_bounds__(256) void k_block_sums(const uint8_t *__restrict__ widths,
-                                                    const uint32_t *__restrict__ offs,
-                                                    const uint32_t *__restrict__ payload,
-                                                    const uint64_t *__restrict__ blk_prefix,
-                                                    const uint64_t *__restrict__ pay_base, uint32_t nlists,
+// First pass of the skip index: every block decoded with a zero seed (one
+// 16-lane row per block); its last four values are written into the seeds
+// array.  Blocks are numbered globally over `nlists` lists; blk_prefix[l]
+// is the first global block of list l.
+__global__ __launch_bounds__(256) void k_block_sums(const DList *__restrict__ lists,
+                                                    const uint64_t *__restrict__ blk_prefix, uint32_t nlists,
                                                     uint64_t total_blocks, uint4 *__restrict__ sums) {
   const uint32_t lane = lane_id();
   const uint64_t wave = uint64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint64_t g = wave * 4 + (lane >> 4);
   const bool active = g < total_blocks;
   uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
+  uint32_t mode = S4_DELTA_D4;
   if (active) {
     // list of block g: last l with blk_prefix[l] <= g
     uint32_t lo = 0, hi = nlists;
@@ -96,41 +94,82 @@ __global__ __launch_bounds__(256) void k_block_sums(const uint8_t *__restrict__ 
       uint32_t mid = (lo + hi) >> 1;
       if (blk_prefix[mid] <= g) lo = mid; else hi = mid;
     }
-    extract_row(payload + pay_base[lo] + offs[g], widths[g], lane & 15u, d0, d1);
+    const DList &L = lists[lo];
+    const uint32_t k = uint32_t(g - blk_prefix[lo]);
+    mode = L.mode;
+    extract_row(L.payload + L.offs[k], L.widths[k], lane & 15u, d0, d1);
   }
-  uint32_t t[4];
+  // rows of one wave may belong to lists of different forms: evaluate each
+  // form the wave holds (row scans keep the rows apart)
+  uint32_t x0[4], x1[4], y0[4], y1[4];
+  const uint32_t zero[4] = {0, 0, 0, 0};
+  for (uint32_t m = 0; m < 4; ++m) {
+    const uint64_t any = __ballot(active && mode == m);
+    if (!any) continue;
+    prefix_deltas<true>(m, d0, d1, zero, y0, y1);
+    if (mode == m) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) t[j] = scan_row16(d0[j] + d1[j]);
-  if (active && (lane & 15u) == 15u) sums[g] = make_uint4(t[0], t[1], t[2], t[3]);
+      for (int j = 0; j < 4; ++j) {
+        x0[j] = y0[j];
+        x1[j] = y1[j];
+      }
+    }
+  }
+  if (active && (lane & 15u) == 15u) sums[g] = make_uint4(x1[0], x1[1], x1[2], x1[3]);
 }
 
-// Second pass: one wave per list turns per-block lane sums into seeds
-// (exclusive prefix over the list's blocks) and bmax (the block's last
-// value, lane 3 of the inclusive prefix).
-__global__ __launch_bounds__(256) void k_seed_scan(const uint64_t *__restrict__ blk_prefix, uint32_t nlists,
+// Second pass: one wave per list turns the zero-seed last values s_k of
+// every block into seeds (the last four values before block k) and bmax.
+// Block k's true last values are s_k plus the carry of its form: each
+// component's own running sum (D4), the running sum of component 3 (D1,
+// DM: one chain), or of components 2 / 3 by parity (D2).  Each lane writes
+// only its own block's entries (reading them first), so the pass works in
+// place over the seeds array.
+__global__ __launch_bounds__(256) void k_seed_scan(const DList *__restrict__ lists,
+                                                   const uint64_t *__restrict__ blk_prefix, uint32_t nlists,
                                                    uint4 *__restrict__ seeds, uint32_t *__restrict__ bmax) {
   const uint32_t lane = lane_id();
   const uint32_t list = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (list >= nlists) return;
+  const uint32_t mode = lists[list].mode;
   const uint64_t b0 = blk_prefix[list], b1 = blk_prefix[list + 1];
-  uint32_t carry[4] = {0, 0, 0, 0};
+  uint32_t carry[4] = {0, 0, 0, 0};   // running sums of each component
+  uint32_t last[4] = {0, 0, 0, 0};    // last four values of the previous chunk
   for (uint64_t base = b0; base < b1; base += 64) {
     const uint64_t g = base + lane;
     uint4 v = make_uint4(0, 0, 0, 0);
     if (g < b1) v = seeds[g];
-    const uint32_t vv[4] = {v.x, v.y, v.z, v.w};
+    const uint32_t sv[4] = {v.x, v.y, v.z, v.w};
     uint32_t inc[4], exc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      inc[j] = scan_wave64(vv[j]);
-      exc[j] = carry[j] + inc[j] - vv[j];
+      inc[j] = scan_wave64(sv[j]);
+      exc[j] = carry[j] + inc[j] - sv[j];
+    }
+    uint32_t out[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint32_t c;
+      if (mode == S4_DELTA_D4) c = exc[j];
+      else if (mode == S4_DELTA_D2) c = (j & 1) ? exc[3] : exc[2];
+      else c = exc[3];
+      out[j] = c + sv[j];
+    }
+    uint32_t prev[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      prev[j] = __shfl_up(out[j], 1);
+      if (lane == 0) prev[j] = last[j];
     }
     if (g < b1) {
-      seeds[g] = make_uint4(exc[0], exc[1], exc[2], exc[3]);
-      bmax[g] = carry[3] + inc[3];
+      seeds[g] = make_uint4(prev[0], prev[1], prev[2], prev[3]);
+      bmax[g] = out[3];
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) carry[j] += uint32_t(__builtin_amdgcn_readlane(int(inc[j]), 63));
+    for (int j = 0; j < 4; ++j) {
+      carry[j] += uint32_t(__builtin_amdgcn_readlane(int(inc[j]), 63));
+      last[j] = uint32_t(__builtin_amdgcn_readlane(int(out[j]), 63));
+    }
   }
 }
 
@@ -179,12 +218,7 @@ __device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint
   for (int p = 0; p < P; ++p) {
     const uint32_t k0 = kbase + 4u * p;
     uint32_t x0[4], x1[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t sc = scan_wave64(d0[p][j] + d1[p][j]);
-      x1[j] = c[j] + sc;
-      x0[j] = x1[j] - d1[p][j];
-    }
+    prefix_deltas<false>(L.mode, d0[p], d1[p], c, x0, x1);
 #pragma unroll
     for (int j = 0; j < 4; ++j) c[j] = uint32_t(__builtin_amdgcn_readlane(int(x1[j]), 63));
     u32x4 *t = reinterpret_cast<u32x4 *>(tb + row * kBlock + 8u * i);
@@ -402,6 +436,8 @@ static DList make_desc(const Upload &u, size_t i, char *base) {
   d.n = u.views[i].n;
   d.nb = u.views[i].nb;
   d.t = u.views[i].t;
+  d.mode = (u.views[i].flags >> 1) & 3u;
+  d.pad_ = 0;
   return d;
 }
 
@@ -452,13 +488,11 @@ int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DLi
     const uint64_t waves = (u.total_blocks + 3) / 4;
     const uint64_t groups = (waves + 3) / 4;
     hipLaunchKernelGGL(k_block_sums, dim3(uint32_t(groups)), dim3(256), 0, stream,
-                       reinterpret_cast<const uint8_t *>(dev + a.widths_off),
-                       reinterpret_cast<const uint32_t *>(dev + a.offs_off),
-                       reinterpret_cast<const uint32_t *>(dev + a.payload_off),
-                       reinterpret_cast<const uint64_t *>(dev + a.blkpre_off),
-                       reinterpret_cast<const uint64_t *>(dev + a.blkpre_off + sizeof(uint64_t) * (L + 1)),
-                       uint32_t(L), u.total_blocks, reinterpret_cast<uint4 *>(dev + a.seeds_off));
+                       reinterpret_cast<const DList *>(dev + a.desc_off),
+                       reinterpret_cast<const uint64_t *>(dev + a.blkpre_off), uint32_t(L), u.total_blocks,
+                       reinterpret_cast<uint4 *>(dev + a.seeds_off));
     hipLaunchKernelGGL(k_seed_scan, dim3(uint32_t((L + 3) / 4)), dim3(256), 0, stream,
+                       reinterpret_cast<const DList *>(dev + a.desc_off),
                        reinterpret_cast<const uint64_t *>(dev + a.blkpre_off), uint32_t(L),
                        reinterpret_cast<uint4 *>(dev + a.seeds_off), reinterpret_cast<uint32_t *>(dev + a.bmax_off));
     e = hipGetLastError();

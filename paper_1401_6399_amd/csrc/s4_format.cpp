@@ -57,8 +57,20 @@ static void pack_block(const uint32_t *d, uint32_t b, uint32_t *words) {
   }
 }
 
-int encode_one(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes) {
+// The value a differential form subtracts from x_i (Sec. 5); values before
+// the list are 0.
+static inline uint32_t reference(const uint32_t *in, uint64_t i, uint32_t delta) {
+  switch (delta) {
+    case S4_DELTA_D1: return i >= 1 ? in[i - 1] : 0u;
+    case S4_DELTA_D2: return i >= 2 ? in[i - 2] : 0u;
+    case S4_DELTA_DM: return i >= 4 ? in[(i & ~uint64_t(3)) - 1] : 0u;
+    default: return i >= 4 ? in[i - 4] : 0u;
+  }
+}
+
+int encode_one(const uint32_t *in, uint64_t n, uint32_t delta, uint8_t *out, size_t cap, size_t *out_bytes) {
   if ((!in && n) || !out_bytes) return fail(S4_EINVAL, "s4_encode: null argument");
+  if (delta > S4_DELTA_D1) return fail(S4_EINVAL, "s4_encode: unknown differential form");
   if (n / kBlock > 0xFFFFFFFFull) return fail(S4_EINVAL, "s4_encode: list too long");
   bool strictly = true;
   for (uint64_t i = 1; i < n; ++i) {
@@ -72,11 +84,7 @@ int encode_one(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t 
   for (uint64_t k = 0; k < nb; ++k) {
     const uint32_t *x = in + k * kBlock;
     uint32_t any = 0;
-    for (uint32_t p = 0; p < kBlock; ++p) {
-      uint64_t i = k * kBlock + p;
-      uint32_t prev = i >= 4 ? in[i - 4] : 0u;
-      any |= x[p] - prev;
-    }
+    for (uint32_t p = 0; p < kBlock; ++p) any |= x[p] - reference(in, k * kBlock + p, delta);
     uint32_t b = any ? 32u - uint32_t(__builtin_clz(any)) : 0u;
     widths[k] = uint8_t(b);
     pw += 4u * b;
@@ -86,7 +94,7 @@ int encode_one(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t 
   if (!out || cap < need) return fail(S4_ERANGE, "s4_encode: output buffer too small");
   std::memset(out, 0, kHeaderBytes + round4(nb));
   wr32(out, kMagic);
-  uint16_t ver = kVersion, fl = strictly ? 1 : 0;
+  uint16_t ver = kVersion, fl = uint16_t((strictly ? 1u : 0u) | (delta << 1));
   std::memcpy(out + 4, &ver, 2);
   std::memcpy(out + 6, &fl, 2);
   std::memcpy(out + 8, &n, 8);
@@ -100,10 +108,7 @@ int encode_one(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t 
   uint32_t words[4 * 32];
   size_t wpos = 0;
   for (uint64_t k = 0; k < nb; ++k) {
-    for (uint32_t p = 0; p < kBlock; ++p) {
-      uint64_t i = k * kBlock + p;
-      d[p] = in[i] - (i >= 4 ? in[i - 4] : 0u);
-    }
+    for (uint32_t p = 0; p < kBlock; ++p) d[p] = in[k * kBlock + p] - reference(in, k * kBlock + p, delta);
     const uint32_t b = widths[k];
     pack_block(d, b, words);
     std::memcpy(payload + 4 * wpos, words, 16u * b);
@@ -121,7 +126,7 @@ int parse_stream(const uint8_t *enc, size_t bytes, StreamView *v) {
   std::memcpy(&ver, enc + 4, 2);
   std::memcpy(&fl, enc + 6, 2);
   if (ver != kVersion) return fail(S4_ECORRUPT, "unknown stream version");
-  if (fl & ~1u) return fail(S4_ECORRUPT, "unknown flag bits");
+  if (fl & ~7u) return fail(S4_ECORRUPT, "unknown flag bits");
   std::memcpy(&v->n, enc + 8, 8);
   std::memcpy(&v->nb, enc + 16, 4);
   std::memcpy(&v->t, enc + 20, 4);
@@ -159,10 +164,14 @@ int s4_version(void) { return int(kVersion); }
 size_t s4_encoded_bound(uint64_t n) { return stream_bound(n); }
 
 int s4_encode(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes) {
-  return encode_one(in, n, out, cap, out_bytes);
+  return encode_one(in, n, S4_DELTA_D4, out, cap, out_bytes);
 }
 
-int s4_encode_many(const uint32_t *in, const uint64_t *in_offsets, uint64_t count, uint8_t *out,
+int s4_encode_ex(const uint32_t *in, uint64_t n, uint32_t delta, uint8_t *out, size_t cap, size_t *out_bytes) {
+  return encode_one(in, n, delta, out, cap, out_bytes);
+}
+
+int s4_encode_many(const uint32_t *in, const uint64_t *in_offsets, uint64_t count, uint32_t delta, uint8_t *out,
                    const uint64_t *out_offsets, uint64_t *out_bytes, int nthreads) {
   if (!in_offsets || !out_offsets || !out_bytes || (count && (!in || !out)))
     return fail(S4_EINVAL, "s4_encode_many: null argument");
@@ -178,7 +187,7 @@ int s4_encode_many(const uint32_t *in, const uint64_t *in_offsets, uint64_t coun
       uint64_t n = in_offsets[i + 1] - in_offsets[i];
       size_t cap = size_t(out_offsets[i + 1] - out_offsets[i]);
       size_t nbytes = 0;
-      int rc = encode_one(in + in_offsets[i], n, out + out_offsets[i], cap, &nbytes);
+      int rc = encode_one(in + in_offsets[i], n, delta, out + out_offsets[i], cap, &nbytes);
       out_bytes[i] = nbytes;
       if (rc) {
         int expected = 0;

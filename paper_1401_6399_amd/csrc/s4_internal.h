@@ -31,6 +31,8 @@ struct DList {
   uint64_t n;
   uint32_t nb;
   uint32_t t;
+  uint32_t mode;  // differential form, S4_DELTA_*
+  uint32_t pad_;
 };
 
 // Parsed header of a serialized stream (host).
@@ -55,7 +57,7 @@ int hip_fail(hipError_t e, const char *what);
 // format (s4_format.cpp)
 int parse_stream(const uint8_t *enc, size_t bytes, StreamView *v);
 size_t stream_bound(uint64_t n);
-int encode_one(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes);
+int encode_one(const uint32_t *in, uint64_t n, uint32_t delta, uint8_t *out, size_t cap, size_t *out_bytes);
 
 // device (s4_device.hip)
 int ensure_device();

@@ -118,10 +118,73 @@ __device__ __forceinline__ void extract_row(const uint32_t *__restrict__ blk, ui
   d1[3] = funnel(hi.w, lo.w, s1) & mask;
 }
 
-// Decode block k of L with one 16-lane row per block: extract, scan each
-// lane j over q within the row (integrated D4 prefix sum, Alg. 1 with
-// P(t, v) = t + v), add the block's seed from the skip index.  Rows whose
-// `active` is false compute zeros.  All 64 lanes must call this together.
+// Inverse differential coding (Sec. 5) of the row layout: lane i holds the
+// deltas of block positions 8i .. 8i + 3 (d0) and 8i + 4 .. 8i + 7 (d1);
+// `seed` holds the four values just before the lanes' span (the previous
+// block's last four values, or the carry of the previous pass).  The scans
+// run over a 16-lane row (ROW, one block) or over the whole wave (four
+// consecutive blocks).  Per form:
+//   D4  each residue class j mod 4 is one chain: scan of d0[j] + d1[j];
+//   D1  one chain through every position: lane totals scanned once;
+//   D2  even and odd positions are two chains: two scans;
+//   DM  the quad ends (positions 4q + 3) form one chain; the other values
+//       of a quad add their delta to the previous quad end.
+template <bool ROW>
+__device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4], const uint32_t d1[4],
+                                              const uint32_t seed[4], uint32_t x0[4], uint32_t x1[4]) {
+  auto scan = [](uint32_t v) { return ROW ? scan_row16(v) : scan_wave64(v); };
+  if (mode == S4_DELTA_D1) {
+    uint32_t l[8];
+    l[0] = d0[0];
+    l[1] = l[0] + d0[1];
+    l[2] = l[1] + d0[2];
+    l[3] = l[2] + d0[3];
+    l[4] = l[3] + d1[0];
+    l[5] = l[4] + d1[1];
+    l[6] = l[5] + d1[2];
+    l[7] = l[6] + d1[3];
+    const uint32_t base = seed[3] + scan(l[7]) - l[7];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x0[j] = base + l[j];
+      x1[j] = base + l[4 + j];
+    }
+  } else if (mode == S4_DELTA_D2) {
+    const uint32_t e0 = d0[0], e1 = e0 + d0[2], e2 = e1 + d1[0], e3 = e2 + d1[2];
+    const uint32_t o0 = d0[1], o1 = o0 + d0[3], o2 = o1 + d1[1], o3 = o2 + d1[3];
+    const uint32_t be = seed[2] + scan(e3) - e3;
+    const uint32_t bo = seed[3] + scan(o3) - o3;
+    x0[0] = be + e0;
+    x0[1] = bo + o0;
+    x0[2] = be + e1;
+    x0[3] = bo + o1;
+    x1[0] = be + e2;
+    x1[1] = bo + o2;
+    x1[2] = be + e3;
+    x1[3] = bo + o3;
+  } else if (mode == S4_DELTA_DM) {
+    const uint32_t tot = d0[3] + d1[3];
+    const uint32_t y0 = seed[3] + scan(tot) - tot;  // quad end before position 8i
+    const uint32_t y1 = y0 + d0[3];                   // quad end before position 8i + 4
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x0[j] = y0 + d0[j];
+      x1[j] = y1 + d1[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t sc = scan(d0[j] + d1[j]);
+      x1[j] = seed[j] + sc;
+      x0[j] = x1[j] - d1[j];
+    }
+  }
+}
+
+// Decode block k of L with one 16-lane row per block: extract, then the
+// integrated prefix sum of the list's differential form (Alg. 1 with the
+// form's P(t, v)) seeded from the skip index.  Rows whose `active` is
+// false compute zeros.  All 64 lanes must call this together.
 __device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool active, uint32_t i,
                                            uint32_t x0[4], uint32_t x1[4]) {
   uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
@@ -131,17 +194,12 @@ __device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool acti
     seed = L.seeds[k];
   }
   const uint32_t sv[4] = {seed.x, seed.y, seed.z, seed.w};
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const uint32_t s = scan_row16(d0[j] + d1[j]);
-    x1[j] = sv[j] + s;
-    x0[j] = x1[j] - d1[j];
-  }
+  prefix_deltas<true>(L.mode, d0, d1, sv, x0, x1);
 }
 
-// Decode block k of L with the whole wave (half-wave layout): lane l takes
-// q = l mod 32 and lanes j0 = 2 (l div 32), j0 + 1; the two half-waves scan
-// over q.  Writes the 128 values to dst[0..127].
+// Decode block k of L (a D4 list) with the whole wave (half-wave layout):
+// lane l takes q = l mod 32 and lanes j0 = 2 (l div 32), j0 + 1; the two
+// half-waves scan over q.  Writes the 128 values to dst[0..127].
 __device__ __forceinline__ void decode_block_wave(const DList &L, uint32_t k, uint32_t *dst) {
   const uint32_t l = lane_id();
   const uint32_t q = l & 31u, j0 = (l >> 5) * 2u;
@@ -206,7 +264,18 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     if (lane + 64 < cnt) s.r[lane + 64] = r.raw[base + 64 + lane];
   } else if (item < r.L.nb) {
     cnt = kBlock;
-    decode_block_wave(r.L, item, s.r);
+    if (r.L.mode == S4_DELTA_D4) {
+      decode_block_wave(r.L, item, s.r);
+    } else {
+      // other forms: row 0 decodes the block in the row layout
+      uint32_t x0[4], x1[4];
+      const uint32_t ri = lane & 15u;
+      decode_row(r.L, item, lane < 16, ri, x0, x1);
+      if (lane < 16) {
+        *reinterpret_cast<uint4 *>(&s.r[8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
+        *reinterpret_cast<uint4 *>(&s.r[8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
+      }
+    }
   } else {
     cnt = item == r.L.nb ? r.L.t : 0u;
     if (lane < cnt) s.r[lane] = r.L.tail[lane];

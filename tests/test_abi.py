@@ -88,3 +88,27 @@ def test_tuning_validation():
         s4.set_tuning(waves_per_group=3)
     s4.set_tuning(**t.as_dict())
     assert s4.get_tuning().as_dict() == t.as_dict()
+
+
+@pytest.mark.parametrize("delta", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [0, 5, 128, 129, 4097, 70001])
+def test_encode_forms_match_oracle(delta, n):
+    x = workloads.sorted_list(workloads.CLUSTERED, 400 + n, 1 << 26, n)
+    assert np.array_equal(s4.encode(x, delta), oracle.encode(x, delta))
+
+
+def test_encode_many_forms_match_oracle():
+    kinds, lens = workloads.bulk_lengths(8)
+    lens = (lens // 32).astype(np.uint64)
+    flat, offs = workloads.lists(kinds, lens, 98, 1 << 26)
+    for delta in range(4):
+        buf, soffs = s4.encode_many(flat, offs, nthreads=3, delta=delta)
+        for i in range(len(lens)):
+            x = flat[int(offs[i]): int(offs[i + 1])]
+            assert np.array_equal(buf[int(soffs[i]): int(soffs[i + 1])], oracle.encode(x, delta))
+
+
+def test_encode_rejects_unknown_form():
+    with pytest.raises(s4.S4Error) as e:
+        s4.encode(np.arange(10, dtype=np.uint32), 4)
+    assert e.value.code == s4.EINVAL
