@@ -189,9 +189,9 @@ constexpr uint32_t kPassWords = 4u * kBlock;
 //  3. The pass's 512 values go through the wave's LDS slice so that each
 //     store instruction writes 1 KiB of contiguous output (lane l stores
 //     values 4l .. 4l + 3 of each half): whole cache lines per instruction.
-template <int P>
-__device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
-                                            uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
+template <int P, uint32_t MODE>
+__device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
+                                                 uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
   static_assert(P >= 1 && P <= 16, "4 P blocks per wave must fit 64 lanes");
   const uint32_t lane = lane_id();
   const uint32_t row = lane >> 4, i = lane & 15u;
@@ -218,7 +218,7 @@ __device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint
   for (int p = 0; p < P; ++p) {
     const uint32_t k0 = kbase + 4u * p;
     uint32_t x0[4], x1[4];
-    prefix_deltas<false>(L.mode, d0[p], d1[p], c, x0, x1);
+    prefix_form<false, MODE>(d0[p], d1[p], c, x0, x1);
 #pragma unroll
     for (int j = 0; j < 4; ++j) c[j] = uint32_t(__builtin_amdgcn_readlane(int(x1[j]), 63));
     u32x4 *t = reinterpret_cast<u32x4 *>(tb + row * kBlock + 8u * i);
@@ -231,6 +231,19 @@ __device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint
     uint32_t *dst = out + uint64_t(k0 - first) * kBlock + 4u * lane;
     if (k0 + (lane >> 5) < full_end) store4(dst, y0);
     if (k0 + 2u + (lane >> 5) < full_end) store4(dst + 256, y1);
+  }
+}
+
+// Dispatch once per wave on the list's differential form, so each variant
+// of the unrolled passes is straight-line code.
+template <int P>
+__device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
+                                            uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
+  switch (uniform(L.mode)) {
+    case S4_DELTA_D1: decode_wave_form<P, S4_DELTA_D1>(L, first, full_end, kbase, out, tb); break;
+    case S4_DELTA_D2: decode_wave_form<P, S4_DELTA_D2>(L, first, full_end, kbase, out, tb); break;
+    case S4_DELTA_DM: decode_wave_form<P, S4_DELTA_DM>(L, first, full_end, kbase, out, tb); break;
+    default: decode_wave_form<P, S4_DELTA_D4>(L, first, full_end, kbase, out, tb); break;
   }
 }
 

@@ -129,11 +129,11 @@ __device__ __forceinline__ void extract_row(const uint32_t *__restrict__ blk, ui
 //   D2  even and odd positions are two chains: two scans;
 //   DM  the quad ends (positions 4q + 3) form one chain; the other values
 //       of a quad add their delta to the previous quad end.
-template <bool ROW>
-__device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4], const uint32_t d1[4],
-                                              const uint32_t seed[4], uint32_t x0[4], uint32_t x1[4]) {
+template <bool ROW, uint32_t MODE>
+__device__ __forceinline__ void prefix_form(const uint32_t d0[4], const uint32_t d1[4], const uint32_t seed[4],
+                                            uint32_t x0[4], uint32_t x1[4]) {
   auto scan = [](uint32_t v) { return ROW ? scan_row16(v) : scan_wave64(v); };
-  if (mode == S4_DELTA_D1) {
+  if (MODE == S4_DELTA_D1) {
     uint32_t l[8];
     l[0] = d0[0];
     l[1] = l[0] + d0[1];
@@ -149,7 +149,7 @@ __device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4
       x0[j] = base + l[j];
       x1[j] = base + l[4 + j];
     }
-  } else if (mode == S4_DELTA_D2) {
+  } else if (MODE == S4_DELTA_D2) {
     const uint32_t e0 = d0[0], e1 = e0 + d0[2], e2 = e1 + d1[0], e3 = e2 + d1[2];
     const uint32_t o0 = d0[1], o1 = o0 + d0[3], o2 = o1 + d1[1], o3 = o2 + d1[3];
     const uint32_t be = seed[2] + scan(e3) - e3;
@@ -162,7 +162,7 @@ __device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4
     x1[1] = bo + o2;
     x1[2] = be + e3;
     x1[3] = bo + o3;
-  } else if (mode == S4_DELTA_DM) {
+  } else if (MODE == S4_DELTA_DM) {
     const uint32_t tot = d0[3] + d1[3];
     const uint32_t y0 = seed[3] + scan(tot) - tot;  // quad end before position 8i
     const uint32_t y1 = y0 + d0[3];                   // quad end before position 8i + 4
@@ -178,6 +178,18 @@ __device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4
       x1[j] = seed[j] + sc;
       x0[j] = x1[j] - d1[j];
     }
+  }
+}
+
+// The same with the form known only at run time (uniform across the wave).
+template <bool ROW>
+__device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4], const uint32_t d1[4],
+                                              const uint32_t seed[4], uint32_t x0[4], uint32_t x1[4]) {
+  switch (mode) {
+    case S4_DELTA_D1: prefix_form<ROW, S4_DELTA_D1>(d0, d1, seed, x0, x1); break;
+    case S4_DELTA_D2: prefix_form<ROW, S4_DELTA_D2>(d0, d1, seed, x0, x1); break;
+    case S4_DELTA_DM: prefix_form<ROW, S4_DELTA_DM>(d0, d1, seed, x0, x1); break;
+    default: prefix_form<ROW, S4_DELTA_D4>(d0, d1, seed, x0, x1); break;
   }
 }
 
