@@ -189,6 +189,7 @@ def batched(s4, workloads, torch, nq, plain_sample):
         stream = torch.cuda.Stream()
         ms, _ = time_graph(torch, lambda: b.run(use_graph=False), stream, steps=5, warmup=2)
         ticks = b.query_ticks().astype(np.float64) / 100.0  # 100 MHz clock -> us
+        abytes, ablocks = b.traffic()
         # plain path: one intersect_k call per query, on a sample
         lists = [index.list(i) for i in range(index.count)] if name == "pairwise" else lists
         sample = np.arange(min(plain_sample, b.nq))
@@ -221,6 +222,10 @@ def batched(s4, workloads, torch, nq, plain_sample):
             "plain_p50_us": round(float(np.percentile(lat, 50)), 1),
             "plain_p99_us": round(float(np.percentile(lat, 99)), 1),
             "speedup_vs_plain": round((b.nq / (ms / 1e3)) / (sample.size / plain_s), 2),
+            "algorithmic_mb": round(abytes / 1e6, 2),
+            "blocks_decoded": int(ablocks),
+            "achieved_gbs": round(abytes / (ms / 1e3) / 1e9, 1),
+            "hbm_frac": round(abytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "tuning": best,
         }
         log(f"{name}: {out[name]}")

@@ -278,6 +278,12 @@ int s4_batch_run(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offsets, u
  * ticks[nq].  Synchronises `stream`. */
 int s4_batch_query_ticks(const s4_batch *batch, uint64_t *ticks, void *stream);
 
+/* Algorithmic traffic of the last run: bytes = packed payload, width byte,
+ * block offset and seed of every block decoded, skip-index entries staged,
+ * raw values read, plus 4 bytes per result; blocks = blocks decoded.
+ * Synchronises `stream`. */
+int s4_batch_traffic(const s4_batch *batch, uint64_t *bytes, uint64_t *blocks, void *stream);
+
 /* Autotune gallop_blocks / waves_per_group / groups_per_cu / items_per_grab
  * on this plan: times `reps` runs per candidate setting, keeps the fastest
  * and installs it with s4_set_tuning.  best_ms receives its time.  The

@@ -93,6 +93,7 @@ SIGNATURES = {
     "s4_batch_results_bound": (_u64, [_vp]),
     "s4_batch_run": (_i, [_vp, _vp, _vp, _vp, _u64, _i, _vp]),
     "s4_batch_query_ticks": (_i, [_vp, _u64p, _vp]),
+    "s4_batch_traffic": (_i, [_vp, _u64p, _u64p, _vp]),
     "s4_batch_autotune": (_i, [_vp, _vp, _vp, _vp, _u64, _i, _vp, ctypes.POINTER(Tuning),
                                ctypes.POINTER(ctypes.c_double)]),
     "s4_server_create": (_i, [_vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
@@ -470,6 +471,13 @@ class Batch:
         _check(require_library().s4_batch_query_ticks(self.h, _ptr(t, ctypes.c_uint64), _stream(stream)),
                "s4_batch_query_ticks")
         return t[: self.nq]
+
+    def traffic(self, stream=None):
+        """(algorithmic bytes, blocks decoded) of the last run."""
+        b, k = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(require_library().s4_batch_traffic(self.h, ctypes.byref(b), ctypes.byref(k), _stream(stream)),
+               "s4_batch_traffic")
+        return b.value, k.value
 
     def autotune(self, reps=3, stream=None):
         best = Tuning()

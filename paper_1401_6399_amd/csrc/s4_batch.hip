@@ -18,6 +18,8 @@ __global__ void k_batch_begin(BatchDev b) {
   if (t == 0) {
     *b.head = 0;
     *b.start = wall_clock64();
+    b.stats[0] = 0;
+    b.stats[1] = 0;
   }
   for (uint32_t q = t; q < b.nq; q += gridDim.x * blockDim.x) b.qtick[q] = 0;
 }
@@ -31,6 +33,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   const uint64_t t0 = *b.start;
+  Traffic tr;
+  // completion stamps: one atomic per run of consecutive chunks of a query
+  uint32_t run_q = kInvalid;
+  uint64_t run_t = 0;
   for (;;) {
     uint32_t it0 = 0;
     if (lane == 0) it0 = atomicAdd(b.head, grab);
@@ -38,21 +44,35 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_
     if (it0 >= b.items) break;
     const uint32_t it1 = min(it0 + grab, b.items);
     for (uint32_t item = it0; item < it1; ++item) {
-      const uint32_t q = uniform(b.item_query[item]);
-      const uint32_t local = item - b.item_base[q];
-      const uint32_t tq = b.qoff[q];
-      const uint32_t k = b.qoff[q + 1] - tq;
+      // one record per chunk: query, chunk within the query, first term, terms
+      const uint4 info = b.item_info[item];
+      const uint32_t q = uniform(info.x), local = uniform(info.y), tq = uniform(info.z), k = uniform(info.w);
+      // the two shortest lists' descriptors, loaded together up front
+      const uint32_t id0 = b.sterms[tq], id1 = b.sterms[tq + (k > 1 ? 1 : 0)];
       RSide r;
-      r.L = b.lists[b.sterms[tq]];
+      r.L = b.lists[id0];
+      const DList f1 = b.lists[id1];
       r.raw = nullptr;
       r.len = r.L.n;
       const uint32_t cnt = chain_chunk(
-          r, local, [&](uint32_t j) -> DList { return b.lists[b.sterms[tq + 1 + j]]; }, k - 1, lds[w],
-          gallop_blocks);
+          r, local, [&](uint32_t j) -> DList { return j == 0 ? f1 : b.lists[b.sterms[tq + 1 + j]]; }, k - 1,
+          lds[w], gallop_blocks, tr);
       store_chunk(cnt, lds[w], b.stage + uint64_t(item) * kBlock, b.counts + item);
-      if (lane == 0) atomicMax(reinterpret_cast<unsigned long long *>(b.qtick + q),
-                               static_cast<unsigned long long>(wall_clock64() - t0));
+      const uint64_t now = wall_clock64() - t0;
+      if (q != run_q) {
+        if (run_q != kInvalid && lane == 0)
+          atomicMax(reinterpret_cast<unsigned long long *>(b.qtick + run_q), static_cast<unsigned long long>(run_t));
+        run_q = q;
+      }
+      run_t = now;
     }
+    if (run_q != kInvalid && lane == 0)
+      atomicMax(reinterpret_cast<unsigned long long *>(b.qtick + run_q), static_cast<unsigned long long>(run_t));
+    run_q = kInvalid;
+  }
+  if (lane == 0) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(b.stats), static_cast<unsigned long long>(tr.bytes));
+    atomicAdd(reinterpret_cast<unsigned long long *>(b.stats + 1), static_cast<unsigned long long>(tr.blocks));
   }
 }
 
@@ -255,9 +275,14 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   }
   qoff[nq] = uint32_t(nterms);
   item_base[nq] = uint32_t(items);
-  std::vector<uint32_t> item_query(items);
+  std::vector<uint32_t> item_info(4 * items);
   for (uint64_t q = 0; q < nq; ++q)
-    for (uint32_t i = item_base[q]; i < item_base[q + 1]; ++i) item_query[i] = uint32_t(q);
+    for (uint32_t i = item_base[q]; i < item_base[q + 1]; ++i) {
+      item_info[4 * size_t(i)] = uint32_t(q);
+      item_info[4 * size_t(i) + 1] = i - item_base[q];
+      item_info[4 * size_t(i) + 2] = qoff[q];
+      item_info[4 * size_t(i) + 3] = uint32_t(h_q_offsets[q + 1] - h_q_offsets[q]);
+    }
   const uint32_t ntiles = uint32_t((items + 1023) / 1024);
   // one device allocation for every table
   size_t off = 0;
@@ -267,7 +292,7 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
     return o;
   };
   const size_t o_sterms = take(4 * nterms), o_qoff = take(4 * (nq + 1)), o_ib = take(4 * (nq + 1)),
-               o_iq = take(4 * items), o_stage = take(4 * kBlock * items), o_counts = take(4 * items),
+               o_iq = take(16 * items), o_stage = take(4 * kBlock * items), o_counts = take(4 * items),
                o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)), o_ctrl = take(64),
                o_qtick = take(8 * nq);
   s4_batch *bt = new (std::nothrow) s4_batch;
@@ -285,7 +310,7 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   up(o_sterms, sterms.data(), 4 * nterms);
   up(o_qoff, qoff.data(), 4 * (nq + 1));
   up(o_ib, item_base.data(), 4 * (nq + 1));
-  up(o_iq, item_query.data(), 4 * items);
+  up(o_iq, item_info.data(), 16 * items);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     (void)hipFree(bt->mem);
@@ -297,7 +322,7 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   d.sterms = reinterpret_cast<const uint32_t *>(m + o_sterms);
   d.qoff = reinterpret_cast<const uint32_t *>(m + o_qoff);
   d.item_base = reinterpret_cast<const uint32_t *>(m + o_ib);
-  d.item_query = reinterpret_cast<const uint32_t *>(m + o_iq);
+  d.item_info = reinterpret_cast<const uint4 *>(m + o_iq);
   d.stage = reinterpret_cast<uint32_t *>(m + o_stage);
   d.counts = reinterpret_cast<uint32_t *>(m + o_counts);
   d.excl = reinterpret_cast<uint32_t *>(m + o_excl);
@@ -306,6 +331,7 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   d.total = reinterpret_cast<uint64_t *>(m + o_ctrl + 8);
   d.start = reinterpret_cast<uint64_t *>(m + o_ctrl + 16);
   d.qtick = reinterpret_cast<uint64_t *>(m + o_qtick);
+  d.stats = reinterpret_cast<uint64_t *>(m + o_ctrl + 24);
   d.items = uint32_t(items);
   d.nq = uint32_t(nq);
   d.ntiles = ntiles;
@@ -367,6 +393,16 @@ int s4_batch_run(s4_batch *b, uint64_t *d_counts, uint64_t *d_res_offsets, uint3
   return S4_OK;
 }
 
+int s4_batch_traffic(const s4_batch *b, uint64_t *bytes, uint64_t *blocks, void *stream) {
+  if (!b || !bytes || !blocks) return fail(S4_EINVAL, "null argument");
+  uint64_t v[2] = {0, 0};
+  S4_HIP(hipMemcpyAsync(v, b->dev.stats, sizeof v, hipMemcpyDeviceToHost, as_stream(stream)));
+  S4_HIP(hipStreamSynchronize(as_stream(stream)));
+  *bytes = v[0];
+  *blocks = v[1];
+  return S4_OK;
+}
+
 int s4_batch_query_ticks(const s4_batch *b, uint64_t *ticks, void *stream) {
   if (!b || (b->nq && !ticks)) return fail(S4_EINVAL, "null argument");
   if (!b->nq) return S4_OK;
@@ -406,7 +442,7 @@ int s4_batch_autotune(s4_batch *b, uint64_t *d_counts, uint64_t *d_res_offsets, 
   const std::vector<uint32_t> gallops = {4, 16, 64, 256, 512};
   const std::vector<uint32_t> waves = {1, 2, 4, 8};
   const std::vector<uint32_t> groups = {2, 4, 8, 16};
-  const std::vector<uint32_t> grabs = {1, 2, 4};
+  const std::vector<uint32_t> grabs = {1, 4, 8, 16, 32, 64};
   for (int round = 0; round < 2 && rc == S4_OK; ++round) {
     for (int dim = 0; dim < 4 && rc == S4_OK; ++dim) {
       const std::vector<uint32_t> &vals = dim == 0 ? gallops : dim == 1 ? waves : dim == 2 ? groups : grabs;

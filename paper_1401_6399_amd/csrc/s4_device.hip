@@ -329,8 +329,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_chain(DList rl, const uint32_t *
     if (lane_id() == 0) counts[item] = 0;
     return;
   }
+  Traffic tr;
   const uint32_t cnt = chain_chunk(r, item, [&](uint32_t j) -> const DList & { return args.f[j]; }, args.nf,
-                                   lds[w], gallop_blocks);
+                                   lds[w], gallop_blocks, tr);
   store_chunk(cnt, lds[w], stage + uint64_t(item) * kBlock, counts + item);
 }
 

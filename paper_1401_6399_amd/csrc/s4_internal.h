@@ -98,7 +98,7 @@ struct BatchDev {
   const uint32_t *sterms;     // terms of every query, shortest list first
   const uint32_t *qoff;       // [nq + 1] term offsets
   const uint32_t *item_base;  // [nq + 1] first chunk of each query
-  const uint32_t *item_query; // [items] query of each chunk
+  const uint4 *item_info;     // [items] {query, chunk in query, first term, terms}
   uint32_t *stage;            // [items * 128] survivors of each chunk
   uint32_t *counts;           // [items]
   uint32_t *excl;             // [items]
@@ -107,6 +107,7 @@ struct BatchDev {
   uint64_t *total;            // number of results
   uint64_t *start;            // device clock at the start of the run
   uint64_t *qtick;            // [nq] completion time of each query
+  uint64_t *stats;            // [2] algorithmic bytes read + written, blocks decoded
   uint32_t items, nq, ntiles;
 };
 // Enqueue one run of a batch on st: persistent chunk kernel, scan,

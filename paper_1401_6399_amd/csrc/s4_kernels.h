@@ -246,6 +246,47 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__
   return lo;
 }
 
+// Two lower bounds at once over v[0 .. n): r0 = first index with
+// v[r0] >= key0, r1 = first with v[r1] >= key1 (n if none).  Lanes 0..31
+// work on key0 and lanes 32..63 on key1; every round each half probes 32
+// evenly spaced entries of its current range in parallel and keeps the
+// piece between the last entry below the key and the first one not below,
+// so a range of n entries takes about log_32 n rounds of loads instead of
+// log_2 n dependent ones.  All 64 lanes call this; the results are uniform.
+__device__ __forceinline__ void coop_lower_bound2(const uint32_t *__restrict__ v, uint32_t n, uint32_t key0,
+                                                  uint32_t key1, uint32_t &r0, uint32_t &r1) {
+  const uint32_t lane = lane_id();
+  const bool upper = lane >= 32;
+  const uint32_t sub = lane & 31u;
+  const uint32_t key = upper ? key1 : key0;
+  uint32_t lo0 = 0, hi0 = n, lo1 = 0, hi1 = n;  // answer of each half lies in [lo, hi]
+  while (hi0 > lo0 || hi1 > lo1) {
+    const uint32_t lo = upper ? lo1 : lo0, hi = upper ? hi1 : hi0;
+    const uint32_t len = hi - lo;
+    const uint32_t step = (len + 31u) >> 5;
+    const uint32_t pos = lo + sub * step;
+    const bool below = len > 0 && pos < hi && v[pos] < key;
+    const uint64_t m = __ballot(below);
+    const uint32_t c0 = uint32_t(__popcll(m & 0xFFFFFFFFull)), c1 = uint32_t(__popcll(m >> 32));
+    if (hi0 > lo0) {
+      const uint32_t st = (hi0 - lo0 + 31u) >> 5;
+      const uint32_t nlo = c0 ? lo0 + (c0 - 1) * st + 1 : lo0;
+      const uint32_t nhi = min(hi0, lo0 + c0 * st);
+      lo0 = nlo;
+      hi0 = max(nlo, nhi);
+    }
+    if (hi1 > lo1) {
+      const uint32_t st = (hi1 - lo1 + 31u) >> 5;
+      const uint32_t nlo = c1 ? lo1 + (c1 - 1) * st + 1 : lo1;
+      const uint32_t nhi = min(hi1, lo1 + c1 * st);
+      lo1 = nlo;
+      hi1 = max(nlo, nhi);
+    }
+  }
+  r0 = uniform(lo0);
+  r1 = uniform(lo1);
+}
+
 // ------------------------------------------------------------ pair items
 
 // Per-wave LDS of the intersection kernels.
@@ -263,9 +304,17 @@ struct RSide {
   uint64_t len;         // number of values of r
 };
 
+// Algorithmic bytes read by a wave (uniform): packed payload + width byte +
+// block offset + seed of every decoded block, staged skip-index entries,
+// raw values; and the number of blocks decoded.
+struct Traffic {
+  uint64_t bytes = 0;
+  uint64_t blocks = 0;
+};
+
 // Load chunk `item` of r (values 128 item .. 128 item + 127) into s.r;
 // returns how many values it has.  The whole wave calls this.
-__device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, ItemLds &s) {
+__device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, ItemLds &s, Traffic &tr) {
   const uint32_t lane = lane_id();
   uint32_t cnt;
   if (r.raw) {
@@ -276,6 +325,8 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     if (lane + 64 < cnt) s.r[lane + 64] = r.raw[base + 64 + lane];
   } else if (item < r.L.nb) {
     cnt = kBlock;
+    tr.bytes += 16u * uniform(r.L.widths[item]) + 1u + 4u + 16u;
+    tr.blocks += 1;
     if (r.L.mode == S4_DELTA_D4) {
       decode_block_wave(r.L, item, s.r);
     } else {
@@ -293,6 +344,7 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     if (lane < cnt) s.r[lane] = r.L.tail[lane];
     if (lane + 64 < cnt) s.r[lane + 64] = r.L.tail[lane + 64];
   }
+  if (r.raw || item >= r.L.nb) tr.bytes += 4u * cnt;
   wave_sync();
   return cnt;
 }
@@ -304,7 +356,7 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
 // the long list for each value of the short one, done here per lane over
 // the skip index), each distinct candidate once.
 __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f, ItemLds &s,
-                                                    uint32_t gallop_blocks) {
+                                                    uint32_t gallop_blocks, Traffic &tr) {
   const uint32_t lane = lane_id();
   const bool v0 = lane < cnt, v1 = lane + 64 < cnt;
   const uint32_t a0 = v0 ? s.r[lane] : 0u;
@@ -313,20 +365,22 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
   const uint32_t last = uniform(s.r[cnt ? cnt - 1 : 0]);
   const uint32_t nbf = f.nb;
   const bool ftail = f.t > 0;
+  // f's largest value and the span of f blocks that can hold [first, last]
+  // (index nb stands for the raw tail, bmax taken as +infinity there); the
+  // two are independent, so their loads overlap
   uint32_t fmax = 0;
   if (f.n > 0) fmax = ftail ? f.tail[f.t - 1] : f.bmax[nbf - 1];
+  uint32_t lo = 0, hi = 0;
+  if (cnt > 0) coop_lower_bound2(f.bmax, nbf, first, last, lo, hi);
   const bool any = cnt > 0 && f.n > 0 && first <= fmax;
   bool f0 = false, f1 = false;
   if (any) {
-    // span of f blocks that can hold [first, last]; index nb stands for the
-    // raw tail (bmax taken as +infinity there)
-    const uint32_t lo = uniform(lower_bound_u32(f.bmax, 0, nbf, first));
-    const uint32_t hi = uniform(lower_bound_u32(f.bmax, lo, nbf, last));
     const uint32_t span = hi - lo + 1;
     uint32_t c0, c1;
     if (span <= gallop_blocks) {
       // merge regime: stage the spanned bmax entries in LDS, search there
       for (uint32_t e = lane; e < span; e += 64) s.bm[e] = (lo + e < nbf) ? f.bmax[lo + e] : kInvalid;
+      tr.bytes += 4u * span;
       wave_sync();
       c0 = lo + lower_bound_u32(s.bm, 0, span - 1, a0);
       c1 = lo + lower_bound_u32(s.bm, 0, span - 1, a1);
@@ -357,6 +411,12 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
     for (uint32_t g = 0; g < U; g += 4) {
       const uint32_t cs = g + row;
       const uint32_t blk = cs < U ? s.cand[cs] : kInvalid;
+      // traffic of the four rows' blocks, summed from each row's first lane
+      uint32_t tb = 0;
+      if (ri == 0) tb = blk < nbf ? 16u * f.widths[blk] + 21u : (blk == nbf ? 4u * f.t : 0u);
+      tr.bytes += uint32_t(__builtin_amdgcn_readlane(int(tb), 0)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 16)) +
+                  uint32_t(__builtin_amdgcn_readlane(int(tb), 32)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 48));
+      tr.blocks += min(4u, U - g);
       uint32_t x0[4], x1[4];
       decode_row(f, blk, blk < nbf, ri, x0, x1);
       if (blk < nbf) {
@@ -407,9 +467,10 @@ __device__ __forceinline__ void store_chunk(uint32_t cnt, const ItemLds &s, uint
 // a partition of the shortest list, so chunks are independent.
 template <class FList>
 __device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, FList f, uint32_t nf, ItemLds &s,
-                                                uint32_t gallop_blocks) {
-  uint32_t cnt = load_chunk(r, item, s);
-  for (uint32_t j = 0; j < nf && cnt > 0; ++j) cnt = intersect_chunk(cnt, f(j), s, gallop_blocks);
+                                                uint32_t gallop_blocks, Traffic &tr) {
+  uint32_t cnt = load_chunk(r, item, s, tr);
+  for (uint32_t j = 0; j < nf && cnt > 0; ++j) cnt = intersect_chunk(cnt, f(j), s, gallop_blocks, tr);
+  tr.bytes += 4u * cnt;  // the chunk's results
   return cnt;
 }
 

@@ -101,7 +101,7 @@ int alloc_context(s4_server *s, Context &c) {
     return o;
   };
   const size_t o_sterms = take(4 * nt), o_qoff = take(4 * (nq + 1)), o_ib = take(4 * (nq + 1)),
-               o_iq = take(4 * items), o_stage = take(4 * s4::kBlock * items), o_counts = take(4 * items),
+               o_iq = take(16 * items), o_stage = take(4 * s4::kBlock * items), o_counts = take(4 * items),
                o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)), o_ctrl = take(64),
                o_qtick = take(8 * nq), o_res = take(4 * s4::kBlock * items);
   if (hipMalloc(&c.dmem, off) != hipSuccess) return s4::fail(S4_ENOMEM, "server context: device allocation failed");
@@ -111,7 +111,7 @@ int alloc_context(s4_server *s, Context &c) {
   d.sterms = reinterpret_cast<const uint32_t *>(m + o_sterms);
   d.qoff = reinterpret_cast<const uint32_t *>(m + o_qoff);
   d.item_base = reinterpret_cast<const uint32_t *>(m + o_ib);
-  d.item_query = reinterpret_cast<const uint32_t *>(m + o_iq);
+  d.item_info = reinterpret_cast<const uint4 *>(m + o_iq);
   d.stage = reinterpret_cast<uint32_t *>(m + o_stage);
   d.counts = reinterpret_cast<uint32_t *>(m + o_counts);
   d.excl = reinterpret_cast<uint32_t *>(m + o_excl);
@@ -120,6 +120,7 @@ int alloc_context(s4_server *s, Context &c) {
   d.total = reinterpret_cast<uint64_t *>(m + o_ctrl + 8);
   d.start = reinterpret_cast<uint64_t *>(m + o_ctrl + 16);
   d.qtick = reinterpret_cast<uint64_t *>(m + o_qtick);
+  d.stats = reinterpret_cast<uint64_t *>(m + o_ctrl + 24);
   c.d_results = reinterpret_cast<uint32_t *>(m + o_res);
   auto hmalloc = [&](void **p, size_t bytes, unsigned flags) {
     return hipHostMalloc(p, std::max<size_t>(bytes, 64), flags) == hipSuccess;
@@ -127,7 +128,7 @@ int alloc_context(s4_server *s, Context &c) {
   bool ok = hmalloc(reinterpret_cast<void **>(&c.h_sterms), 4 * nt, hipHostMallocDefault) &&
             hmalloc(reinterpret_cast<void **>(&c.h_qoff), 4 * (nq + 1), hipHostMallocDefault) &&
             hmalloc(reinterpret_cast<void **>(&c.h_ib), 4 * (nq + 1), hipHostMallocDefault) &&
-            hmalloc(reinterpret_cast<void **>(&c.h_iq), 4 * items, hipHostMallocDefault) &&
+            hmalloc(reinterpret_cast<void **>(&c.h_iq), 16 * items, hipHostMallocDefault) &&
             hmalloc(reinterpret_cast<void **>(&c.h_results), 4 * s->results_per_ctx, hipHostMallocDefault) &&
             hmalloc(reinterpret_cast<void **>(&c.h_counts), 8 * nq, hipHostMallocMapped) &&
             hmalloc(reinterpret_cast<void **>(&c.h_offs), 8 * (nq + 1), hipHostMallocMapped);
@@ -159,7 +160,13 @@ int launch_context(s4_server *s, Context &c) {
     c.h_qoff[q] = uint32_t(nt);
     c.h_ib[q] = uint32_t(items);
     for (uint32_t t : qq.terms) c.h_sterms[nt++] = t;
-    for (uint64_t i = 0; i < qq.items; ++i) c.h_iq[items + i] = uint32_t(q);
+    for (uint64_t i = 0; i < qq.items; ++i) {
+      uint32_t *rec = c.h_iq + 4 * (items + i);
+      rec[0] = uint32_t(q);
+      rec[1] = uint32_t(i);
+      rec[2] = c.h_qoff[q];
+      rec[3] = uint32_t(qq.terms.size());
+    }
     items += qq.items;
   }
   c.h_qoff[nq] = uint32_t(nt);
@@ -173,7 +180,7 @@ int launch_context(s4_server *s, Context &c) {
   S4_HIP(hipMemcpyAsync(const_cast<uint32_t *>(d.qoff), c.h_qoff, 4 * (nq + 1), hipMemcpyHostToDevice, c.stream));
   S4_HIP(hipMemcpyAsync(const_cast<uint32_t *>(d.item_base), c.h_ib, 4 * (nq + 1), hipMemcpyHostToDevice, c.stream));
   if (items)
-    S4_HIP(hipMemcpyAsync(const_cast<uint32_t *>(d.item_query), c.h_iq, 4 * items, hipMemcpyHostToDevice, c.stream));
+    S4_HIP(hipMemcpyAsync(const_cast<uint4 *>(d.item_info), c.h_iq, 16 * items, hipMemcpyHostToDevice, c.stream));
   int rc = s4::enqueue_batch_dev(d, c.d_counts, c.d_offs, c.d_results, c.stream);
   if (rc) return rc;
   S4_HIP(hipEventRecord(c.done, c.stream));

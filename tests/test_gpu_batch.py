@@ -113,6 +113,10 @@ def test_query_ticks(gpu, small_index):
     b.run()
     t = b.query_ticks()
     assert t.size == 300 and (t > 0).all()
+    nbytes, blocks = b.traffic()
+    chunks = sum((int(ix.lengths[min(terms[int(qoffs[q]): int(qoffs[q + 1])], key=lambda x: ix.lengths[x])]) + 127)
+                 // 128 for q in range(300))
+    assert blocks >= chunks * 0.5 and nbytes > 16 * blocks
 
 
 def test_batch_rejects_bad_queries(gpu, small_index):
