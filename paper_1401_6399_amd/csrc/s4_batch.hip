@@ -113,10 +113,14 @@ static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream
 
 template <int W>
 static void launch_chunks(const BatchDev &d, const s4_tuning &t, hipStream_t st) {
-  const uint32_t per_group = W * t.items_per_grab;
+  // chunks per queue fetch: the tuned value, but small batches spread over
+  // every resident wave (at least ~4 fetches per wave)
+  const uint32_t resident = uint32_t(cu_count()) * t.groups_per_cu * W;
+  const uint32_t grab = std::max<uint32_t>(1, std::min<uint32_t>(t.items_per_grab, d.items / (4 * resident)));
+  const uint32_t per_group = W * grab;
   uint32_t groups = uint32_t(cu_count()) * t.groups_per_cu;
   groups = std::max<uint32_t>(1, std::min<uint32_t>(groups, (d.items + per_group - 1) / per_group));
-  hipLaunchKernelGGL(k_batch_chunks<W>, dim3(groups), dim3(W * 64), 0, st, d, t.items_per_grab,
+  hipLaunchKernelGGL(k_batch_chunks<W>, dim3(groups), dim3(W * 64), 0, st, d, grab,
                      std::min(t.gallop_blocks, kMaxGallopBlocks));
 }
 

@@ -19,7 +19,7 @@ namespace s4 {
 static std::mutex g_dev_mu;
 static int g_dev_checked = -1;  // device id verified, -1 none
 static int g_cus = 0;
-static s4_tuning g_tuning = {64u, 4u, 8u, 1u, 4u};
+static s4_tuning g_tuning = {256u, 8u, 4u, 32u, 4u};
 
 int ensure_device() {
   int dev = -1;
