@@ -294,13 +294,21 @@ int s4_batch_autotune(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offse
 
 /* ----------------------------------------------------------------- server
  *
- * Continuous-batching query server over a device-resident index.  A
- * dispatcher thread owns one HIP stream; each iteration admits waiting
- * queries into free slots while the reserved intermediate memory (the
- * output-to-input bound of each query) fits the pool, runs one chain level
- * for every active query in one persistent launch, and retires finished
- * queries.  Queries that arrive while others run join at the next
- * iteration.  Submission never blocks on the GPU.
+ * Continuous-batching query server over a device-resident index (each
+ * query a conjunction whose lists are intersected as in Sec. 6, shortest
+ * list first).  A dispatcher thread owns three iteration contexts, each
+ * with its own HIP stream and buffers allocated at creation.  An iteration
+ * admits waiting queries, oldest first, while the context's slots, the
+ * reserved intermediate memory (the output-to-input bound: 512 bytes per
+ * 128-value chunk of the query's shortest list) and the result buffer (the
+ * shortest list's length per query) fit, runs every admitted query to
+ * completion in one persistent decode-fused launch (a single-pass kernel
+ * with look-back offsets when the iteration has at most one 128-value
+ * chunk per resident wave, else chunk kernel + scan + compaction), and
+ * retires them.
+ * Queries that arrive while iterations run join the next free context, so
+ * up to three iterations overlap on the device.  Submission never blocks
+ * on the GPU.
  */
 typedef struct s4_server s4_server;
 typedef struct {
@@ -331,6 +339,11 @@ typedef struct {
   uint64_t peak_active;
   uint64_t peak_pool_bytes;
   uint64_t waits_for_memory; /* admissions deferred because the pool was full */
+  uint64_t max_batch;        /* most queries admitted into one iteration */
+  uint64_t direct_iterations;/* iterations whose results the device wrote straight to pinned host memory */
+  uint64_t single_pass_iterations; /* iterations run as one single-pass kernel (at most one chunk per resident wave) */
+  uint64_t device_ns;        /* summed launch-to-finish time of iterations, as seen by the dispatcher */
+  uint64_t host_ns;          /* dispatcher time spent packing, launching and retiring iterations */
 } s4_server_stats;
 int s4_server_stats_get(const s4_server *srv, s4_server_stats *st);
 /* Stop accepting, finish every admitted query, join the dispatcher. */

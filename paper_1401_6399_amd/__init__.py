@@ -48,7 +48,10 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("iterations", ctypes.c_uint64), ("peak_active", ctypes.c_uint64),
-                ("peak_pool_bytes", ctypes.c_uint64), ("waits_for_memory", ctypes.c_uint64)]
+                ("peak_pool_bytes", ctypes.c_uint64), ("waits_for_memory", ctypes.c_uint64),
+                ("max_batch", ctypes.c_uint64), ("direct_iterations", ctypes.c_uint64),
+                ("single_pass_iterations", ctypes.c_uint64),
+                ("device_ns", ctypes.c_uint64), ("host_ns", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

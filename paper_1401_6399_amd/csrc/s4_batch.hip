@@ -76,6 +76,115 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_
   }
 }
 
+// Sum over the wave.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += uint32_t(__shfl_xor(int(v), o));
+  return v;
+}
+
+// Scan word of one chunk: high half (epoch << 2 | flag), low half a value;
+// flag 1: the chunk's count alone, flag 2: inclusive prefix through it.
+__device__ __forceinline__ void publish(uint64_t *w, uint32_t tag, uint32_t v) {
+  __hip_atomic_store(w, (uint64_t(tag) << 32) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+constexpr uint32_t kLookbackSpins = 1u << 22;
+
+// Decoupled look-back: publish this chunk's count, then read the words of
+// the 64 nearest predecessors at once; the offset is the sum of the counts
+// back to (and including) the nearest inclusive prefix, and is published
+// in turn as this chunk's inclusive prefix.  Chunks are taken from the
+// queue in increasing order by running waves, so the earliest unfinished
+// chunk never waits and the walk always ends; the spin bound is a guard.
+__device__ uint32_t lookback(uint64_t *__restrict__ state, uint32_t item, uint32_t epoch, uint32_t cnt,
+                             uint32_t *__restrict__ err, bool &ok) {
+  const uint32_t lane = lane_id();
+  const uint32_t tag_a = (epoch << 2) | 1u, tag_p = (epoch << 2) | 2u;
+  if (item == 0) {
+    if (lane == 0) publish(state, tag_p, cnt);
+    return 0;
+  }
+  if (lane == 0) publish(state + item, tag_a, cnt);
+  uint32_t excl = 0, spins = 0;
+  int64_t base = int64_t(item) - 1;
+  for (;;) {
+    const int64_t j = base - int64_t(lane);
+    uint32_t hi = tag_p, val = 0;  // before the first chunk: prefix 0
+    if (j >= 0) {
+      const uint64_t v = __hip_atomic_load(state + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hi = uint32_t(v >> 32);
+      val = uint32_t(v);
+    }
+    const uint64_t is_p = __ballot(hi == tag_p);
+    const uint64_t ready = __ballot(hi == tag_p || hi == tag_a);
+    // lanes through the nearest inclusive prefix (all 64 if none)
+    const uint64_t need = is_p ? ((is_p & (~is_p + 1)) << 1) - 1 : ~0ull;
+    if ((ready & need) == need) {
+      excl += wave_sum(((need >> lane) & 1) ? val : 0u);
+      if (is_p) break;
+      base -= 64;
+    } else {
+      if (++spins > kLookbackSpins) {
+        if (lane == 0) *err = 1u;
+        ok = false;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  if (lane == 0) publish(state + item, tag_p, excl + cnt);
+  return excl;
+}
+
+// Single-pass persistent chunk kernel: as k_batch_chunks, but every chunk
+// writes its survivors straight to out at the offset found by look-back,
+// and the first chunk of each query writes that query's CSR offset (and
+// those of any chunkless queries just before it; the last chunk closes the
+// table).  No staging, no per-query stamps.
+template <int WAVES>
+__global__ __launch_bounds__(WAVES * 64) void k_serve_chunks(BatchDev b, uint32_t grab, uint32_t gallop_blocks,
+                                                             uint32_t *__restrict__ out, uint64_t out_cap,
+                                                             uint64_t *__restrict__ offs) {
+  __shared__ ItemLds lds[WAVES];
+  const uint32_t w = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  Traffic tr;
+  for (;;) {
+    uint32_t it0 = 0;
+    if (lane == 0) it0 = atomicAdd(b.head, grab);
+    it0 = uint32_t(__shfl(int(it0), 0));
+    if (it0 >= b.items) break;
+    const uint32_t it1 = min(it0 + grab, b.items);
+    for (uint32_t item = it0; item < it1; ++item) {
+      const uint4 info = b.item_info[item];
+      const uint32_t q = uniform(info.x), local = uniform(info.y), tq = uniform(info.z), k = uniform(info.w);
+      const uint32_t id0 = b.sterms[tq], id1 = b.sterms[tq + (k > 1 ? 1 : 0)];
+      RSide r;
+      r.L = b.lists[id0];
+      const DList f1 = b.lists[id1];
+      r.raw = nullptr;
+      r.len = r.L.n;
+      const uint32_t cnt = chain_chunk(
+          r, local, [&](uint32_t j) -> DList { return j == 0 ? f1 : b.lists[b.sterms[tq + 1 + j]]; }, k - 1,
+          lds[w], gallop_blocks, tr);
+      bool ok = true;
+      const uint32_t excl = lookback(b.state, item, b.epoch, cnt, b.err, ok);
+      if (ok && uint64_t(excl) + cnt <= out_cap) {
+        if (lane < cnt) out[excl + lane] = lds[w].r[lane];
+        if (lane + 64 < cnt) out[excl + lane + 64] = lds[w].r[lane + 64];
+      } else if (lane == 0) {
+        *b.err = 1u;
+      }
+      if (local == 0) {
+        const uint32_t q0 = item ? uniform(b.item_info[item - 1].x) + 1 : 0u;
+        for (uint32_t qq = q0 + lane; qq <= q; qq += 64) offs[qq] = excl;
+      }
+      if (item + 1 == b.items)
+        for (uint32_t qq = q + 1 + lane; qq <= b.nq; qq += 64) offs[qq] = uint64_t(excl) + cnt;
+    }
+  }
+}
+
 // Per-query counts and CSR offsets from the global exclusive scan.
 __global__ void k_batch_finish(BatchDev b, uint64_t *__restrict__ d_counts, uint64_t *__restrict__ d_offs) {
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -124,7 +233,38 @@ static void launch_chunks(const BatchDev &d, const s4_tuning &t, hipStream_t st)
                      std::min(t.gallop_blocks, kMaxGallopBlocks));
 }
 
+template <int W>
+static void launch_serve(const BatchDev &d, const s4_tuning &t, uint32_t *out, uint64_t out_cap, uint64_t *offs,
+                         hipStream_t st) {
+  const uint32_t resident = uint32_t(cu_count()) * t.groups_per_cu * W;
+  const uint32_t grab = std::max<uint32_t>(1, std::min<uint32_t>(t.items_per_grab, d.items / (4 * resident)));
+  const uint32_t per_group = W * grab;
+  uint32_t groups = uint32_t(cu_count()) * t.groups_per_cu;
+  groups = std::max<uint32_t>(1, std::min<uint32_t>(groups, (d.items + per_group - 1) / per_group));
+  hipLaunchKernelGGL(k_serve_chunks<W>, dim3(groups), dim3(W * 64), 0, st, d, grab,
+                     std::min(t.gallop_blocks, kMaxGallopBlocks), out, out_cap, offs);
+}
+
 namespace s4 {
+uint64_t single_pass_max_items() {
+  const s4_tuning t = tuning();
+  return uint64_t(cu_count()) * t.groups_per_cu * t.waves_per_group;
+}
+
+int enqueue_serve_dev(const BatchDev &d, uint32_t *out, uint64_t out_cap, uint64_t *d_offs, hipStream_t st) {
+  if (!d.items || !d.state || !d.err || d.epoch == 0 || d.epoch > kMaxEpoch)
+    return fail(S4_EINVAL, "single-pass run: needs chunks, scan words and an epoch in 1 .. 2^30 - 1");
+  const s4_tuning t = tuning();
+  switch (t.waves_per_group) {
+    case 1: launch_serve<1>(d, t, out, out_cap, d_offs, st); break;
+    case 2: launch_serve<2>(d, t, out, out_cap, d_offs, st); break;
+    case 8: launch_serve<8>(d, t, out, out_cap, d_offs, st); break;
+    default: launch_serve<4>(d, t, out, out_cap, d_offs, st); break;
+  }
+  S4_HIP(hipGetLastError());
+  return S4_OK;
+}
+
 // Enqueue one run of a batch described by d on st.
 int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st) {
   const s4_tuning t = tuning();

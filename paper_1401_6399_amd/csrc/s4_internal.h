@@ -108,11 +108,26 @@ struct BatchDev {
   uint64_t *start;            // device clock at the start of the run
   uint64_t *qtick;            // [nq] completion time of each query
   uint64_t *stats;            // [2] algorithmic bytes read + written, blocks decoded
+  uint64_t *state;            // [items] single-pass scan words (see enqueue_serve_dev)
+  uint32_t *err;              // set to 1 by the single-pass kernel on a failed look-back or overflow
   uint32_t items, nq, ntiles;
+  uint32_t epoch;             // single-pass scan generation, 1 .. 2^30 - 1
 };
 // Enqueue one run of a batch on st: persistent chunk kernel, scan,
 // compaction into d_results, per-query counts / CSR offsets.
 int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st);
+// Enqueue one single-pass run on st: the persistent chunk kernel alone,
+// each chunk taking its output offset from a decoupled look-back over the
+// scan words d.state (tagged with d.epoch, so they need no clearing between
+// runs) and writing its survivors to their final place in out[out_cap].
+// d_offs[nq + 1] receives the CSR offsets.  *d.head must be 0.
+int enqueue_serve_dev(const BatchDev &d, uint32_t *out, uint64_t out_cap, uint64_t *d_offs, hipStream_t st);
+constexpr uint32_t kMaxEpoch = (1u << 30) - 1;
+// Most chunks a single-pass run takes under the current tuning: one per
+// resident wave.  A chunk's count is known only when its chain is done, so
+// with more chunks than waves every wave would wait on the slowest chunk in
+// flight before taking the next; larger runs use the staged path.
+uint64_t single_pass_max_items();
 
 }  // namespace s4
 

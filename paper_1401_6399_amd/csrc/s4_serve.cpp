@@ -2,22 +2,28 @@
 //
 // A dispatcher thread owns `kContexts` iteration contexts, each with its own
 // HIP stream, device tables and pinned host buffers, all allocated when the
-// server is created (nothing is allocated while serving).  Each turn of its
-// loop it
+// server is created (nothing is allocated on the device while serving).
+// Each turn of its loop it
 //   1. retires contexts whose iteration has finished on the device (an event
 //      query, never a wait), handing results to the completed queue and
 //      releasing their memory reservation;
 //   2. admits waiting queries, oldest first, into a free context while the
 //      context's slot count, chunk memory (the output-to-input bound: at
 //      most 128 survivors per 128-value chunk of the shortest list) and
-//      result memory (at most the shortest list's length) all fit;
-//   3. launches the admitted queries as one batch (persistent decode-fused
-//      chunk kernel + scan + compaction) on that context's stream.
+//      result memory (at most the shortest list's length per query) all fit;
+//   3. launches the admitted queries as one batch on that context's stream:
+//      one upload of the packed query tables (which also resets the work
+//      queue), then, for an iteration of at most one chunk per resident
+//      wave, one single-pass persistent decode-fused chunk kernel whose
+//      chunks find their output offsets by decoupled look-back; a larger
+//      iteration runs the staged form (chunk kernel into per-chunk slots,
+//      scan, compaction), whose waves never wait on each other.
 // Queries that arrive while earlier ones run on the device are admitted into
 // the next free context and launched at once, so iterations overlap on the
-// device.  Per-query counts and offsets are written by the device straight
-// into pinned, device-mapped host memory; the results themselves are copied
-// back with one asynchronous copy of exactly their total size.
+// device.  Per-query offsets, and the results themselves when their bound
+// fits the context's result buffer, are written by the device straight into
+// pinned, device-mapped host memory; an iteration whose bound does not fit
+// writes to device memory and copies exactly the total back.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -36,9 +42,14 @@ namespace {
 using Clock = std::chrono::steady_clock;
 constexpr int kContexts = 3;
 
+uint64_t ns_between(Clock::time_point a, Clock::time_point b) {
+  return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(b - a).count());
+}
+
 struct Query {
   uint64_t id = 0;
-  std::vector<uint32_t> terms;  // sorted shortest first
+  uint32_t k = 0;
+  uint32_t terms[s4::kMaxTerms + 1];  // shortest list first
   uint64_t items = 0, bound = 0;
   Clock::time_point submitted;
 };
@@ -53,16 +64,26 @@ struct Context {
   hipEvent_t done = nullptr;
   void *dmem = nullptr;
   s4::BatchDev dev{};
-  // pinned host: tables (uploaded) and outputs (written by the device)
-  uint32_t *h_sterms = nullptr, *h_qoff = nullptr, *h_ib = nullptr, *h_iq = nullptr;
-  uint32_t *h_results = nullptr;  // pinned, results_per_ctx values
-  uint64_t *h_counts = nullptr, *h_offs = nullptr;  // pinned, device-mapped
-  uint32_t *d_results = nullptr;  // device, one value per staged slot
-  uint64_t *d_counts = nullptr, *d_offs = nullptr;  // device views of h_counts / h_offs
+  // query tables of one iteration, packed: queue head (zero), terms, first
+  // chunk of each query, chunk records (each part 16-byte aligned)
+  uint8_t *h_tab = nullptr;  // pinned
+  uint8_t *d_tab = nullptr;  // device
+  uint64_t *state = nullptr;       // device, one scan word per chunk (single pass)
+  uint64_t *d_counts = nullptr;    // device, per-query counts (staged form; unused by the host)
+  uint32_t epoch = 0;              // scan generation of the last launch
+  uint32_t *h_results = nullptr;   // pinned, device-mapped, results_per_ctx values
+  uint32_t *d_hresults = nullptr;  // device view of h_results
+  uint64_t *h_offs = nullptr, *d_offs = nullptr;  // pinned, device-mapped: CSR offsets
+  uint32_t *h_err = nullptr, *d_err = nullptr;    // pinned, device-mapped: scan failure flag
+  uint32_t *d_results = nullptr;  // device, 128 values per chunk
   std::vector<Query> queries;
+  uint64_t items = 0, terms = 0, bound = 0;
   bool busy = false;
-  int phase = 0;  // 1: kernels running, 2: results copy running
+  bool direct = false;  // results written to h_results by the device
+  bool single = false;  // single-pass kernel
+  int phase = 0;        // 1: kernels running, 2: results copy running
   uint64_t reserved_stage = 0;
+  Clock::time_point launched;
 };
 
 }  // namespace
@@ -89,61 +110,67 @@ struct s4_server {
 
 namespace {
 
+// byte offsets of the parts of a packed table
+size_t terms_at() { return 16; }
+size_t bases_at(uint64_t nt) { return 16 + s4::align_up(4 * nt, 16); }
+size_t records_at(uint64_t nt, uint64_t nq) { return bases_at(nt) + s4::align_up(4 * (nq + 1), 16); }
+
 int alloc_context(s4_server *s, Context &c) {
   S4_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   S4_HIP(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
   const uint64_t nq = s->slots_per_ctx, items = s->items_per_ctx, nt = s->terms_per_ctx;
   const uint32_t ntiles = uint32_t((items + 1023) / 1024);
+  const size_t tab = records_at(nt, nq) + 16 * items;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = s4::align_up(off + std::max<size_t>(bytes, 4), 256);
     return o;
   };
-  const size_t o_sterms = take(4 * nt), o_qoff = take(4 * (nq + 1)), o_ib = take(4 * (nq + 1)),
-               o_iq = take(16 * items), o_stage = take(4 * s4::kBlock * items), o_counts = take(4 * items),
-               o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)), o_ctrl = take(64),
-               o_qtick = take(8 * nq), o_res = take(4 * s4::kBlock * items);
+  const size_t o_tab = take(tab), o_state = take(8 * items), o_stage = take(4 * s4::kBlock * items),
+               o_counts = take(4 * items), o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)),
+               o_ctrl = take(64), o_qtick = take(8 * nq), o_qcounts = take(8 * nq),
+               o_res = take(4 * s4::kBlock * items);
   if (hipMalloc(&c.dmem, off) != hipSuccess) return s4::fail(S4_ENOMEM, "server context: device allocation failed");
   char *m = static_cast<char *>(c.dmem);
+  c.d_tab = reinterpret_cast<uint8_t *>(m + o_tab);
+  c.state = reinterpret_cast<uint64_t *>(m + o_state);
+  c.d_counts = reinterpret_cast<uint64_t *>(m + o_qcounts);
+  c.d_results = reinterpret_cast<uint32_t *>(m + o_res);
+  S4_HIP(hipMemset(c.state, 0, 8 * items));  // no word carries a live epoch
   s4::BatchDev &d = c.dev;
   d.lists = s->index->d_lists;
-  d.sterms = reinterpret_cast<const uint32_t *>(m + o_sterms);
-  d.qoff = reinterpret_cast<const uint32_t *>(m + o_qoff);
-  d.item_base = reinterpret_cast<const uint32_t *>(m + o_ib);
-  d.item_info = reinterpret_cast<const uint4 *>(m + o_iq);
+  d.head = reinterpret_cast<uint32_t *>(c.d_tab);
+  d.sterms = reinterpret_cast<const uint32_t *>(c.d_tab + terms_at());
+  d.state = c.state;
   d.stage = reinterpret_cast<uint32_t *>(m + o_stage);
   d.counts = reinterpret_cast<uint32_t *>(m + o_counts);
   d.excl = reinterpret_cast<uint32_t *>(m + o_excl);
   d.tiles = reinterpret_cast<uint32_t *>(m + o_tiles);
-  d.head = reinterpret_cast<uint32_t *>(m + o_ctrl);
   d.total = reinterpret_cast<uint64_t *>(m + o_ctrl + 8);
   d.start = reinterpret_cast<uint64_t *>(m + o_ctrl + 16);
-  d.qtick = reinterpret_cast<uint64_t *>(m + o_qtick);
   d.stats = reinterpret_cast<uint64_t *>(m + o_ctrl + 24);
-  c.d_results = reinterpret_cast<uint32_t *>(m + o_res);
+  d.qtick = reinterpret_cast<uint64_t *>(m + o_qtick);
   auto hmalloc = [&](void **p, size_t bytes, unsigned flags) {
     return hipHostMalloc(p, std::max<size_t>(bytes, 64), flags) == hipSuccess;
   };
-  bool ok = hmalloc(reinterpret_cast<void **>(&c.h_sterms), 4 * nt, hipHostMallocDefault) &&
-            hmalloc(reinterpret_cast<void **>(&c.h_qoff), 4 * (nq + 1), hipHostMallocDefault) &&
-            hmalloc(reinterpret_cast<void **>(&c.h_ib), 4 * (nq + 1), hipHostMallocDefault) &&
-            hmalloc(reinterpret_cast<void **>(&c.h_iq), 16 * items, hipHostMallocDefault) &&
-            hmalloc(reinterpret_cast<void **>(&c.h_results), 4 * s->results_per_ctx, hipHostMallocDefault) &&
-            hmalloc(reinterpret_cast<void **>(&c.h_counts), 8 * nq, hipHostMallocMapped) &&
-            hmalloc(reinterpret_cast<void **>(&c.h_offs), 8 * (nq + 1), hipHostMallocMapped);
+  bool ok = hmalloc(reinterpret_cast<void **>(&c.h_tab), tab, hipHostMallocDefault) &&
+            hmalloc(reinterpret_cast<void **>(&c.h_results), 4 * s->results_per_ctx, hipHostMallocMapped) &&
+            hmalloc(reinterpret_cast<void **>(&c.h_offs), 8 * (nq + 1), hipHostMallocMapped) &&
+            hmalloc(reinterpret_cast<void **>(&c.h_err), 4, hipHostMallocMapped);
   if (!ok) return s4::fail(S4_ENOMEM, "server context: pinned host allocation failed");
-  S4_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&c.d_counts), c.h_counts, 0));
+  S4_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&c.d_hresults), c.h_results, 0));
   S4_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&c.d_offs), c.h_offs, 0));
+  S4_HIP(hipHostGetDevicePointer(reinterpret_cast<void **>(&c.d_err), c.h_err, 0));
+  c.dev.err = c.d_err;
   return S4_OK;
 }
 
 void free_context(Context &c) {
   if (c.stream) (void)hipStreamSynchronize(c.stream);
   if (c.dmem) (void)hipFree(c.dmem);
-  for (void *p : {static_cast<void *>(c.h_sterms), static_cast<void *>(c.h_qoff), static_cast<void *>(c.h_ib),
-                  static_cast<void *>(c.h_iq), static_cast<void *>(c.h_results), static_cast<void *>(c.h_counts),
-                  static_cast<void *>(c.h_offs)})
+  for (void *p : {static_cast<void *>(c.h_tab), static_cast<void *>(c.h_results), static_cast<void *>(c.h_offs),
+                  static_cast<void *>(c.h_err)})
     if (p) (void)hipHostFree(p);
   if (c.done) (void)hipEventDestroy(c.done);
   if (c.stream) (void)hipStreamDestroy(c.stream);
@@ -153,39 +180,61 @@ void free_context(Context &c) {
 // Launch the queries gathered in c (caller holds no lock; c is private to
 // the dispatcher while busy).
 int launch_context(s4_server *s, Context &c) {
-  uint64_t nt = 0, items = 0;
-  const uint64_t nq = c.queries.size();
+  const uint64_t nq = c.queries.size(), items = c.items;
+  uint32_t *head = reinterpret_cast<uint32_t *>(c.h_tab);
+  uint32_t *sterms = reinterpret_cast<uint32_t *>(c.h_tab + terms_at());
+  uint32_t *ib = reinterpret_cast<uint32_t *>(c.h_tab + bases_at(c.terms));
+  uint32_t *iq = reinterpret_cast<uint32_t *>(c.h_tab + records_at(c.terms, nq));
+  std::memset(head, 0, 16);
+  uint64_t t = 0, it = 0;
   for (uint64_t q = 0; q < nq; ++q) {
     const Query &qq = c.queries[q];
-    c.h_qoff[q] = uint32_t(nt);
-    c.h_ib[q] = uint32_t(items);
-    for (uint32_t t : qq.terms) c.h_sterms[nt++] = t;
+    ib[q] = uint32_t(it);
+    for (uint32_t j = 0; j < qq.k; ++j) sterms[t + j] = qq.terms[j];
     for (uint64_t i = 0; i < qq.items; ++i) {
-      uint32_t *rec = c.h_iq + 4 * (items + i);
+      uint32_t *rec = iq + 4 * (it + i);
       rec[0] = uint32_t(q);
       rec[1] = uint32_t(i);
-      rec[2] = c.h_qoff[q];
-      rec[3] = uint32_t(qq.terms.size());
+      rec[2] = uint32_t(t);
+      rec[3] = qq.k;
     }
-    items += qq.items;
+    t += qq.k;
+    it += qq.items;
   }
-  c.h_qoff[nq] = uint32_t(nt);
-  c.h_ib[nq] = uint32_t(items);
-  s4::BatchDev d = c.dev;
-  d.items = uint32_t(items);
-  d.nq = uint32_t(nq);
-  d.ntiles = uint32_t((items + 1023) / 1024);
-  S4_HIP(hipMemcpyAsync(const_cast<uint32_t *>(d.sterms), c.h_sterms, 4 * std::max<uint64_t>(nt, 1),
-                        hipMemcpyHostToDevice, c.stream));
-  S4_HIP(hipMemcpyAsync(const_cast<uint32_t *>(d.qoff), c.h_qoff, 4 * (nq + 1), hipMemcpyHostToDevice, c.stream));
-  S4_HIP(hipMemcpyAsync(const_cast<uint32_t *>(d.item_base), c.h_ib, 4 * (nq + 1), hipMemcpyHostToDevice, c.stream));
-  if (items)
-    S4_HIP(hipMemcpyAsync(const_cast<uint4 *>(d.item_info), c.h_iq, 16 * items, hipMemcpyHostToDevice, c.stream));
-  int rc = s4::enqueue_batch_dev(d, c.d_counts, c.d_offs, c.d_results, c.stream);
-  if (rc) return rc;
+  ib[nq] = uint32_t(it);
+  c.direct = c.bound <= s->results_per_ctx;
+  c.single = false;
+  if (items == 0) {  // every shortest list is empty: nothing to run
+    std::fill(c.h_offs, c.h_offs + nq + 1, 0);
+    c.direct = true;
+  } else {
+    s4::BatchDev d = c.dev;
+    d.item_base = reinterpret_cast<const uint32_t *>(c.d_tab + bases_at(c.terms));
+    d.item_info = reinterpret_cast<const uint4 *>(c.d_tab + records_at(c.terms, nq));
+    d.items = uint32_t(items);
+    d.nq = uint32_t(nq);
+    d.ntiles = uint32_t((items + 1023) / 1024);
+    c.single = items <= s4::single_pass_max_items();
+    if (c.single) {
+      if (++c.epoch > s4::kMaxEpoch) {
+        c.epoch = 1;
+        S4_HIP(hipMemsetAsync(c.state, 0, 8 * s->items_per_ctx, c.stream));
+      }
+      d.epoch = c.epoch;
+    }
+    *c.h_err = 0;
+    S4_HIP(hipMemcpyAsync(c.d_tab, c.h_tab, records_at(c.terms, nq) + 16 * items, hipMemcpyHostToDevice,
+                          c.stream));
+    uint32_t *out = c.direct ? c.d_hresults : c.d_results;
+    int rc = c.single ? s4::enqueue_serve_dev(d, out, c.direct ? s->results_per_ctx : s4::kBlock * items,
+                                              c.d_offs, c.stream)
+                      : s4::enqueue_batch_dev(d, c.d_counts, c.d_offs, out, c.stream);
+    if (rc) return rc;
+  }
   S4_HIP(hipEventRecord(c.done, c.stream));
   c.busy = true;
   c.phase = 1;
+  c.launched = Clock::now();
   return S4_OK;
 }
 
@@ -193,7 +242,7 @@ int launch_context(s4_server *s, Context &c) {
 // fit the pinned buffer).  Returns true when the context can retire now.
 bool start_copy(s4_server *s, Context &c, std::vector<uint32_t> *spill) {
   const uint64_t total = c.h_offs[c.queries.size()];
-  if (total == 0) return true;
+  if (c.direct || total == 0) return true;
   if (total <= s->results_per_ctx) {
     if (hipMemcpyAsync(c.h_results, c.d_results, 4 * total, hipMemcpyDeviceToHost, c.stream) == hipSuccess &&
         hipEventRecord(c.done, c.stream) == hipSuccess) {
@@ -212,11 +261,11 @@ void retire_context(s4_server *s, Context &c, const uint32_t *res) {
   std::vector<Done> out;
   out.reserve(c.queries.size());
   for (size_t q = 0; q < c.queries.size(); ++q) {
-    const uint64_t o0 = c.h_offs[q], cnt = c.h_counts[q];
+    const uint64_t o0 = c.h_offs[q], cnt = c.h_offs[q + 1] - o0;
     Done d;
     d.id = c.queries[q].id;
     d.count = cnt;
-    d.latency_ns = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(now - c.queries[q].submitted).count());
+    d.latency_ns = ns_between(c.queries[q].submitted, now);
     d.result.assign(res + o0, res + o0 + cnt);
     out.push_back(std::move(d));
   }
@@ -236,16 +285,26 @@ void retire_context(s4_server *s, Context &c, const uint32_t *res) {
 
 void dispatcher(s4_server *s) {
   (void)hipSetDevice(s->device);
+  uint64_t device_ns = 0, host_ns = 0;
   for (;;) {
     bool progressed = false;
     for (Context &c : s->ctx) {
       if (c.busy && hipEventQuery(c.done) == hipSuccess) {
+        const auto t0 = Clock::now();
         if (c.phase == 1) {
+          device_ns += ns_between(c.launched, t0);
+          if (*c.h_err) {
+            std::lock_guard<std::mutex> lock(s->mu);
+            s->worker_error = S4_EDEVICE;
+            s->worker_msg = "single-pass scan failed (look-back guard or output overflow)";
+            s->stop = true;
+          }
           std::vector<uint32_t> spill;
           if (start_copy(s, c, &spill)) retire_context(s, c, spill.empty() ? c.h_results : spill.data());
         } else {
           retire_context(s, c, c.h_results);
         }
+        host_ns += ns_between(t0, Clock::now());
         progressed = true;
       }
     }
@@ -258,29 +317,36 @@ void dispatcher(s4_server *s) {
     bool launched = false;
     if (free_ctx) {
       Context &c = *free_ctx;
+      const auto t0 = Clock::now();
       {
         std::unique_lock<std::mutex> lock(s->mu);
-        uint64_t items = 0, terms = 0;
+        uint64_t items = 0, terms = 0, bound = 0;
         while (!s->waiting.empty() && c.queries.size() < s->slots_per_ctx) {
           const Query &q = s->waiting.front();
-          const bool fits = items + q.items <= s->items_per_ctx && terms + q.terms.size() <= s->terms_per_ctx &&
-                            s->pool_in_use + 4 * s4::kBlock * (items + q.items) <= s->cfg.pool_bytes;
+          const bool fits = items + q.items <= s->items_per_ctx && terms + q.k <= s->terms_per_ctx &&
+                            s->pool_in_use + 4 * s4::kBlock * (items + q.items) <= s->cfg.pool_bytes &&
+                            (c.queries.empty() || bound + q.bound <= s->results_per_ctx);
           if (!fits) {
             if (c.queries.empty()) ++s->st.waits_for_memory;
             break;
           }
           items += q.items;
-          terms += q.terms.size();
+          terms += q.k;
+          bound += q.bound;
           c.queries.push_back(std::move(s->waiting.front()));
           s->waiting.pop_front();
         }
         if (!c.queries.empty()) {
+          c.items = items;
+          c.terms = terms;
+          c.bound = bound;
           c.reserved_stage = 4 * s4::kBlock * items;
           s->pool_in_use += c.reserved_stage;
           s->active += c.queries.size();
           s->st.admitted += c.queries.size();
           s->st.peak_active = std::max(s->st.peak_active, s->active);
           s->st.peak_pool_bytes = std::max(s->st.peak_pool_bytes, s->pool_in_use);
+          s->st.max_batch = std::max<uint64_t>(s->st.max_batch, c.queries.size());
           ++s->st.iterations;
         }
       }
@@ -291,22 +357,64 @@ void dispatcher(s4_server *s) {
           s->worker_error = rc;
           s->worker_msg = s4_last_error();
           s->stop = true;
+        } else {
+          std::lock_guard<std::mutex> lock(s->mu);
+          s->st.direct_iterations += c.direct;
+          s->st.single_pass_iterations += c.single;
         }
         launched = true;
+        host_ns += ns_between(t0, Clock::now());
       }
     }
-    bool idle = false;
+    bool idle = false, any_busy = false;
     {
       std::unique_lock<std::mutex> lock(s->mu);
-      bool any_busy = false;
+      s->st.device_ns = device_ns;
+      s->st.host_ns = host_ns;
       for (Context &c : s->ctx) any_busy |= c.busy;
       if (s->stop && !any_busy && (s->waiting.empty() || s->worker_error)) break;
       idle = !progressed && !launched;
-      if (idle && !any_busy && s->waiting.empty())
+      if (idle && !any_busy && s->waiting.empty()) {
         s->cv.wait_for(lock, std::chrono::milliseconds(1));
+        continue;
+      }
     }
-    if (idle) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    // iterations in flight: poll their events again at once
+    if (idle) std::this_thread::yield();
   }
+}
+
+// Validate a query and put its terms in chain order (no lock needed: the
+// index is immutable while the server exists).
+int prepare_query(const s4_server *s, const uint32_t *terms, uint32_t k, Query *q) {
+  if (k == 0 || k > s->cfg.max_terms) return s4::fail(S4_EINVAL, "query must have 1..max_terms terms");
+  const s4_index *ix = s->index;
+  for (uint32_t j = 0; j < k; ++j) {
+    const uint32_t t = terms[j];
+    if (t >= ix->count) return s4::fail(S4_EINVAL, "term out of range");
+    if (k > 1 && !(ix->flags[t] & 1u)) return s4::fail(S4_EUNSORTED, "list is not strictly increasing");
+    // insertion by length, stable for equal lengths
+    uint32_t p = j;
+    while (p > 0 && ix->lengths[q->terms[p - 1]] > ix->lengths[t]) {
+      q->terms[p] = q->terms[p - 1];
+      --p;
+    }
+    q->terms[p] = t;
+  }
+  q->k = k;
+  const uint64_t m = ix->lengths[q->terms[0]];
+  q->items = (m + s4::kBlock - 1) / s4::kBlock;
+  q->bound = m;
+  if (q->items > s->items_per_ctx || k > s->terms_per_ctx || 4 * s4::kBlock * q->items > s->cfg.pool_bytes)
+    return s4::fail(S4_ERANGE, "query needs more intermediate memory than one iteration holds");
+  return S4_OK;
+}
+
+// Caller holds s->mu.
+int check_open_locked(s4_server *s) {
+  if (s->stop) return s4::fail(S4_EINVAL, "server is stopping");
+  if (s->worker_error) return s4::fail(s->worker_error, "server failed: " + s->worker_msg);
+  return S4_OK;
 }
 
 }  // namespace
@@ -350,31 +458,20 @@ int s4_server_create(const s4_index *index, const s4_server_config *cfg, s4_serv
 
 int s4_server_submit(s4_server *s, const uint32_t *terms, uint32_t k, uint64_t *id) {
   if (!s || !terms || !id) return fail(S4_EINVAL, "null argument");
-  if (k == 0 || k > s->cfg.max_terms) return fail(S4_EINVAL, "query must have 1..max_terms terms");
   Query q;
-  q.terms.assign(terms, terms + k);
-  for (uint32_t t : q.terms) {
-    if (t >= s->index->count) return fail(S4_EINVAL, "term out of range");
-    if (k > 1 && !(s->index->flags[t] & 1u)) return fail(S4_EUNSORTED, "list is not strictly increasing");
-  }
-  std::stable_sort(q.terms.begin(), q.terms.end(),
-                   [&](uint32_t x, uint32_t y) { return s->index->lengths[x] < s->index->lengths[y]; });
-  const uint64_t m = s->index->lengths[q.terms[0]];
-  q.items = (m + kBlock - 1) / kBlock;
-  q.bound = m;
+  int rc = prepare_query(s, terms, k, &q);
   std::lock_guard<std::mutex> lock(s->mu);
-  if (s->stop) return fail(S4_EINVAL, "server is stopping");
-  if (s->worker_error) return fail(s->worker_error, "server failed: " + s->worker_msg);
-  if (q.items > s->items_per_ctx || q.terms.size() > s->terms_per_ctx ||
-      4 * kBlock * q.items > s->cfg.pool_bytes) {
-    ++s->st.rejected;
-    return fail(S4_ERANGE, "query needs more intermediate memory than one iteration holds");
+  if (rc) {
+    if (rc == S4_ERANGE) ++s->st.rejected;
+    return rc;
   }
+  rc = check_open_locked(s);
+  if (rc) return rc;
   if (s->waiting.size() >= 64ull * s->cfg.max_slots) return fail(S4_EAGAIN, "waiting queue full");
   q.id = s->next_id++;
   q.submitted = Clock::now();
   *id = q.id;
-  s->waiting.push_back(std::move(q));
+  s->waiting.push_back(q);
   ++s->st.submitted;
   s->cv.notify_one();
   return S4_OK;
@@ -387,7 +484,7 @@ int s4_server_poll(s4_server *s, uint64_t *ids, uint64_t *counts, uint64_t *late
   std::lock_guard<std::mutex> lock(s->mu);
   uint32_t n = 0;
   uint64_t used = 0;
-  res_offsets[0] = 0;
+  if (max_done) res_offsets[0] = 0;
   while (n < max_done && !s->completed.empty()) {
     Done &d = s->completed.front();
     if (used + d.count > results_cap || (d.count && !results)) break;
@@ -422,46 +519,75 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
   std::vector<std::vector<uint32_t>> res(results ? nq : 0);
   uint64_t ndone = 0, next = 0;
   std::unordered_map<uint64_t, uint64_t> pending;
+  pending.reserve(size_t(std::min<uint64_t>(nq, 64ull * s->cfg.max_slots)));
+  std::vector<Query> due;
+  std::deque<Done> got;
+  std::deque<Clock::time_point> got_at;
   const auto t0 = Clock::now();
-  auto now_ns = [&]() { return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count()); };
-  uint64_t last_done_ns = 0;
+  auto now_ns = [&]() { return ns_between(t0, Clock::now()); };
+  uint64_t last_done_ns = 0, last_drain_ns = 0;
   while (ndone < nq) {
+    // every query due by now, validated without the lock, queued under one
     const uint64_t t = now_ns();
-    // submit everything due
-    while (next < nq && h_arrival_ns[next] <= t) {
-      const uint64_t a = h_q_offsets[next], b = h_q_offsets[next + 1];
-      uint64_t id = 0;
-      int rc = s4_server_submit(s, h_terms + a, uint32_t(b - a), &id);
-      if (rc == S4_EAGAIN) break;
-      if (rc) return rc;
-      pending.emplace(id, next);
-      ++next;
+    due.clear();
+    for (uint64_t q = next; q < nq && h_arrival_ns[q] <= t && due.size() < 8192; ++q) {
+      const uint64_t a = h_q_offsets[q], b = h_q_offsets[q + 1];
+      due.emplace_back();
+      int rc = prepare_query(s, h_terms + a, uint32_t(b - a), &due.back());
+      if (rc) {
+        if (rc == S4_ERANGE) {
+          std::lock_guard<std::mutex> lock(s->mu);
+          ++s->st.rejected;
+        }
+        return rc;
+      }
     }
-    // drain completions
+    // nothing due: take the lock only to drain now and then (latencies are
+    // stamped by the dispatcher, not here)
+    if (due.empty() && t < last_drain_ns + 50000) continue;
+    last_drain_ns = t;
     {
       std::lock_guard<std::mutex> lock(s->mu);
-      while (!s->completed.empty()) {
-        Done &d = s->completed.front();
-        auto it = pending.find(d.id);
-        if (it != pending.end()) {
-          const uint64_t q = it->second;
-          const uint64_t fin = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
-                                            s->completed_at.front() - t0).count());
-          latency_ns[q] = fin > h_arrival_ns[q] ? fin - h_arrival_ns[q] : 0;
-          last_done_ns = std::max(last_done_ns, fin);
-          counts[q] = d.count;
-          if (results) res[q] = std::move(d.result);
-          ++ndone;
-          pending.erase(it);
-        }
-        s->completed.pop_front();
-        s->completed_at.pop_front();
+      int rc = check_open_locked(s);
+      if (rc) return rc;
+      const uint64_t room = 64ull * s->cfg.max_slots - std::min<uint64_t>(s->waiting.size(), 64ull * s->cfg.max_slots);
+      const uint64_t take = std::min<uint64_t>(room, due.size());
+      const auto now = Clock::now();
+      for (uint64_t i = 0; i < take; ++i) {
+        Query &q = due[i];
+        q.id = s->next_id++;
+        q.submitted = now;
+        pending.emplace(q.id, next + i);
+        s->waiting.push_back(q);
       }
-      if (s->worker_error) return fail(s->worker_error, "server failed: " + s->worker_msg);
+      s->st.submitted += take;
+      next += take;
+      if (take) s->cv.notify_one();
+      got.swap(s->completed);
+      got_at.swap(s->completed_at);
+    }
+    // completions, outside the lock
+    while (!got.empty()) {
+      Done &d = got.front();
+      auto it = pending.find(d.id);
+      if (it != pending.end()) {
+        const uint64_t q = it->second;
+        const uint64_t fin = ns_between(t0, got_at.front());
+        latency_ns[q] = fin > h_arrival_ns[q] ? fin - h_arrival_ns[q] : 0;
+        last_done_ns = std::max(last_done_ns, fin);
+        counts[q] = d.count;
+        if (results) res[q] = std::move(d.result);
+        ++ndone;
+        pending.erase(it);
+      }
+      got.pop_front();
+      got_at.pop_front();
     }
     if (double(now_ns()) * 1e-9 > timeout_s) return fail(S4_ERANGE, "replay timed out");
     if (next < nq && h_arrival_ns[next] > now_ns() + 50000)
       std::this_thread::sleep_for(std::chrono::microseconds(10));
+    else if (next == nq)
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
   }
   if (elapsed_s) *elapsed_s = double(last_done_ns - (nq ? h_arrival_ns[0] : 0)) * 1e-9;
   if (results) {

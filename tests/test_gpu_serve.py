@@ -38,10 +38,15 @@ def want(flat, offs, ts):
     return oracle.intersect_k([flat[int(offs[t]): int(offs[t + 1])] for t in ts])
 
 
-def test_server_results_match_oracle(gpu, served):
+@pytest.mark.parametrize("result_bytes", [32 << 20, 3 * 4 * 128])
+def test_server_results_match_oracle(gpu, served, result_bytes):
+    """With a roomy result buffer the device writes results straight to
+    pinned host memory; with one of 128 values per context most iterations
+    go through device memory (an asynchronous copy, or a synchronous one
+    when the total exceeds the buffer)."""
     ix, flat, offs = served
     terms, qoffs = workloads.queries(21, ix.lengths, 600, 1, 8)
-    srv = gpu.Server(ix, max_slots=256, pool_bytes=64 << 20, result_bytes=32 << 20)
+    srv = gpu.Server(ix, max_slots=256, pool_bytes=64 << 20, result_bytes=result_bytes)
     try:
         ids = {}
         for q in range(600):
@@ -53,8 +58,40 @@ def test_server_results_match_oracle(gpu, served):
             assert got[qid][1] > 0
         st = srv.stats()
         assert st["completed"] == 600 and st["admitted"] == 600 and st["iterations"] >= 1
+        assert 1 <= st["max_batch"] <= 256 // 3 and st["device_ns"] > 0
+        if result_bytes > 1 << 20:
+            assert st["direct_iterations"] == st["iterations"]
+        else:
+            assert st["direct_iterations"] < st["iterations"]
     finally:
         srv.close()
+
+
+def test_single_pass_and_staged_iterations(gpu, served):
+    """An iteration of at most one chunk per resident wave runs as one
+    single-pass kernel (look-back offsets), a larger one in the staged form;
+    with one one-wave group per CU (256 resident waves) a mix of queries
+    takes both, and every result still equals the oracle's."""
+    ix, flat, offs = served
+    terms, qoffs = workloads.queries(23, ix.lengths, 800, 2, 6)
+    saved = gpu.get_tuning()
+    gpu.set_tuning(waves_per_group=1, groups_per_cu=1)
+    srv = gpu.Server(ix, max_slots=3 * 1024, pool_bytes=3 << 30, result_bytes=3 << 26)
+    try:
+        small = int(np.argmin(ix.lengths[:64]))
+        first = srv.submit([small, small])
+        drain(srv, [first])
+        # all 800 due at once: queued under one lock, so iterations are large
+        r = srv.replay(terms, qoffs, np.zeros(800, np.uint64), with_results=True, results_cap=1 << 24)
+        for q in range(800):
+            ts = terms[int(qoffs[q]): int(qoffs[q + 1])]
+            got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
+            assert np.array_equal(got, want(flat, offs, ts)), q
+        st = srv.stats()
+        assert 1 <= st["single_pass_iterations"] < st["iterations"], st
+    finally:
+        srv.close()
+        gpu.set_tuning(**{k: getattr(saved, k) for k, _ in saved._fields_})
 
 
 def test_alone_equals_in_mix(gpu, served):
