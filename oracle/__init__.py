@@ -61,6 +61,9 @@ def _bind(path):
     lib.orc_stream_bytes.argtypes = [ctypes.c_uint64, u8p]
     lib.orc_stream_bytes.restype = sz
     lib.orc_intersect.argtypes = [u32p, ctypes.c_uint64, u32p, ctypes.c_uint64, u32p, u64p]
+    lib.orc_hyb_is_bitmap.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
+    lib.orc_hyb_intersect_k.argtypes = [ctypes.POINTER(u32p), u64p, ctypes.c_uint32, ctypes.c_uint64,
+                                        ctypes.c_uint32, u32p, ctypes.c_uint64, u64p]
     lib.orc_intersect_k.argtypes = [ctypes.POINTER(u32p), u64p, ctypes.c_uint32, u32p,
                                     ctypes.c_uint64, u64p]
     for f in (lib.orc_encode, lib.orc_encode_mode, lib.orc_decode, lib.orc_decode_alg1, lib.orc_decoded_length,
@@ -214,4 +217,33 @@ def intersect_k(lists) -> np.ndarray:
                              ctypes.byref(c))
     if rc:
         raise OracleError(rc, "intersect_k")
+    return out[: c.value].copy()
+
+
+def hyb_is_bitmap(n: int, universe: int, gap: int) -> bool:
+    """hyb+m2 rule: a list of n > 0 values is a bitmap when universe / n <= gap."""
+    return bool(_active().orc_hyb_is_bitmap(int(n), int(universe), int(gap)))
+
+
+def hyb_intersect_k(lists, universe: int, gap: int) -> np.ndarray:
+    """Conjunctive query under hyb+m2: SvS over the compressed lists, then
+    bit probes of the bitmap lists (AND of the bitmaps when all are)."""
+    lib = _active()
+    arrs = [np.ascontiguousarray(l, dtype=np.uint32) for l in lists]
+    k = len(arrs)
+    ptrs = (ctypes.POINTER(ctypes.c_uint32) * max(1, k))()
+    keep = []
+    for i, a in enumerate(arrs):
+        if a.size == 0:
+            a = np.zeros(1, np.uint32)[:0]
+        keep.append(a)
+        ptrs[i] = a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    lens = (ctypes.c_uint64 * max(1, k))(*[a.size for a in arrs])
+    cap = min(a.size for a in arrs) if k else 0
+    out = np.zeros(max(1, cap), dtype=np.uint32)
+    c = ctypes.c_uint64(0)
+    rc = lib.orc_hyb_intersect_k(ptrs, lens, k, int(universe), int(gap),
+                                 out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), cap, ctypes.byref(c))
+    if rc:
+        raise OracleError(rc, "hyb_intersect_k")
     return out[: c.value].copy()

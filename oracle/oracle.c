@@ -22,9 +22,9 @@
  *   - Differential coding (Sec. 5), one of four forms recorded in the
  *     stream: D4 delta_i = x_i - x_{i-4}; DM delta_{4i+j} = x_{4i+j} -
  *     x_{4i-1}; D2 delta_i = x_i - x_{i-2}; D1 delta_i = x_i - x_{i-1};
- *     values before the list are 0.  The inverse ("prefix sum") runs over
+ *     values before the list are 0.  The inverse (a prefix sum) runs over
  *     the whole list, seeded with zeros (Alg. 1).
- *   - Intersection: the textbook two-pointer merge ("scalar", Sec. 6) and
+ *   - Intersection: the textbook two-pointer merge (the scalar baseline of Sec. 6) and
  *     SvS folding of k lists (Sec. 6).
  *
  * Readings where the paper is silent or garbled (each is also listed in
@@ -79,9 +79,9 @@ static uint32_t get32(const uint8_t *p) {
 static uint16_t get16(const uint8_t *p) { return (uint16_t)(p[0] | (p[1] << 8)); }
 static uint64_t get64(const uint8_t *p) { return (uint64_t)get32(p) | ((uint64_t)get32(p + 4) << 32); }
 
-/* Sec. 4.3: "the smallest value b such that all corresponding integers are
- * smaller than 2^b".  Written as the definition (increase b until every
- * value fits), in 64-bit arithmetic so that b = 32 is reachable. */
+/* Block width (Sec. 4.3): the least b for which every delta of the block
+ * is below 2^b.  Written as that definition (increase b until every value
+ * fits), in 64-bit arithmetic so that b = 32 is reachable. */
 static uint32_t orc_width(const uint32_t *d, size_t count) {
   uint32_t b = 0;
   for (;;) {
@@ -358,7 +358,7 @@ int orc_decode_alg1(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t ca
   return ORC_OK;
 }
 
-/* Textbook two-pointer merge intersection ("scalar", Sec. 6): advance the
+/* Textbook two-pointer merge intersection (scalar baseline, Sec. 6): advance the
  * pointer at the smaller value; on equality emit once and advance both.
  * Inputs must be strictly increasing.  Safe when out aliases the shorter
  * input (the output-to-input property, Sec. 6.2). */
@@ -398,6 +398,108 @@ int orc_intersect_k(const uint32_t *const *lists, const uint64_t *lens, uint32_t
     if (rc) return rc;
     cur = c;
   }
+  *count = cur;
+  return ORC_OK;
+}
+
+/* hyb+m2 (Sec. 7.7, the bitmap-list hybrid of Culpepper and Moffat): a
+ * list of n > 0 values over the universe [0, U) is kept as a bitmap of U
+ * bits when its average gap U / n is at most B, that is when n * B >= U;
+ * B = 0 means no bitmaps.  Reading: the average gap of a list is the
+ * universe size over its length. */
+int orc_hyb_is_bitmap(uint64_t n, uint64_t universe, uint32_t B) {
+  if (B == 0 || n == 0) return 0;
+  /* n * B >= U  <=>  n >= ceil(U / B), without overflow */
+  return n >= (universe + B - 1u) / B;
+}
+
+/* A conjunctive query under hyb+m2 (Sec. 7.7): the lists that stay
+ * compressed are intersected two at a time starting from the shortest
+ * (SvS with the two-pointer merge), then every surviving value is looked
+ * up in each bitmap in turn and kept only if its bit is set.  When every
+ * list is a bitmap (the paper does not treat this case) the bitmaps are
+ * ANDed word by word and the set bits are read out in increasing order.
+ * Inputs must be strictly increasing; values of bitmap lists must be
+ * below the universe (ORC_EINVAL); a compressed value >= U has no bit and
+ * is dropped by any bitmap.  Result capacity: the shortest list's length
+ * (ORC_ERANGE otherwise). */
+int orc_hyb_intersect_k(const uint32_t *const *lists, const uint64_t *lens, uint32_t k, uint64_t universe,
+                        uint32_t B, uint32_t *out, uint64_t cap, uint64_t *count) {
+  if (!count || k == 0 || k > 64) return ORC_EINVAL;
+  const uint64_t words = (universe + 31u) / 32u;
+  uint32_t comp[64], bm[64];
+  uint32_t nc = 0, nbm = 0;
+  uint64_t shortest = lens[0];
+  for (uint32_t l = 0; l < k; ++l) {
+    for (uint64_t i = 1; i < lens[l]; ++i)
+      if (lists[l][i] <= lists[l][i - 1]) return ORC_EUNSORTED;
+    if (lens[l] < shortest) shortest = lens[l];
+    if (orc_hyb_is_bitmap(lens[l], universe, B)) {
+      if (lists[l][lens[l] - 1] >= universe) return ORC_EINVAL;
+      bm[nbm++] = l;
+    } else {
+      comp[nc++] = l;
+    }
+  }
+  if (cap < shortest) return ORC_ERANGE;
+  /* the bitmaps: bit x of list l is bit (x mod 32) of word floor(x / 32) */
+  uint32_t **bits = NULL;
+  if (nbm) {
+    bits = (uint32_t **)calloc(nbm, sizeof(uint32_t *));
+    if (!bits) return ORC_ENOMEM;
+    for (uint32_t j = 0; j < nbm; ++j) {
+      bits[j] = (uint32_t *)calloc(words ? words : 1u, sizeof(uint32_t));
+      if (!bits[j]) {
+        for (uint32_t i = 0; i < j; ++i) free(bits[i]);
+        free(bits);
+        return ORC_ENOMEM;
+      }
+      const uint32_t *x = lists[bm[j]];
+      for (uint64_t i = 0; i < lens[bm[j]]; ++i) bits[j][x[i] / 32u] |= 1u << (x[i] % 32u);
+    }
+  }
+  uint64_t cur = 0;
+  if (nc) {
+    /* compressed lists by length (stable insertion sort), then SvS */
+    for (uint32_t i = 1; i < nc; ++i)
+      for (uint32_t j = i; j > 0 && lens[comp[j - 1]] > lens[comp[j]]; --j) {
+        const uint32_t t = comp[j];
+        comp[j] = comp[j - 1];
+        comp[j - 1] = t;
+      }
+    cur = lens[comp[0]];
+    memcpy(out, lists[comp[0]], (size_t)cur * sizeof(uint32_t));
+    for (uint32_t i = 1; i < nc; ++i) {
+      uint64_t c = 0;
+      orc_intersect(out, cur, lists[comp[i]], lens[comp[i]], out, &c);
+      cur = c;
+    }
+    /* then the bitmaps, one by one */
+    for (uint32_t j = 0; j < nbm; ++j) {
+      uint64_t c = 0;
+      for (uint64_t i = 0; i < cur; ++i) {
+        const uint32_t x = out[i];
+        if (x < universe && ((bits[j][x / 32u] >> (x % 32u)) & 1u)) out[c++] = x;
+      }
+      cur = c;
+    }
+  } else {
+    for (uint64_t w = 0; w < words; ++w) {
+      uint32_t a = bits[0][w];
+      for (uint32_t j = 1; j < nbm; ++j) a &= bits[j][w];
+      for (uint32_t b = 0; b < 32u; ++b)
+        if ((a >> b) & 1u) {
+          if (cur == cap) { /* more results than the shortest list: impossible */
+            for (uint32_t j = 0; j < nbm; ++j) free(bits[j]);
+            free(bits);
+            return ORC_ERANGE;
+          }
+          out[cur++] = (uint32_t)(32u * w + b);
+        }
+    }
+  }
+  for (uint32_t j = 0; j < nbm; ++j) free(bits[j]);
+  free(bits);
   *count = cur;
   return ORC_OK;
 }

@@ -37,6 +37,14 @@ MUTANTS = {
     "tail_offset": ("out[128u * v.nb + i] = get32(v.tail + 4u * i);\n  return ORC_OK;\n}\n\n/* The vector",
                     "out[128u * v.nb + i] = get32(v.tail);\n  return ORC_OK;\n}\n\n/* The vector"),
     "extract_shift": ("(uint32_t)((window >> s) & mask)", "(uint32_t)((window >> (s + 1)) & mask)"),
+    "hyb_rule_strict": ("return n >= (universe + B - 1u) / B;", "return n > (universe + B - 1u) / B;"),
+    "hyb_rule_floor": ("return n >= (universe + B - 1u) / B;", "return n >= universe / B;"),
+    "hyb_probe_msb_first": ("((bits[j][x / 32u] >> (x % 32u)) & 1u)", "((bits[j][x / 32u] >> (31u - x % 32u)) & 1u)"),
+    "hyb_first_bitmap_skipped": ("for (uint32_t j = 0; j < nbm; ++j) {\n      uint64_t c = 0;",
+                                 "for (uint32_t j = 1; j < nbm; ++j) {\n      uint64_t c = 0;"),
+    "hyb_and_drops_one": ("for (uint32_t j = 1; j < nbm; ++j) a &= bits[j][w];",
+                          "for (uint32_t j = 2; j < nbm; ++j) a &= bits[j][w];"),
+    "hyb_extract_offset": ("out[cur++] = (uint32_t)(32u * w + b);", "out[cur++] = (uint32_t)(32u * w + 31u - b);"),
 }
 
 
@@ -70,6 +78,12 @@ def battery():
     for name in pins.MODES:
         checks.append((f"modes_alg1_{name}", lambda n=name: pins.test_modes_random_access_matches_alg1_walk(n, 17)))
         checks.append((f"modes_rt_{name}", lambda n=name: pins.test_modes_round_trip(n, 2049)))
+    rule_cases = [(128, 1024, 8, True), (127, 1024, 8, False), (32, 1000, 32, True), (31, 1000, 32, False),
+                  (5, 41, 8, False)]
+    checks.append(("hyb_rule", lambda: [pins.test_hyb_bitmap_rule(*c) for c in rule_cases]))
+    checks.append(("hyb_hand", pins.test_hyb_all_bitmaps_and_mixed_by_hand))
+    for sd in range(12):
+        checks.append((f"hyb_sets_{sd}", lambda sd=sd: pins.test_hyb_equals_set_intersection(sd)))
     for name, fn in checks:
         try:
             fn()

@@ -445,3 +445,73 @@ def test_modes_round_trip(name, n):
     assert header(enc)["flags"] >> 1 == MODES[name]
     assert np.array_equal(oracle.decode(enc), x)
     assert np.array_equal(oracle.decode_alg1(enc), x)
+
+
+# ------------------------------------------------------ hyb+m2 (Sec. 7.7)
+
+@pytest.mark.parametrize("n, universe, gap, want", [
+    (128, 1024, 8, True),      # average gap exactly B: a bitmap (at most B)
+    (127, 1024, 8, False),     # just above B
+    (64, 1024, 16, True), (63, 1024, 16, False),
+    (32, 1000, 32, True),      # 1000 / 32 = 31.25
+    (31, 1000, 32, False),     # 32.3
+    (1, 1, 1, True), (5, 40, 8, True), (5, 41, 8, False),
+    (0, 1024, 8, False),       # an empty list is never a bitmap
+    (1 << 20, 1 << 20, 0, False),  # B = 0: no bitmaps
+    ((1 << 32) - 1, 1 << 32, 2, True),
+])
+def test_hyb_bitmap_rule(n, universe, gap, want):
+    """The representation rule: a bitmap exactly when universe / n <= B,
+    checked on boundaries in exact rational arithmetic."""
+    from fractions import Fraction
+    assert oracle.hyb_is_bitmap(n, universe, gap) == want
+    if n and gap:
+        assert (Fraction(universe, n) <= gap) == want
+
+
+def _hyb_brute(lists):
+    s = set(int(v) for v in lists[0])
+    for l in lists[1:]:
+        s &= set(int(v) for v in l)
+    return np.array(sorted(s), dtype=np.uint32)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_hyb_equals_set_intersection(seed):
+    """Whatever lists become bitmaps, the hybrid procedure (SvS over the
+    compressed lists, then bit probes) returns exactly the set
+    intersection; every mix of representations is drawn, including all
+    compressed and all bitmaps, and universes that are not a multiple of 32
+    with the last value U - 1 present."""
+    rng = np.random.default_rng(4400 + seed)
+    universe = int(rng.choice([61, 96, 1000, 4096, 5003]))
+    k = int(rng.integers(1, 6))
+    lists = []
+    for _ in range(k):
+        n = int(rng.integers(0, universe + 1)) if rng.random() < 0.8 else int(rng.integers(universe // 2, universe + 1))
+        v = np.sort(rng.choice(universe, size=n, replace=False)).astype(np.uint32)
+        if n and rng.random() < 0.3:
+            v[-1] = universe - 1 if universe - 1 not in v[:-1] else v[-1]
+            v = np.unique(v)
+        lists.append(v)
+    for gap in (0, 1, 2, 4, 8, 16, 32, 1 << 20):
+        kinds = [oracle.hyb_is_bitmap(l.size, universe, gap) for l in lists]
+        got = oracle.hyb_intersect_k(lists, universe, gap)
+        assert np.array_equal(got, _hyb_brute(lists)), (seed, gap, kinds)
+
+
+def test_hyb_all_bitmaps_and_mixed_by_hand():
+    """Hand-checked cases: multiples of 2 and 3 below 100 (50 and 34
+    values) are bitmaps at B = 4 (gaps 2 and 2.94); {6, 12, 99, 100} stays
+    compressed; 100 >= U has no bit."""
+    m2 = np.arange(0, 100, 2, dtype=np.uint32)
+    m3 = np.arange(0, 100, 3, dtype=np.uint32)
+    few = np.array([6, 12, 99, 100], dtype=np.uint32)
+    assert oracle.hyb_is_bitmap(m2.size, 100, 4) and oracle.hyb_is_bitmap(m3.size, 100, 4)
+    assert not oracle.hyb_is_bitmap(few.size, 100, 4)
+    assert oracle.hyb_intersect_k([m2, m3], 100, 4).tolist() == list(range(0, 100, 6))
+    assert oracle.hyb_intersect_k([few, m2, m3], 100, 4).tolist() == [6, 12]
+    assert oracle.hyb_intersect_k([m3, few], 100, 4).tolist() == [6, 12, 99]
+    assert oracle.hyb_intersect_k([m2], 100, 4).tolist() == m2.tolist()
+    with pytest.raises(oracle.OracleError):  # a bitmap list reaching the universe
+        oracle.hyb_intersect_k([np.arange(0, 101, 2, dtype=np.uint32)], 100, 4)
