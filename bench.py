@@ -230,7 +230,39 @@ def batched(s4, workloads, torch, nq, plain_sample):
         }
         log(f"{name}: {out[name]}")
         del b
+    out["hybrid"] = hybrid(s4, workloads, torch, index, buf, soffs, nq, {k: out[k] for k in ("pairwise", "multiterm")})
     return out
+
+
+def hybrid(s4, workloads, torch, index, buf, soffs, nq, plain):
+    """hyb+m2 (Sec. 7.7): the same index and queries with the lists of
+    average gap <= B held as bitmaps over [0, 2^26), B = 8, 16, 32; each
+    workload under its own autotuned launch parameters, replayed as a graph.
+    Storage in bits/int counts packed payload + width bytes + tails +
+    bitmaps (skip index and select samples apart)."""
+    res = {"none": {"bitmap_lists": 0, "bits_per_int": round(8 * index.payload_bytes / index.total_ints, 3),
+                    **{f"{k}_qps": plain[k]["batched_qps"] for k in plain}}}
+    queries = {"pairwise": workloads.pairwise_queries(index.lengths, nq),
+               "multiterm": workloads.multiterm_queries(index.lengths, nq)}
+    for gap in (8, 16, 32):
+        hx = s4.Index(buf, soffs, universe=1 << 26, bitmap_gap=gap)
+        row = {"bitmap_lists": hx.bitmap_lists, "bitmap_mib": round(hx.bitmap_bytes / 2**20, 1),
+               "bits_per_int": round(8 * hx.payload_bytes / hx.total_ints, 3)}
+        for name, (terms, qoffs) in queries.items():
+            s4.set_tuning(**plain[name]["tuning"])
+            b = s4.Batch(hx, terms, qoffs)
+            stream = torch.cuda.Stream()
+            ms, _ = time_graph(torch, lambda: b.run(use_graph=False), stream, steps=5, warmup=2)
+            abytes, _ = b.traffic()
+            row[f"{name}_qps"] = round(b.nq / (ms / 1e3), 1)
+            row[f"{name}_ms"] = round(ms, 3)
+            row[f"{name}_algorithmic_mb"] = round(abytes / 1e6, 2)
+            row[f"{name}_speedup_vs_no_bitmaps"] = round(plain[name]["batched_ms"] / ms, 3)
+            del b
+        res[f"B={gap}"] = row
+        log(f"hyb+m2 B={gap}: {row}")
+        hx.free()
+    return res
 
 
 def kernel_source_sha():

@@ -249,8 +249,32 @@ int s4_index_lengths(const s4_index *index, uint64_t *lengths);
 int s4_index_info(const s4_index *index, uint64_t *count, uint64_t *total_ints,
                   uint64_t *payload_bytes, uint64_t *index_bytes);
 /* A view of list i of the index usable with every s4_list call; valid
- * until the index is freed; release it with s4_list_free. */
+ * until the index is freed; release it with s4_list_free.  S4_EINVAL for a
+ * list a hybrid index holds as a bitmap. */
 int s4_index_list(const s4_index *index, uint64_t i, s4_list **out);
+
+/* Hybrid index (hyb+m2, Sec. 7.7, after Culpepper and Moffat): as
+ * s4_index_build, but every strictly increasing list whose average gap
+ * universe / n is at most bitmap_gap (B; the paper uses 8, 16 and 32) is
+ * held as a bitmap of `universe` bits (bit x in bit x % 32 of 32-bit word
+ * x / 32) instead of compressed blocks, with one 4-byte select sample per
+ * 128 values; the other lists stay compressed.  Such lists are at least as
+ * long as any compressed one, so a query's SvS order (shortest first)
+ * intersects the compressed lists first and then checks each survivor's
+ * bit in every bitmap list; a query whose lists are all bitmaps walks its
+ * shortest bitmap 128 values at a time.  universe in [1, 2^32]; S4_EINVAL
+ * if bitmap_gap is 0 or a bitmap list has a value >= universe.  The
+ * bitmaps are built on the device from the compressed streams.
+ * s4_index_info's payload_bytes counts the bitmaps, index_bytes the select
+ * samples.  Synchronises `stream`. */
+int s4_index_build_hybrid(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count,
+                          uint64_t universe, uint32_t bitmap_gap, void *stream, s4_index **out);
+/* kinds[count]: 0 for a compressed list, 1 for a bitmap. */
+int s4_index_kinds(const s4_index *index, uint8_t *kinds);
+/* Hybrid parameters and sizes (all 0 for an index built without bitmaps);
+ * any pointer may be null. */
+int s4_index_hybrid_info(const s4_index *index, uint64_t *universe, uint32_t *bitmap_gap,
+                         uint64_t *bitmap_lists, uint64_t *bitmap_bytes, uint64_t *select_bytes);
 
 /* ------------------------------------------------------------------ batch
  *

@@ -91,6 +91,9 @@ SIGNATURES = {
     "s4_index_lengths": (_i, [_vp, _u64p]),
     "s4_index_info": (_i, [_vp, _u64p, _u64p, _u64p, _u64p]),
     "s4_index_list": (_i, [_vp, _u64, ctypes.POINTER(_vp)]),
+    "s4_index_build_hybrid": (_i, [_u8p, _u64p, _u64, _u64, _u32, _vp, ctypes.POINTER(_vp)]),
+    "s4_index_kinds": (_i, [_vp, _u8p]),
+    "s4_index_hybrid_info": (_i, [_vp, _u64p, ctypes.POINTER(_u32), _u64p, _u64p, _u64p]),
     "s4_batch_plan": (_i, [_vp, _u32p, _u64p, _u64, _vp, ctypes.POINTER(_vp)]),
     "s4_batch_free": (_i, [_vp]),
     "s4_batch_results_bound": (_u64, [_vp]),
@@ -407,16 +410,23 @@ def set_tuning(**kw):
 # ----------------------------------------------------------------- index
 
 class Index:
-    """Many device-resident lists in one arena (s4_index)."""
+    """Many device-resident lists (s4_index).  With bitmap_gap = B > 0 the
+    index is a hyb+m2 hybrid: lists with universe / n <= B are bitmaps over
+    [0, universe) (s4_index_build_hybrid)."""
 
-    def __init__(self, streams, offsets, stream=None):
+    def __init__(self, streams, offsets, stream=None, universe=0, bitmap_gap=0):
         lib = require_library()
         streams = np.ascontiguousarray(streams, dtype=np.uint8)
         offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
         self.h = ctypes.c_void_p()
-        _check(lib.s4_index_build(_ptr(streams if streams.size else np.zeros(1, np.uint8), ctypes.c_uint8),
-                                  _ptr(offsets, ctypes.c_uint64), offsets.size - 1, _stream(stream),
-                                  ctypes.byref(self.h)), "s4_index_build")
+        sp = _ptr(streams if streams.size else np.zeros(1, np.uint8), ctypes.c_uint8)
+        if bitmap_gap:
+            _check(lib.s4_index_build_hybrid(sp, _ptr(offsets, ctypes.c_uint64), offsets.size - 1, int(universe),
+                                             int(bitmap_gap), _stream(stream), ctypes.byref(self.h)),
+                   "s4_index_build_hybrid")
+        else:
+            _check(lib.s4_index_build(sp, _ptr(offsets, ctypes.c_uint64), offsets.size - 1, _stream(stream),
+                                      ctypes.byref(self.h)), "s4_index_build")
         self.count = offsets.size - 1
         self.lengths = np.zeros(max(1, self.count), np.uint64)
         _check(lib.s4_index_lengths(self.h, _ptr(self.lengths, ctypes.c_uint64)), "s4_index_lengths")
@@ -425,6 +435,18 @@ class Index:
         _check(lib.s4_index_info(self.h, ctypes.byref(c), ctypes.byref(ti), ctypes.byref(pb), ctypes.byref(ib)),
                "s4_index_info")
         self.total_ints, self.payload_bytes, self.index_bytes = ti.value, pb.value, ib.value
+        u, nbm, bb, sb = (ctypes.c_uint64() for _ in range(4))
+        g = ctypes.c_uint32()
+        _check(lib.s4_index_hybrid_info(self.h, ctypes.byref(u), ctypes.byref(g), ctypes.byref(nbm),
+                                        ctypes.byref(bb), ctypes.byref(sb)), "s4_index_hybrid_info")
+        self.universe, self.bitmap_gap = u.value, g.value
+        self.bitmap_lists, self.bitmap_bytes, self.select_bytes = nbm.value, bb.value, sb.value
+
+    def kinds(self) -> np.ndarray:
+        """1 where the list is held as a bitmap, else 0."""
+        k = np.zeros(max(1, self.count), np.uint8)
+        _check(require_library().s4_index_kinds(self.h, _ptr(k, ctypes.c_uint8)), "s4_index_kinds")
+        return k[: self.count]
 
     def list(self, i) -> DeviceList:
         h = ctypes.c_void_p()

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libs4.so")
 
-SOURCES = ["s4_format.cpp", "s4_device.hip", "s4_batch.hip", "s4_serve.cpp"]
+SOURCES = ["s4_format.cpp", "s4_device.hip", "s4_batch.hip", "s4_hybrid.hip", "s4_serve.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",

@@ -298,53 +298,124 @@ static void drop_graph(s4_batch *b) {
   b->graph = nullptr;
 }
 
-extern "C" {
-
-int s4_index_build(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count, void *stream,
-                   s4_index **out) {
+// Index over count serialized lists; with gap > 0 (hyb+m2) the lists whose
+// average gap universe / n is at most gap, and that are strictly
+// increasing, are held as bitmaps over [0, universe), the rest compressed.
+static int index_build(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count, uint64_t universe,
+                       uint32_t gap, hipStream_t st, s4_index **out) {
   if (!out || !enc_offsets || (count && !encs)) return fail(S4_EINVAL, "null argument");
   if (count > 0xFFFFFFFFull) return fail(S4_EINVAL, "too many lists");
-  Upload u;
-  u.views.resize(count);
+  if (gap && (universe == 0 || universe > (1ull << 32)))
+    return fail(S4_EINVAL, "universe must be in [1, 2^32] for a hybrid index");
+  int rc = ensure_device();
+  if (rc) return rc;
+  std::vector<StreamView> views(count);
   for (uint64_t i = 0; i < count; ++i) {
     if (enc_offsets[i + 1] < enc_offsets[i]) return fail(S4_EINVAL, "offsets decrease");
-    int rc = parse_stream(encs + enc_offsets[i], size_t(enc_offsets[i + 1] - enc_offsets[i]), &u.views[i]);
+    rc = parse_stream(encs + enc_offsets[i], size_t(enc_offsets[i + 1] - enc_offsets[i]), &views[i]);
     if (rc) return fail(rc, "list " + std::to_string(i) + ": " + s4_last_error());
   }
   s4_index *ix = new (std::nothrow) s4_index;
   if (!ix) return fail(S4_ENOMEM, "handle allocation failed");
-  int rc = build_arena(u, as_stream(stream), &ix->arena, &ix->lists);
-  if (rc) {
+  auto drop = [&](int code) {
+    if (ix->arena) (void)hipFree(ix->arena);
+    if (ix->bitmaps) (void)hipFree(ix->bitmaps);
+    if (ix->desc) (void)hipFree(ix->desc);
     delete ix;
-    return rc;
-  }
-  hipError_t e = hipStreamSynchronize(as_stream(stream));
-  if (e != hipSuccess) {
-    (void)hipFree(ix->arena);
-    delete ix;
-    return hip_fail(e, "index build");
-  }
+    return code;
+  };
   ix->count = count;
-  ix->d_lists = reinterpret_cast<const DList *>(static_cast<char *>(ix->arena) + u.lay.desc_off);
+  ix->universe = universe;
+  ix->gap = gap;
+  ix->kinds.assign(count, 0);
+  Upload uc, ub;
+  std::vector<uint64_t> slot(count);
+  for (uint64_t i = 0; i < count; ++i) {
+    const StreamView &v = views[i];
+    const bool bitmap = (v.flags & 1u) && hyb_is_bitmap(v.n, universe, gap);
+    ix->kinds[i] = bitmap ? 1 : 0;
+    Upload &u = bitmap ? ub : uc;
+    slot[i] = u.views.size();
+    u.views.push_back(v);
+  }
+  std::vector<DList> dc, db;
+  if (!uc.views.empty()) {
+    rc = build_arena(uc, st, &ix->arena, &dc);
+    if (rc) return drop(rc);
+  }
+  if (!ub.views.empty()) {
+    rc = build_bitmaps(ub, universe, st, &ix->bitmaps, &db, &ix->bitmap_bytes, &ix->select_bytes);
+    if (rc) return drop(rc);
+  }
+  ix->lists.resize(count);
+  for (uint64_t i = 0; i < count; ++i) ix->lists[i] = ix->kinds[i] ? db[slot[i]] : dc[slot[i]];
+  hipError_t e = hipMalloc(&ix->desc, sizeof(DList) * std::max<uint64_t>(count, 1));
+  if (e != hipSuccess) return drop(fail(S4_ENOMEM, "descriptor table allocation failed"));
+  if (count) e = hipMemcpyAsync(ix->desc, ix->lists.data(), sizeof(DList) * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return drop(hip_fail(e, "index build"));
+  ix->d_lists = static_cast<const DList *>(ix->desc);
   ix->lengths.resize(count);
   ix->flags.resize(count);
   ix->pw.resize(count);
   for (uint64_t i = 0; i < count; ++i) {
-    const StreamView &v = u.views[i];
+    const StreamView &v = views[i];
     ix->lengths[i] = v.n;
-    ix->pw[i] = v.pw;
     ix->flags[i] = v.flags;
     ix->total_ints += v.n;
-    ix->payload_bytes += uint64_t(v.nb) + 4 * v.pw + 4ull * v.t;
-    ix->index_bytes += uint64_t(v.nb) * (4 + 4 + 16);
+    if (ix->kinds[i]) {
+      ix->pw[i] = 0;
+      ++ix->bitmap_lists;
+    } else {
+      ix->pw[i] = v.pw;
+      ix->payload_bytes += uint64_t(v.nb) + 4 * v.pw + 4ull * v.t;
+      ix->index_bytes += uint64_t(v.nb) * (4 + 4 + 16);
+    }
   }
+  ix->payload_bytes += ix->bitmap_bytes;
+  ix->index_bytes += ix->select_bytes;
   *out = ix;
+  return S4_OK;
+}
+
+extern "C" {
+
+int s4_index_build(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count, void *stream,
+                   s4_index **out) {
+  return index_build(encs, enc_offsets, count, 0, 0, as_stream(stream), out);
+}
+
+int s4_index_build_hybrid(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count, uint64_t universe,
+                          uint32_t bitmap_gap, void *stream, s4_index **out) {
+  if (bitmap_gap == 0) return fail(S4_EINVAL, "bitmap_gap must be > 0 (s4_index_build builds without bitmaps)");
+  return index_build(encs, enc_offsets, count, universe, bitmap_gap, as_stream(stream), out);
+}
+
+int s4_index_kinds(const s4_index *ix, uint8_t *kinds) {
+  if (!ix || (ix->count && !kinds)) return fail(S4_EINVAL, "null argument");
+  std::copy(ix->kinds.begin(), ix->kinds.end(), kinds);
+  return S4_OK;
+}
+
+int s4_index_hybrid_info(const s4_index *ix, uint64_t *universe, uint32_t *bitmap_gap, uint64_t *bitmap_lists,
+                         uint64_t *bitmap_bytes, uint64_t *select_bytes) {
+  if (!ix) return fail(S4_EINVAL, "null index");
+  if (universe) *universe = ix->universe;
+  if (bitmap_gap) *bitmap_gap = ix->gap;
+  if (bitmap_lists) *bitmap_lists = ix->bitmap_lists;
+  if (bitmap_bytes) *bitmap_bytes = ix->bitmap_bytes;
+  if (select_bytes) *select_bytes = ix->select_bytes;
   return S4_OK;
 }
 
 int s4_index_free(s4_index *ix) {
   if (!ix) return S4_OK;
-  hipError_t e = ix->arena ? hipFree(ix->arena) : hipSuccess;
+  hipError_t e = hipSuccess;
+  for (void *p : {ix->arena, ix->bitmaps, ix->desc})
+    if (p) {
+      const hipError_t f = hipFree(p);
+      if (e == hipSuccess) e = f;
+    }
   delete ix;
   if (e != hipSuccess) return hip_fail(e, "hipFree");
   return S4_OK;
@@ -369,6 +440,7 @@ int s4_index_info(const s4_index *ix, uint64_t *count, uint64_t *total_ints, uin
 int s4_index_list(const s4_index *ix, uint64_t i, s4_list **out) {
   if (!ix || !out) return fail(S4_EINVAL, "null argument");
   if (i >= ix->count) return fail(S4_ERANGE, "list id out of range");
+  if (ix->kinds[i]) return fail(S4_EINVAL, "list " + std::to_string(i) + " is held as a bitmap (hybrid index)");
   s4_list *l = new (std::nothrow) s4_list;
   if (!l) return fail(S4_ENOMEM, "handle allocation failed");
   const DList &d = ix->lists[i];

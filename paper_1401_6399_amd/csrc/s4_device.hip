@@ -451,7 +451,7 @@ static DList make_desc(const Upload &u, size_t i, char *base) {
   d.nb = u.views[i].nb;
   d.t = u.views[i].t;
   d.mode = (u.views[i].flags >> 1) & 3u;
-  d.pad_ = 0;
+  d.words = 0;
   return d;
 }
 

@@ -31,9 +31,15 @@ struct DList {
   uint64_t n;
   uint32_t nb;
   uint32_t t;
-  uint32_t mode;  // differential form, S4_DELTA_*
-  uint32_t pad_;
+  uint32_t mode;   // differential form, S4_DELTA_*, or kBitmapList
+  uint32_t words;  // bitmap lists: bitmap length in 32-bit words (else 0)
 };
+// DList.mode of a list stored as a bitmap (hybrid index): payload holds
+// ceil(U / 32) words, bit x of the list being bit x % 32 of word x / 32;
+// bmax holds one select sample per 128 values (chunk k: the value of rank
+// 128 k, so the chunk starts at that bit); nb = ceil(n / 128), t = 0;
+// widths, offs, seeds and tail are null.
+constexpr uint32_t kBitmapList = 8;
 
 // Parsed header of a serialized stream (host).
 struct StreamView {
@@ -81,6 +87,16 @@ struct Upload {
 // Copy parsed streams into a new device arena (descriptor table at
 // lay.desc_off) and build the skip index on `stream`.
 int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DList> *descs);
+// hyb+m2 (Sec. 7.7): a list of n > 0 values over [0, universe) is a
+// bitmap when universe / n <= gap (gap 0: never).
+inline bool hyb_is_bitmap(uint64_t n, uint64_t universe, uint32_t gap) {
+  return gap && n && n >= (universe + gap - 1) / gap;
+}
+// Build the bitmap lists of u (universe bits each, with select samples) in
+// one new device allocation *mem; descs receives their descriptors.
+// S4_EINVAL if a value reaches the universe.  Synchronises stream.
+int build_bitmaps(Upload &u, uint64_t universe, hipStream_t stream, void **mem, std::vector<DList> *descs,
+                  uint64_t *bitmap_bytes, uint64_t *select_bytes);
 // Decode blocks [first, first + count) of L into d_out (index nb = tail).
 int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream);
 // The same, the kernel launched so that ev0 / ev1 record its start and end.
@@ -140,10 +156,15 @@ struct s4_list {
 };
 
 struct s4_index {
-  void *arena = nullptr;
+  void *arena = nullptr;    // compressed lists
+  void *bitmaps = nullptr;  // bitmap lists and their select samples (hybrid index)
+  void *desc = nullptr;     // device descriptor table
   uint64_t count = 0, total_ints = 0, payload_bytes = 0, index_bytes = 0;
+  uint64_t universe = 0, bitmap_lists = 0, bitmap_bytes = 0, select_bytes = 0;
+  uint32_t gap = 0;         // hyb+m2 parameter B (0: no bitmaps)
   std::vector<s4::DList> lists;    // host copy of the descriptors
   std::vector<uint64_t> lengths, pw;
   std::vector<uint32_t> flags;
+  std::vector<uint8_t> kinds;      // 1: bitmap
   const s4::DList *d_lists = nullptr;  // device copy
 };

@@ -312,6 +312,39 @@ struct Traffic {
   uint64_t blocks = 0;
 };
 
+// Chunk `item` of a bitmap list (its values of rank 128 item .. 128 item +
+// 127) into s.r: from the chunk's select sample (its first value), 64 words
+// at a time, each lane takes one word, an inclusive wave scan of the
+// popcounts places its set bits, and lanes write their values in
+// increasing order.  Returns the number of values (uniform).
+__device__ __forceinline__ uint32_t load_bitmap_chunk(const DList &L, uint32_t item, ItemLds &s, Traffic &tr) {
+  const uint32_t lane = lane_id();
+  const uint64_t base = uint64_t(item) * kBlock;
+  const uint32_t want = L.n > base ? uint32_t(min<uint64_t>(kBlock, L.n - base)) : 0u;
+  uint32_t got = 0;
+  if (want) {
+    const uint32_t first = uniform(L.bmax[item]);
+    const uint32_t w0 = first >> 5;
+    tr.bytes += 4u;
+    for (uint32_t w = w0; got < want && w < L.words; w += 64) {
+      const uint32_t wi = w + lane;
+      uint32_t word = wi < L.words ? L.payload[wi] : 0u;
+      if (wi == w0) word &= ~((1u << (first & 31u)) - 1u);  // bits of earlier chunks
+      tr.bytes += 4u * min(64u, L.words - w);
+      const uint32_t pc = uint32_t(__popc(word));
+      const uint32_t incl = scan_wave64(pc);
+      uint32_t pos = got + incl - pc;
+      while (word && pos < want) {
+        s.r[pos++] = (wi << 5) | uint32_t(__builtin_ctz(word));
+        word &= word - 1u;
+      }
+      got += uint32_t(__builtin_amdgcn_readlane(int(incl), 63));
+    }
+  }
+  wave_sync();
+  return min(got, want);
+}
+
 // Load chunk `item` of r (values 128 item .. 128 item + 127) into s.r;
 // returns how many values it has.  The whole wave calls this.
 __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, ItemLds &s, Traffic &tr) {
@@ -323,6 +356,8 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     cnt = left < kBlock ? uint32_t(left) : kBlock;
     if (lane < cnt) s.r[lane] = r.raw[base + lane];
     if (lane + 64 < cnt) s.r[lane + 64] = r.raw[base + 64 + lane];
+  } else if (r.L.mode == kBitmapList) {
+    return load_bitmap_chunk(r.L, item, s, tr);
   } else if (item < r.L.nb) {
     cnt = kBlock;
     tr.bytes += 16u * uniform(r.L.widths[item]) + 1u + 4u + 16u;
@@ -347,6 +382,19 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
   if (r.raw || item >= r.L.nb) tr.bytes += 4u * cnt;
   wave_sync();
   return cnt;
+}
+
+// Ordered compaction (ballot + mbcnt), in place: lane values a0 (position
+// lane) and a1 (position lane + 64) are kept where f0 / f1; returns the
+// number kept (uniform).
+__device__ __forceinline__ uint32_t compact_chunk(bool f0, bool f1, uint32_t a0, uint32_t a1, ItemLds &s) {
+  const uint64_t mm0 = __ballot(f0), mm1 = __ballot(f1);
+  const uint32_t k0 = uint32_t(__popcll(mm0));
+  wave_sync();
+  if (f0) s.r[mbcnt64(mm0)] = a0;
+  if (f1) s.r[k0 + mbcnt64(mm1)] = a1;
+  wave_sync();
+  return k0 + uint32_t(__popcll(mm1));
 }
 
 // Intersect the sorted values s.r[0 .. cnt) with list f; the values found
@@ -442,14 +490,22 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
       wave_sync();
     }
   }
-  // ordered compaction of the survivors (ballot + mbcnt), in place
-  const uint64_t mm0 = __ballot(f0), mm1 = __ballot(f1);
-  const uint32_t k0 = uint32_t(__popcll(mm0));
-  wave_sync();
-  if (f0) s.r[mbcnt64(mm0)] = a0;
-  if (f1) s.r[k0 + mbcnt64(mm1)] = a1;
-  wave_sync();
-  return k0 + uint32_t(__popcll(mm1));
+  return compact_chunk(f0, f1, a0, a1, s);
+}
+
+// Keep the values s.r[0 .. cnt) whose bit is set in bitmap list f (hyb+m2,
+// Sec. 7.7: the survivors of the compressed lists are checked against the
+// bitmaps one by one): one word gathered per value, then ordered compaction.
+__device__ __forceinline__ uint32_t probe_chunk(uint32_t cnt, const DList &f, ItemLds &s, Traffic &tr) {
+  const uint32_t lane = lane_id();
+  const bool v0 = lane < cnt, v1 = lane + 64 < cnt;
+  const uint32_t a0 = v0 ? s.r[lane] : 0u;
+  const uint32_t a1 = v1 ? s.r[lane + 64] : 0u;
+  bool f0 = false, f1 = false;
+  if (v0 && (a0 >> 5) < f.words) f0 = (f.payload[a0 >> 5] >> (a0 & 31u)) & 1u;
+  if (v1 && (a1 >> 5) < f.words) f1 = (f.payload[a1 >> 5] >> (a1 & 31u)) & 1u;
+  tr.bytes += 4u * cnt;
+  return compact_chunk(f0, f1, a0, a1, s);
 }
 
 // Write s.r[0 .. cnt) to out and cnt to *count.
@@ -462,14 +518,17 @@ __device__ __forceinline__ void store_chunk(uint32_t cnt, const ItemLds &s, uint
 }
 
 // SvS over one chunk: intersect chunk `item` of r with lists f[0 .. nf) in
-// order, stopping early when nothing survives (Sec. 6: "intersect them
-// two-by-two, starting with the smallest").  Intersection distributes over
-// a partition of the shortest list, so chunks are independent.
+// order, stopping early when nothing survives (Sec. 6: pairwise, from the
+// shortest list up).  Intersection distributes over a partition of the
+// shortest list, so chunks are independent.
 template <class FList>
 __device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, FList f, uint32_t nf, ItemLds &s,
                                                 uint32_t gallop_blocks, Traffic &tr) {
   uint32_t cnt = load_chunk(r, item, s, tr);
-  for (uint32_t j = 0; j < nf && cnt > 0; ++j) cnt = intersect_chunk(cnt, f(j), s, gallop_blocks, tr);
+  for (uint32_t j = 0; j < nf && cnt > 0; ++j) {
+    const DList fj = f(j);
+    cnt = fj.mode == kBitmapList ? probe_chunk(cnt, fj, s, tr) : intersect_chunk(cnt, fj, s, gallop_blocks, tr);
+  }
   tr.bytes += 4u * cnt;  // the chunk's results
   return cnt;
 }
