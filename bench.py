@@ -18,7 +18,8 @@ Also reported:
                 path, with p50 / p99 query latency;
   cpu_baseline  the oracle's decode timed on the host cores.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the engine runs on one GPU
+(sharding by document-ID range across GPUs is a design, not code).
 """
 from __future__ import annotations
 
@@ -49,6 +50,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-passes", type=int, default=16)
     ap.add_argument("--decode-only", action="store_true", help="skip the batched and CPU legs (for profiling)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched leg and print its JSON (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB three times with a plain copy kernel (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -142,15 +145,15 @@ def cpu_baseline(flat, offs, passes):
         encs = list(ex.map(lambda i: oracle.encode(flat[int(offs[i]): int(offs[i + 1])]), range(n)))
     order = sorted(range(n), key=lambda i: -int(offs[i + 1] - offs[i]))
     done = 0
-    t0 = time.perf_counter()
+    t0, c0 = time.perf_counter(), time.process_time()
     for _ in range(passes):
         with ThreadPoolExecutor(threads) as ex:
             for r in ex.map(lambda i: oracle.decode(encs[i]).size, order):
                 done += r
-    dt = time.perf_counter() - t0
+    dt, cpu = time.perf_counter() - t0, time.process_time() - c0
     return {"value": round(done / dt / 1e9, 4), "unit": "Gint/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle decode of all {n} bulk lists ({int(offs[-1])} ints), {passes} passes, "
-                      f"{threads} threads, {dt:.1f} s wall"}
+                      f"{threads} threads, {dt:.1f} s wall, {cpu:.1f} s CPU"}
 
 
 def delta_forms(s4, torch, flat, offs, outs, stream, steps, warmup):
@@ -396,8 +399,8 @@ def main():
     if args.calibrate_copy:
         return calibrate_copy()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in DESIGN.md "
-                                   "and not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the engine runs on one GPU; sharding across GPUs (by document-ID range) "
+                                   "is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
@@ -406,6 +409,10 @@ def main():
 
     s4.require_library()
     torch.cuda.set_device(0)
+    if args.batched_only:
+        print(json.dumps({"batched": batched(s4, workloads, torch, args.batch_queries, args.plain_sample)}),
+              flush=True)
+        return
     flat, offs, kinds, buf, soffs, lists, outs, out = build_bulk(s4, workloads, torch)
     ns = np.array([l.n for l in lists], dtype=np.float64)
     rbytes = np.array([l.payload_bytes for l in lists], dtype=np.float64)
