@@ -329,7 +329,8 @@ int s4_batch_autotune(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offse
  * completion in one persistent decode-fused launch (a single-pass kernel
  * with look-back offsets when the iteration has at most one 128-value
  * chunk per resident wave, else chunk kernel + scan + compaction), and
- * retires them.
+ * retires them.  Queries longer than slice_chunks chunks run a slice per
+ * iteration (see s4_server_config).
  * Queries that arrive while iterations run join the next free context, so
  * up to three iterations overlap on the device.  Submission never blocks
  * on the GPU.
@@ -342,12 +343,17 @@ typedef struct {
                                128-value chunk of its shortest list) */
   uint64_t result_bytes;    /* pinned host memory for results in flight (0: 64 MiB) */
   uint32_t max_terms;       /* longest query accepted */
+  uint32_t slice_chunks;    /* most 128-value chunks of one query's shortest list per iteration
+                               (0: 16384); a longer query runs one slice per iteration, its
+                               slices' results joined in order, so it never holds the device
+                               long while short queries wait; an iteration takes at most four
+                               slices' worth of chunks */
 } s4_server_config;
 
 int s4_server_create(const s4_index *index, const s4_server_config *cfg, s4_server **out);
 /* Submit a query (host terms[k]); *id receives its ticket.  S4_EINVAL for
- * bad terms, S4_ERANGE if it can never fit the pool, S4_EAGAIN if the
- * waiting queue is full. */
+ * bad terms, S4_ERANGE if one slice of it can never fit the pool, S4_EAGAIN
+ * if the waiting queue is full. */
 int s4_server_submit(s4_server *srv, const uint32_t *terms, uint32_t k, uint64_t *id);
 /* Retrieve up to max_done finished queries: ids[], counts[], latency_ns[]
  * (submit -> result on host).  Results are copied to host memory:
@@ -366,6 +372,7 @@ typedef struct {
   uint64_t max_batch;        /* most queries admitted into one iteration */
   uint64_t direct_iterations;/* iterations whose results the device wrote straight to pinned host memory */
   uint64_t single_pass_iterations; /* iterations run as one single-pass kernel (at most one chunk per resident wave) */
+  uint64_t sliced_queries;   /* queries run in more than one slice */
   uint64_t device_ns;        /* summed launch-to-finish time of iterations, as seen by the dispatcher */
   uint64_t host_ns;          /* dispatcher time spent packing, launching and retiring iterations */
 } s4_server_stats;

@@ -41,7 +41,8 @@ class Tuning(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_uint32), ("pool_bytes", ctypes.c_uint64),
-                ("result_bytes", ctypes.c_uint64), ("max_terms", ctypes.c_uint32)]
+                ("result_bytes", ctypes.c_uint64), ("max_terms", ctypes.c_uint32),
+                ("slice_chunks", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -50,7 +51,7 @@ class ServerStats(ctypes.Structure):
                 ("iterations", ctypes.c_uint64), ("peak_active", ctypes.c_uint64),
                 ("peak_pool_bytes", ctypes.c_uint64), ("waits_for_memory", ctypes.c_uint64),
                 ("max_batch", ctypes.c_uint64), ("direct_iterations", ctypes.c_uint64),
-                ("single_pass_iterations", ctypes.c_uint64),
+                ("single_pass_iterations", ctypes.c_uint64), ("sliced_queries", ctypes.c_uint64),
                 ("device_ns", ctypes.c_uint64), ("host_ns", ctypes.c_uint64)]
 
     def as_dict(self):
@@ -537,8 +538,9 @@ class Batch:
 class Server:
     """Continuous-batching query server (s4_server)."""
 
-    def __init__(self, index: Index, max_slots=4096, pool_bytes=1 << 30, result_bytes=1 << 28, max_terms=8):
-        cfg = ServerConfig(max_slots, pool_bytes, result_bytes, max_terms)
+    def __init__(self, index: Index, max_slots=4096, pool_bytes=1 << 30, result_bytes=1 << 28, max_terms=8,
+                 slice_chunks=0):
+        cfg = ServerConfig(max_slots, pool_bytes, result_bytes, max_terms, slice_chunks)
         self.index = index
         self.h = ctypes.c_void_p()
         _check(require_library().s4_server_create(index.h, ctypes.byref(cfg), ctypes.byref(self.h)),

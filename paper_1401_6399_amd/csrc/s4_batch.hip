@@ -138,8 +138,8 @@ __device__ uint32_t lookback(uint64_t *__restrict__ state, uint32_t item, uint32
 
 // Single-pass persistent chunk kernel: as k_batch_chunks, but every chunk
 // writes its survivors straight to out at the offset found by look-back,
-// and the first chunk of each query writes that query's CSR offset (and
-// those of any chunkless queries just before it; the last chunk closes the
+// and the first chunk of each entry writes that entry's CSR offset (and
+// those of any chunkless entries just before it; the last chunk closes the
 // table).  No staging, no per-query stamps.
 template <int WAVES>
 __global__ __launch_bounds__(WAVES * 64) void k_serve_chunks(BatchDev b, uint32_t grab, uint32_t gallop_blocks,
@@ -175,8 +175,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_serve_chunks(BatchDev b, uint32_
       } else if (lane == 0) {
         *b.err = 1u;
       }
-      if (local == 0) {
-        const uint32_t q0 = item ? uniform(b.item_info[item - 1].x) + 1 : 0u;
+      // first chunk of its entry (entries may start at any chunk of their
+      // query): the previous chunk belongs to an earlier entry
+      const uint32_t qprev = item ? uniform(b.item_info[item - 1].x) : kInvalid;
+      if (item == 0 || qprev != q) {
+        const uint32_t q0 = item ? qprev + 1 : 0u;
         for (uint32_t qq = q0 + lane; qq <= q; qq += 64) offs[qq] = excl;
       }
       if (item + 1 == b.items)

@@ -7,10 +7,16 @@
 //   1. retires contexts whose iteration has finished on the device (an event
 //      query, never a wait), handing results to the completed queue and
 //      releasing their memory reservation;
-//   2. admits waiting queries, oldest first, into a free context while the
-//      context's slot count, chunk memory (the output-to-input bound: at
-//      most 128 survivors per 128-value chunk of the shortest list) and
-//      result memory (at most the shortest list's length per query) all fit;
+//   2. fills a free context: first one slice of every query already running
+//      in slices, then waiting queries, oldest first, while the context's
+//      slot count, chunk memory (the output-to-input bound: at most 128
+//      survivors per 128-value chunk of the shortest list), result memory
+//      (at most the shortest list's length per query) and the iteration's
+//      chunk budget all fit.  A query of more than `slice` chunks is run a
+//      slice of its chunks per iteration (intersection distributes over a
+//      partition of the shortest list) so that it never holds the device
+//      for long while small queries wait behind it; its slices' results are
+//      joined in chunk order when the last one retires;
 //   3. launches the admitted queries as one batch on that context's stream:
 //      one upload of the packed query tables (which also resets the work
 //      queue), then, for an iteration of at most one chunk per resident
@@ -30,6 +36,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -59,6 +66,27 @@ struct Done {
   std::vector<uint32_t> result;
 };
 
+// A query run in several slices (owned by the dispatcher thread).
+struct Job {
+  Query q;
+  uint64_t next = 0;         // first chunk not admitted yet
+  uint32_t outstanding = 0;  // slices admitted and not retired
+  std::vector<std::pair<uint64_t, std::vector<uint32_t>>> parts;  // (first chunk, results) per retired slice
+};
+
+// A query's share of one iteration: chunks [c0, c1) of its shortest list.
+struct Slice {
+  Query q;             // the whole query (job == nullptr)
+  Job *job = nullptr;  // or the job this slice belongs to
+  uint64_t c0 = 0, c1 = 0;
+  const Query &query() const { return job ? job->q : q; }
+  // values of the shortest list in the slice: the bound on its results
+  uint64_t bound() const {
+    const uint64_t m = query().bound;
+    return std::min<uint64_t>(m, s4::kBlock * c1) - std::min<uint64_t>(m, s4::kBlock * c0);
+  }
+};
+
 struct Context {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
@@ -76,7 +104,7 @@ struct Context {
   uint64_t *h_offs = nullptr, *d_offs = nullptr;  // pinned, device-mapped: CSR offsets
   uint32_t *h_err = nullptr, *d_err = nullptr;    // pinned, device-mapped: scan failure flag
   uint32_t *d_results = nullptr;  // device, 128 values per chunk
-  std::vector<Query> queries;
+  std::vector<Slice> slices;
   uint64_t items = 0, terms = 0, bound = 0;
   bool busy = false;
   bool direct = false;  // results written to h_results by the device
@@ -92,6 +120,9 @@ struct s4_server {
   const s4_index *index = nullptr;
   s4_server_config cfg{};
   uint64_t slots_per_ctx = 0, items_per_ctx = 0, results_per_ctx = 0, terms_per_ctx = 0;
+  uint64_t slice = 0;        // most chunks of one query per iteration
+  uint64_t iter_items = 0;   // chunk budget of an iteration (a lone first slice aside)
+  std::list<Job> jobs;       // queries running in slices (dispatcher only)
   Context ctx[kContexts];
   std::mutex mu;
   std::condition_variable cv;
@@ -180,7 +211,7 @@ void free_context(Context &c) {
 // Launch the queries gathered in c (caller holds no lock; c is private to
 // the dispatcher while busy).
 int launch_context(s4_server *s, Context &c) {
-  const uint64_t nq = c.queries.size(), items = c.items;
+  const uint64_t nq = c.slices.size(), items = c.items;
   uint32_t *head = reinterpret_cast<uint32_t *>(c.h_tab);
   uint32_t *sterms = reinterpret_cast<uint32_t *>(c.h_tab + terms_at());
   uint32_t *ib = reinterpret_cast<uint32_t *>(c.h_tab + bases_at(c.terms));
@@ -188,18 +219,20 @@ int launch_context(s4_server *s, Context &c) {
   std::memset(head, 0, 16);
   uint64_t t = 0, it = 0;
   for (uint64_t q = 0; q < nq; ++q) {
-    const Query &qq = c.queries[q];
+    const Slice &sl = c.slices[q];
+    const Query &qq = sl.query();
     ib[q] = uint32_t(it);
     for (uint32_t j = 0; j < qq.k; ++j) sterms[t + j] = qq.terms[j];
-    for (uint64_t i = 0; i < qq.items; ++i) {
+    const uint64_t n = sl.c1 - sl.c0;
+    for (uint64_t i = 0; i < n; ++i) {
       uint32_t *rec = iq + 4 * (it + i);
       rec[0] = uint32_t(q);
-      rec[1] = uint32_t(i);
+      rec[1] = uint32_t(sl.c0 + i);
       rec[2] = uint32_t(t);
       rec[3] = qq.k;
     }
     t += qq.k;
-    it += qq.items;
+    it += n;
   }
   ib[nq] = uint32_t(it);
   c.direct = c.bound <= s->results_per_ctx;
@@ -241,7 +274,7 @@ int launch_context(s4_server *s, Context &c) {
 // Kernels done: copy exactly the results back (asynchronously when they
 // fit the pinned buffer).  Returns true when the context can retire now.
 bool start_copy(s4_server *s, Context &c, std::vector<uint32_t> *spill) {
-  const uint64_t total = c.h_offs[c.queries.size()];
+  const uint64_t total = c.h_offs[c.slices.size()];
   if (c.direct || total == 0) return true;
   if (total <= s->results_per_ctx) {
     if (hipMemcpyAsync(c.h_results, c.d_results, 4 * total, hipMemcpyDeviceToHost, c.stream) == hipSuccess &&
@@ -255,19 +288,50 @@ bool start_copy(s4_server *s, Context &c, std::vector<uint32_t> *spill) {
   return true;
 }
 
-// Move a finished context's results to the completed queue.
+// The CSR offsets the device wrote for c: non-decreasing, within the
+// iteration's result bound.
+bool offsets_valid(const Context &c) {
+  if (c.h_offs[0] != 0) return false;
+  for (size_t i = 0; i < c.slices.size(); ++i)
+    if (c.h_offs[i + 1] < c.h_offs[i] || c.h_offs[i + 1] - c.h_offs[i] > c.slices[i].bound()) return false;
+  return true;
+}
+
+// Move a finished context's results to the completed queue: whole queries
+// at once, slices into their job (finished jobs joined in chunk order).
 void retire_context(s4_server *s, Context &c, const uint32_t *res) {
   const auto now = Clock::now();
   std::vector<Done> out;
-  out.reserve(c.queries.size());
-  for (size_t q = 0; q < c.queries.size(); ++q) {
-    const uint64_t o0 = c.h_offs[q], cnt = c.h_offs[q + 1] - o0;
+  out.reserve(c.slices.size());
+  auto done_of = [&](const Query &q, std::vector<uint32_t> &&r) {
     Done d;
-    d.id = c.queries[q].id;
-    d.count = cnt;
-    d.latency_ns = ns_between(c.queries[q].submitted, now);
-    d.result.assign(res + o0, res + o0 + cnt);
+    d.id = q.id;
+    d.count = r.size();
+    d.latency_ns = ns_between(q.submitted, now);
+    d.result = std::move(r);
     out.push_back(std::move(d));
+  };
+  for (size_t i = 0; i < c.slices.size(); ++i) {
+    Slice &sl = c.slices[i];
+    const uint64_t o0 = c.h_offs[i], cnt = c.h_offs[i + 1] - o0;
+    if (!sl.job) {
+      done_of(sl.q, std::vector<uint32_t>(res + o0, res + o0 + cnt));
+      continue;
+    }
+    Job &j = *sl.job;
+    j.parts.emplace_back(sl.c0, std::vector<uint32_t>(res + o0, res + o0 + cnt));
+    if (--j.outstanding == 0 && j.next == j.q.items) {
+      std::sort(j.parts.begin(), j.parts.end(),
+                [](const auto &a, const auto &b) { return a.first < b.first; });
+      uint64_t total = 0;
+      for (const auto &p : j.parts) total += p.second.size();
+      std::vector<uint32_t> r;
+      r.reserve(total);
+      for (const auto &p : j.parts) r.insert(r.end(), p.second.begin(), p.second.end());
+      done_of(j.q, std::move(r));
+      const Job *jp = &j;
+      s->jobs.remove_if([jp](const Job &x) { return &x == jp; });
+    }
   }
   std::lock_guard<std::mutex> lock(s->mu);
   for (auto &d : out) {
@@ -275,9 +339,9 @@ void retire_context(s4_server *s, Context &c, const uint32_t *res) {
     s->completed_at.push_back(now);
   }
   s->st.completed += out.size();
-  s->active -= c.queries.size();
+  s->active -= out.size();
   s->pool_in_use -= c.reserved_stage;
-  c.queries.clear();
+  c.slices.clear();
   c.reserved_stage = 0;
   c.busy = false;
   c.phase = 0;
@@ -293,11 +357,14 @@ void dispatcher(s4_server *s) {
         const auto t0 = Clock::now();
         if (c.phase == 1) {
           device_ns += ns_between(c.launched, t0);
-          if (*c.h_err) {
+          if (*c.h_err || !offsets_valid(c)) {
+            // results unusable: fail the server loudly, drop the iteration
             std::lock_guard<std::mutex> lock(s->mu);
             s->worker_error = S4_EDEVICE;
-            s->worker_msg = "single-pass scan failed (look-back guard or output overflow)";
+            s->worker_msg = *c.h_err ? "single-pass scan failed (look-back guard or output overflow)"
+                                     : "device wrote inconsistent result offsets";
             s->stop = true;
+            std::fill(c.h_offs, c.h_offs + c.slices.size() + 1, 0);
           }
           std::vector<uint32_t> spill;
           if (start_copy(s, c, &spill)) retire_context(s, c, spill.empty() ? c.h_results : spill.data());
@@ -320,37 +387,78 @@ void dispatcher(s4_server *s) {
       const auto t0 = Clock::now();
       {
         std::unique_lock<std::mutex> lock(s->mu);
-        uint64_t items = 0, terms = 0, bound = 0;
-        while (!s->waiting.empty() && c.queries.size() < s->slots_per_ctx) {
-          const Query &q = s->waiting.front();
-          const bool fits = items + q.items <= s->items_per_ctx && terms + q.k <= s->terms_per_ctx &&
-                            s->pool_in_use + 4 * s4::kBlock * (items + q.items) <= s->cfg.pool_bytes &&
-                            (c.queries.empty() || bound + q.bound <= s->results_per_ctx);
-          if (!fits) {
-            if (c.queries.empty()) ++s->st.waits_for_memory;
-            break;
-          }
-          items += q.items;
-          terms += q.k;
-          bound += q.bound;
-          c.queries.push_back(std::move(s->waiting.front()));
-          s->waiting.pop_front();
+        uint64_t items = 0, terms = 0, bound = 0, started = 0;
+        // does a slice of `n` chunks, k terms and result bound `b` fit?
+        auto fits = [&](uint64_t n, uint64_t k, uint64_t b) {
+          if (s->pool_in_use + 4 * s4::kBlock * (items + n) > s->cfg.pool_bytes) return false;
+          if (c.slices.empty()) return true;  // a single slice always fits the context
+          return c.slices.size() < s->slots_per_ctx && items + n <= s->iter_items && terms + k <= s->terms_per_ctx &&
+                 bound + b <= s->results_per_ctx;
+        };
+        auto admit = [&](Slice &&sl) {
+          const uint64_t n = sl.c1 - sl.c0;
+          items += n;
+          terms += sl.query().k;
+          bound += sl.bound();
+          c.slices.push_back(std::move(sl));
+        };
+        // 1. one slice of every query already running in slices
+        for (Job &j : s->jobs) {
+          if (j.next == j.q.items) continue;
+          Slice sl;
+          sl.job = &j;
+          sl.c0 = j.next;
+          sl.c1 = std::min(j.q.items, j.next + s->slice);
+          if (!fits(sl.c1 - sl.c0, j.q.k, sl.bound())) break;
+          j.next = sl.c1;
+          ++j.outstanding;
+          admit(std::move(sl));
         }
-        if (!c.queries.empty()) {
+        // 2. waiting queries, oldest first
+        while (!s->waiting.empty()) {
+          Query &q = s->waiting.front();
+          Slice sl;
+          sl.c1 = std::min(q.items, s->slice);
+          if (sl.c1 < q.items) {  // too long for one slice: a job
+            Job probe;
+            probe.q = q;
+            sl.job = &probe;
+            if (!fits(sl.c1, q.k, sl.bound())) {
+              if (c.slices.empty()) ++s->st.waits_for_memory;
+              break;
+            }
+            s->jobs.push_back(std::move(probe));
+            Job &j = s->jobs.back();
+            sl.job = &j;
+            j.next = sl.c1;
+            j.outstanding = 1;
+            ++s->st.sliced_queries;
+          } else {
+            sl.q = q;
+            if (!fits(sl.c1, q.k, sl.bound())) {
+              if (c.slices.empty()) ++s->st.waits_for_memory;
+              break;
+            }
+          }
+          s->waiting.pop_front();
+          ++started;
+          admit(std::move(sl));
+        }
+        if (!c.slices.empty()) {
           c.items = items;
           c.terms = terms;
           c.bound = bound;
           c.reserved_stage = 4 * s4::kBlock * items;
           s->pool_in_use += c.reserved_stage;
-          s->active += c.queries.size();
-          s->st.admitted += c.queries.size();
+          s->active += started;
+          s->st.admitted += started;
           s->st.peak_active = std::max(s->st.peak_active, s->active);
           s->st.peak_pool_bytes = std::max(s->st.peak_pool_bytes, s->pool_in_use);
-          s->st.max_batch = std::max<uint64_t>(s->st.max_batch, c.queries.size());
+          s->st.max_batch = std::max<uint64_t>(s->st.max_batch, c.slices.size());
           ++s->st.iterations;
         }
       }
-      if (!c.queries.empty()) {
+      if (!c.slices.empty()) {
         int rc = launch_context(s, c);
         if (rc) {
           std::lock_guard<std::mutex> lock(s->mu);
@@ -372,9 +480,10 @@ void dispatcher(s4_server *s) {
       s->st.device_ns = device_ns;
       s->st.host_ns = host_ns;
       for (Context &c : s->ctx) any_busy |= c.busy;
-      if (s->stop && !any_busy && (s->waiting.empty() || s->worker_error)) break;
+      const bool jobs_left = !s->jobs.empty();
+      if (s->stop && !any_busy && ((s->waiting.empty() && !jobs_left) || s->worker_error)) break;
       idle = !progressed && !launched;
-      if (idle && !any_busy && s->waiting.empty()) {
+      if (idle && !any_busy && s->waiting.empty() && !jobs_left) {
         s->cv.wait_for(lock, std::chrono::milliseconds(1));
         continue;
       }
@@ -405,8 +514,8 @@ int prepare_query(const s4_server *s, const uint32_t *terms, uint32_t k, Query *
   const uint64_t m = ix->lengths[q->terms[0]];
   q->items = (m + s4::kBlock - 1) / s4::kBlock;
   q->bound = m;
-  if (q->items > s->items_per_ctx || k > s->terms_per_ctx || 4 * s4::kBlock * q->items > s->cfg.pool_bytes)
-    return s4::fail(S4_ERANGE, "query needs more intermediate memory than one iteration holds");
+  if (k > s->terms_per_ctx || 4 * s4::kBlock * std::min(q->items, s->slice) > s->cfg.pool_bytes)
+    return s4::fail(S4_ERANGE, "one slice of the query needs more intermediate memory than the pool holds");
   return S4_OK;
 }
 
@@ -439,6 +548,9 @@ int s4_server_create(const s4_index *index, const s4_server_config *cfg, s4_serv
   const uint64_t rb = cfg->result_bytes ? cfg->result_bytes : (64ull << 20);
   s->results_per_ctx = std::max<uint64_t>(kBlock, rb / kContexts / 4);
   s->terms_per_ctx = s->slots_per_ctx * cfg->max_terms;
+  s->slice = std::max<uint64_t>(1, std::min<uint64_t>(cfg->slice_chunks ? cfg->slice_chunks : 16384,
+                                                      s->items_per_ctx));
+  s->iter_items = std::min<uint64_t>(s->items_per_ctx, 4 * s->slice);
   if (s->items_per_ctx >= 0xFFFFFFFFull / kBlock) {
     delete s;
     return fail(S4_EINVAL, "pool_bytes too large");

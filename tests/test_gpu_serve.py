@@ -131,14 +131,50 @@ def test_memory_admission(gpu, served):
         assert st["completed"] == 6
     finally:
         srv.close()
+    # a pool of 8 chunks per iteration: the long query runs 8 chunks at a
+    # time, its slices joined in order
     tiny = gpu.Server(ix, max_slots=8, pool_bytes=3 * 4096, result_bytes=1 << 20)
     try:
-        with pytest.raises(gpu.S4Error) as e:
-            tiny.submit([big, 0])
-        assert e.value.code == gpu.ERANGE
-        assert tiny.stats()["rejected"] == 1
+        qid = tiny.submit([big, 0])
+        got = drain(tiny, [qid])
+        assert np.array_equal(got[qid][0], want(flat, offs, [big, 0]))
+        st = tiny.stats()
+        assert st["sliced_queries"] == 1 and st["iterations"] >= (int(ix.lengths[0]) + 1023) // 1024
     finally:
         tiny.close()
+    # a pool smaller than one chunk can hold nothing
+    none = gpu.Server(ix, max_slots=8, pool_bytes=256, result_bytes=1 << 20)
+    try:
+        with pytest.raises(gpu.S4Error) as e:
+            none.submit([big, 0])
+        assert e.value.code == gpu.ERANGE
+        assert none.stats()["rejected"] == 1
+    finally:
+        none.close()
+
+
+@pytest.mark.parametrize("slice_chunks", [1, 7, 64])
+def test_sliced_queries_match_oracle(gpu, served, slice_chunks):
+    """Queries longer than a slice run one slice per iteration, interleaved
+    with short ones and with each other (several contexts in flight); the
+    joined results equal the oracle's, and short queries still finish."""
+    ix, flat, offs = served
+    terms, qoffs = workloads.queries(24 + slice_chunks, ix.lengths, 500, 1, 6)
+    srv = gpu.Server(ix, max_slots=384, pool_bytes=256 << 20, result_bytes=64 << 20, slice_chunks=slice_chunks)
+    try:
+        r = srv.replay(terms, qoffs, np.zeros(500, np.uint64), with_results=True, results_cap=1 << 24)
+        st = srv.stats()
+    finally:
+        srv.close()
+    for q in range(500):
+        ts = terms[int(qoffs[q]): int(qoffs[q + 1])]
+        got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
+        assert np.array_equal(got, want(flat, offs, ts)), q
+    long_q = sum(1 for q in range(500)
+                 if (min(int(ix.lengths[t]) for t in terms[int(qoffs[q]): int(qoffs[q + 1])]) + 127) // 128
+                 > slice_chunks)
+    assert st["sliced_queries"] == long_q > 0
+    assert st["completed"] == 500
 
 
 def test_replay_open_loop(gpu, served):
