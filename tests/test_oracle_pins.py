@@ -133,7 +133,7 @@ def test_b0_block_repeats_seed():
 # ------------------------------------------------------------ round trips
 
 def recipe_list(b, n=4096, seed=0):
-    """Sec. 7.1 recipe: 4096 integers whose D4 gaps are below 2^b, built
+    """Sec. 7.4 recipe: 4096 integers whose D4 gaps are below 2^b, built
     as a sorted list (each consecutive gap below 2^b / 4)."""
     rng = np.random.default_rng(seed + b)
     g = max(1, (1 << b) // 4) if b >= 2 else 1
