@@ -61,12 +61,16 @@ def _bind(path):
     lib.orc_stream_bytes.argtypes = [ctypes.c_uint64, u8p]
     lib.orc_stream_bytes.restype = sz
     lib.orc_intersect.argtypes = [u32p, ctypes.c_uint64, u32p, ctypes.c_uint64, u32p, u64p]
+    lib.orc_encode_fp.argtypes = [u32p, ctypes.c_uint64, ctypes.c_uint32, u8p, sz, ctypes.POINTER(sz)]
+    lib.orc_fp_choose.argtypes = [u32p, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                  ctypes.POINTER(ctypes.c_uint32)]
+    lib.orc_fp_choose.restype = None
     lib.orc_hyb_is_bitmap.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
     lib.orc_hyb_intersect_k.argtypes = [ctypes.POINTER(u32p), u64p, ctypes.c_uint32, ctypes.c_uint64,
                                         ctypes.c_uint32, u32p, ctypes.c_uint64, u64p]
     lib.orc_intersect_k.argtypes = [ctypes.POINTER(u32p), u64p, ctypes.c_uint32, u32p,
                                     ctypes.c_uint64, u64p]
-    for f in (lib.orc_encode, lib.orc_encode_mode, lib.orc_decode, lib.orc_decode_alg1, lib.orc_decoded_length,
+    for f in (lib.orc_encode, lib.orc_encode_mode, lib.orc_encode_fp, lib.orc_decode, lib.orc_decode_alg1, lib.orc_decoded_length,
               lib.orc_widths, lib.orc_intersect, lib.orc_intersect_k):
         f.restype = ctypes.c_int
     return lib
@@ -120,20 +124,35 @@ def _u8(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
 
 
-def encode(x, mode: int = D4) -> np.ndarray:
+def encode(x, mode: int = D4, patched: bool = False) -> np.ndarray:
     """Serialized S4-BP128 stream of a non-decreasing uint32 list with the
-    given differential form (D4 by default)."""
+    given differential form (D4 by default); patched=True gives the
+    S4-FastPFOR stream (Sec. 4.4)."""
     lib = _active()
     x, xp = _u32(x)
     n = x.size
-    bound = HEADER_BYTES + ((n // 128 + 3) & ~3) + 512 * (n // 128) + 4 * (n % 128) + 16
+    nb = n // 128
+    bound = HEADER_BYTES + ((nb + 3) & ~3) + 514 * nb + 4 * (n % 128) + 16
+    if patched:  # per page: 2 headers, padding of up to 32 arrays
+        bound += ((nb + 511) // 512) * (16 + 4 * 33 + 32 * 32 * 4)
     out = np.zeros(bound, dtype=np.uint8)
     nbytes = ctypes.c_size_t(0)
-    rc = lib.orc_encode_mode(xp, n, mode, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), bound,
-                             ctypes.byref(nbytes))
+    fn = lib.orc_encode_fp if patched else lib.orc_encode_mode
+    rc = fn(xp, n, mode, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), bound, ctypes.byref(nbytes))
     if rc:
         raise OracleError(rc, "encode")
     return out[: nbytes.value].copy()
+
+
+def fp_choose(block):
+    """FastPFOR's (b, b', exceptions) for one block of 128 deltas."""
+    lib = _active()
+    blk, bp = _u32(block)
+    if blk.size != 128:
+        raise ValueError("a block has 128 deltas")
+    b, p, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    lib.orc_fp_choose(bp, ctypes.byref(b), ctypes.byref(p), ctypes.byref(c))
+    return b.value, p.value, c.value
 
 
 def decode(enc) -> np.ndarray:

@@ -49,6 +49,15 @@
  *   32 u8 widths[nb], then zero bytes up to a multiple of 4
  *      u32 payload[pw]
  *      u32 tail[t]
+ *   With flag bit 3 (S4-FastPFOR, Sec. 4.4) the widths are the packed
+ *   widths b' and the payload holds each delta's low b' bits; after the tail
+ *   come the pages of up to 512 blocks, each:
+ *      u32 meta_len, then per block: u8 b, u8 c, c u8 positions (increasing),
+ *      zero bytes up to a multiple of 4;
+ *      u32 present (bit d-1 set when the page has exceptions with b - b' = d),
+ *      then for each such d ascending: u32 count, and the counted high parts
+ *      (delta >> b') packed LSB-first at d bits each, value e at bit e d,
+ *      padded to a multiple of 32 values (d words per 32).
  *
  * Parity status of each function is recorded in the tests that pin it.
  */
@@ -66,6 +75,8 @@
 
 #define ORC_MAGIC 0x34443453u
 #define ORC_HEADER 32u
+#define ORC_PATCHED 8u  /* flag bit 3: S4-FastPFOR */
+#define ORC_PAGE 512u   /* blocks whose exceptions are pooled (Sec. 4.4) */
 
 static void put32(uint8_t *p, uint32_t v) {
   p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8);
@@ -116,6 +127,25 @@ size_t orc_stream_bytes(uint64_t n, const uint8_t *widths) {
   uint64_t nb = n / 128u, t = n % 128u, pw = 0;
   for (uint64_t k = 0; k < nb; ++k) pw += 4u * widths[k];
   return ORC_HEADER + pad4((size_t)nb) + 4u * (size_t)pw + 4u * (size_t)t;
+}
+
+/* Pack 128 values of b bits into 4 b words at byte pointer payload: lane j
+ * takes values 4q + j, q = 0..31, LSB first; its completed word m goes to
+ * payload word 4m + j (Sec. 4.2, Fig. 2).  Bits above b are dropped. */
+static void orc_pack_block(const uint32_t *d, uint32_t b, uint8_t *payload) {
+  const uint64_t keep = (b == 32u) ? 0xFFFFFFFFull : (((uint64_t)1 << b) - 1u);
+  for (uint32_t j = 0; j < 4; ++j) {
+    uint64_t acc = 0;
+    uint32_t have = 0, m = 0;
+    for (uint32_t q = 0; q < 32; ++q) {
+      acc |= ((uint64_t)d[4u * q + j] & keep) << have;
+      have += b;
+      while (have >= 32) {
+        put32(payload + 4u * (4u * m + j), (uint32_t)acc);
+        acc >>= 32; have -= 32; ++m;
+      }
+    }
+  }
 }
 
 /* Encode a non-decreasing list: D4 deltas (Sec. 5), per-block width
@@ -184,19 +214,186 @@ int orc_encode(const uint32_t *x, uint64_t n, uint8_t *out, size_t cap, size_t *
   return orc_encode_mode(x, n, ORC_D4, out, cap, out_bytes);
 }
 
+/* FastPFOR's choice for one block of 128 deltas (Sec. 4.4): b is the
+ * block's width (Sec. 4.3); the packed width b' in [0, b] minimises
+ * 128 b' + c(b') (b - b' + 8), c(b') the number of deltas >= 2^b' (the
+ * exceptions).  Reading: ties go to the larger b'.  Each candidate's count
+ * is taken directly from the deltas. */
+void orc_fp_choose(const uint32_t *d, uint32_t *b_out, uint32_t *bp_out, uint32_t *c_out) {
+  const uint32_t b = orc_width(d, 128u);
+  uint64_t best = 0;
+  uint32_t best_bp = b, best_c = 0;
+  for (uint32_t k = 0; k <= b; ++k) {
+    const uint32_t bp = b - k; /* b, b - 1, ..., 0 */
+    uint32_t c = 0;
+    for (uint32_t i = 0; i < 128u; ++i)
+      if ((uint64_t)d[i] >= ((uint64_t)1 << bp)) ++c;
+    const uint64_t cost = 128u * (uint64_t)bp + (uint64_t)c * (b - bp + 8u);
+    if (k == 0 || cost < best) { best = cost; best_bp = bp; best_c = c; }
+  }
+  *b_out = b;
+  *bp_out = best_bp;
+  *c_out = best_c;
+}
+
+/* Encode a non-decreasing list as S4-FastPFOR (Sec. 4.4) with the given
+ * differential form (Sec. 5): per block, b' by orc_fp_choose; the low b'
+ * bits of every delta packed as in S4-BP128 at width b'; the exceptions'
+ * positions and high parts pooled per page of 512 blocks, one array per
+ * value of b - b' (layout in the header comment). */
+int orc_encode_fp(const uint32_t *x, uint64_t n, uint32_t mode, uint8_t *out, size_t cap, size_t *out_bytes) {
+  if ((!x && n) || !out_bytes || mode > 3u) return ORC_EINVAL;
+  int strictly = 1;
+  for (uint64_t i = 1; i < n; ++i) {
+    if (x[i] < x[i - 1]) return ORC_EUNSORTED;
+    if (x[i] == x[i - 1]) strictly = 0;
+  }
+  const uint64_t nb = n / 128u, t = n % 128u, packed = nb * 128u;
+  if (nb > 0xFFFFFFFFull) return ORC_EINVAL;
+  uint32_t *d = (uint32_t *)malloc((packed ? packed : 1) * sizeof(uint32_t));
+  uint8_t *bb = (uint8_t *)malloc(nb ? nb : 1), *bp = (uint8_t *)malloc(nb ? nb : 1);
+  uint8_t *cc = (uint8_t *)malloc(nb ? nb : 1);
+  if (!d || !bb || !bp || !cc) { free(d); free(bb); free(bp); free(cc); return ORC_ENOMEM; }
+  for (uint64_t i = 0; i < packed; ++i) d[i] = x[i] - orc_reference(x, i, mode);
+  uint64_t pw = 0;
+  for (uint64_t k = 0; k < nb; ++k) {
+    uint32_t b, p, c;
+    orc_fp_choose(d + 128u * k, &b, &p, &c);
+    bb[k] = (uint8_t)b; bp[k] = (uint8_t)p; cc[k] = (uint8_t)c;
+    pw += 4u * p;
+  }
+  /* size of the pages */
+  size_t pages = 0;
+  for (uint64_t k0 = 0; k0 < nb; k0 += ORC_PAGE) {
+    const uint64_t k1 = (k0 + ORC_PAGE < nb) ? k0 + ORC_PAGE : nb;
+    uint64_t meta = 0, cnt[33] = {0};
+    for (uint64_t k = k0; k < k1; ++k) { meta += 2u + cc[k]; cnt[bb[k] - bp[k]] += cc[k]; }
+    pages += 4u + pad4((size_t)meta) + 4u;
+    for (uint32_t e = 1; e <= 32u; ++e)
+      if (cnt[e]) pages += 4u + 4u * (size_t)e * ((cnt[e] + 31u) / 32u);
+  }
+  const size_t base = ORC_HEADER + pad4((size_t)nb) + 4u * (size_t)pw + 4u * (size_t)t;
+  *out_bytes = base + pages;
+  if (cap < base + pages) { free(d); free(bb); free(bp); free(cc); return ORC_ERANGE; }
+  memset(out, 0, base + pages);
+  put32(out, ORC_MAGIC);
+  put16(out + 4, 1);
+  put16(out + 6, (uint16_t)((strictly ? 1u : 0u) | (mode << 1) | ORC_PATCHED));
+  put64(out + 8, n);
+  put32(out + 16, (uint32_t)nb);
+  put32(out + 20, (uint32_t)t);
+  put64(out + 24, pw);
+  memcpy(out + ORC_HEADER, bp, (size_t)nb);
+  uint8_t *payload = out + ORC_HEADER + pad4((size_t)nb);
+  uint64_t word_base = 0;
+  for (uint64_t k = 0; k < nb; ++k) {
+    orc_pack_block(d + 128u * k, bp[k], payload + 4u * word_base);
+    word_base += 4u * bp[k];
+  }
+  uint8_t *tail = payload + 4u * pw;
+  for (uint64_t i = 0; i < t; ++i) put32(tail + 4u * i, x[packed + i]);
+  uint8_t *q = out + base;
+  for (uint64_t k0 = 0; k0 < nb; k0 += ORC_PAGE) {
+    const uint64_t k1 = (k0 + ORC_PAGE < nb) ? k0 + ORC_PAGE : nb;
+    uint8_t *m = q + 4;
+    uint32_t o = 0, present = 0;
+    for (uint64_t k = k0; k < k1; ++k) {
+      m[o++] = bb[k];
+      m[o++] = cc[k];
+      for (uint32_t i = 0; i < 128u; ++i)
+        if ((uint64_t)d[128u * k + i] >= ((uint64_t)1 << bp[k])) m[o++] = (uint8_t)i;
+      if (cc[k]) present |= 1u << (bb[k] - bp[k] - 1u);
+    }
+    put32(q, o);
+    q = m + pad4(o);
+    put32(q, present);
+    q += 4;
+    for (uint32_t e = 1; e <= 32u; ++e) {
+      if (!((present >> (e - 1u)) & 1u)) continue;
+      uint8_t *cnt_at = q;
+      uint8_t *words = q + 4;
+      uint64_t idx = 0;
+      for (uint64_t k = k0; k < k1; ++k) {
+        if (!cc[k] || (uint32_t)(bb[k] - bp[k]) != e) continue;
+        for (uint32_t i = 0; i < 128u; ++i) {
+          const uint32_t v = d[128u * k + i];
+          if ((uint64_t)v < ((uint64_t)1 << bp[k])) continue;
+          const uint64_t high = (uint64_t)v >> bp[k];
+          const uint64_t bit = idx++ * e;
+          const uint64_t w = bit / 32u, s = bit % 32u;
+          uint64_t cur = get32(words + 4u * w);
+          if (s + e > 32u) cur |= (uint64_t)get32(words + 4u * (w + 1u)) << 32;
+          cur |= high << s;
+          put32(words + 4u * w, (uint32_t)cur);
+          if (s + e > 32u) put32(words + 4u * (w + 1u), (uint32_t)(cur >> 32));
+        }
+      }
+      put32(cnt_at, (uint32_t)idx);
+      q = words + 4u * (size_t)e * ((idx + 31u) / 32u);
+    }
+  }
+  free(d); free(bb); free(bp); free(cc);
+  return ORC_OK;
+}
+
 typedef struct {
   uint64_t n, nb, t, pw;
   uint16_t flags;
   const uint8_t *widths;
   const uint8_t *payload; /* byte pointer, read with get32 */
   const uint8_t *tail;
+  const uint8_t *pages;   /* patched streams: first page */
 } orc_view;
+
+/* Check the pages of a patched stream from p to end: every field in range,
+ * c > 0 exactly when b' < b, positions increasing below 128, each array's
+ * count equal to the exceptions that use it, nothing left over. */
+static int orc_check_pages(const orc_view *v, const uint8_t *p, const uint8_t *end) {
+  for (uint64_t k0 = 0; k0 < v->nb; k0 += ORC_PAGE) {
+    const uint64_t k1 = (k0 + ORC_PAGE < v->nb) ? k0 + ORC_PAGE : v->nb;
+    uint64_t cnt[33] = {0};
+    if ((size_t)(end - p) < 4u) return ORC_ECORRUPT;
+    const uint32_t meta_len = get32(p);
+    const uint8_t *m = p + 4;
+    if ((size_t)(end - m) < pad4(meta_len) + 4u) return ORC_ECORRUPT;
+    uint32_t o = 0;
+    for (uint64_t k = k0; k < k1; ++k) {
+      if (o + 2u > meta_len) return ORC_ECORRUPT;
+      const uint32_t b = m[o], c = m[o + 1], bp = v->widths[k];
+      o += 2;
+      if (b > 32u || bp > b || c > 128u || (c > 0) != (bp < b) || o + c > meta_len) return ORC_ECORRUPT;
+      for (uint32_t e = 0; e < c; ++e)
+        if (m[o + e] >= 128u || (e && m[o + e] <= m[o + e - 1])) return ORC_ECORRUPT;
+      o += c;
+      cnt[b - bp] += c;
+    }
+    if (o != meta_len) return ORC_ECORRUPT;
+    for (uint32_t z = meta_len; z < pad4(meta_len); ++z)
+      if (m[z]) return ORC_ECORRUPT;
+    const uint8_t *q = m + pad4(meta_len);
+    const uint32_t present = get32(q);
+    q += 4;
+    for (uint32_t d = 1; d <= 32u; ++d) {
+      if (!((present >> (d - 1u)) & 1u)) {
+        if (cnt[d]) return ORC_ECORRUPT;
+        continue;
+      }
+      if ((size_t)(end - q) < 4u) return ORC_ECORRUPT;
+      const uint32_t count = get32(q);
+      const size_t words = (size_t)d * ((count + 31u) / 32u);
+      if (count == 0 || count != cnt[d] || (size_t)(end - q) < 4u + 4u * words) return ORC_ECORRUPT;
+      q += 4u + 4u * words;
+    }
+    p = q;
+  }
+  return p == end ? ORC_OK : ORC_ECORRUPT;
+}
 
 static int orc_parse(const uint8_t *enc, size_t bytes, orc_view *v) {
   if (!enc || bytes < ORC_HEADER) return ORC_ECORRUPT;
   if (get32(enc) != ORC_MAGIC || get16(enc + 4) != 1) return ORC_ECORRUPT;
   v->flags = get16(enc + 6);
-  if (v->flags & ~7u) return ORC_ECORRUPT;
+  if (v->flags & ~15u) return ORC_ECORRUPT;
   v->n = get64(enc + 8);
   v->nb = get32(enc + 16);
   v->t = get32(enc + 20);
@@ -213,10 +410,13 @@ static int orc_parse(const uint8_t *enc, size_t bytes, orc_view *v) {
   for (uint64_t k = v->nb; k < wbytes; ++k)
     if (enc[ORC_HEADER + k] != 0) return ORC_ECORRUPT;
   if (pw != v->pw) return ORC_ECORRUPT;
-  if (bytes != ORC_HEADER + wbytes + 4u * pw + 4u * v->t) return ORC_ECORRUPT;
+  const size_t base = ORC_HEADER + wbytes + 4u * pw + 4u * v->t;
   v->payload = enc + ORC_HEADER + wbytes;
   v->tail = v->payload + 4u * pw;
-  return ORC_OK;
+  v->pages = enc + base;
+  if (!(v->flags & ORC_PATCHED)) return bytes == base ? ORC_OK : ORC_ECORRUPT;
+  if (bytes < base) return ORC_ECORRUPT;
+  return orc_check_pages(v, enc + base, enc + bytes);
 }
 
 int orc_decoded_length(const uint8_t *enc, size_t bytes, uint64_t *n) {
@@ -252,6 +452,46 @@ static uint32_t orc_extract(const uint8_t *w, uint32_t b, uint32_t p) {
   return (uint32_t)((window >> s) & mask);
 }
 
+/* Patching (Sec. 4.4), by random access: for each page, locate array d of
+ * every present d; block k's e-th exception, the j-th of its page to use
+ * array d = b - b', has high part bits [j d, j d + d) of that array, added
+ * above the b' low bits already unpacked at its position. */
+static void orc_patch_random(const orc_view *v, uint32_t *out) {
+  const uint8_t *p = v->pages;
+  for (uint64_t k0 = 0; k0 < v->nb; k0 += ORC_PAGE) {
+    const uint64_t k1 = (k0 + ORC_PAGE < v->nb) ? k0 + ORC_PAGE : v->nb;
+    const uint32_t meta_len = get32(p);
+    const uint8_t *m = p + 4;
+    const uint8_t *q = m + pad4(meta_len);
+    const uint32_t present = get32(q);
+    q += 4;
+    const uint8_t *arr[33] = {0};
+    for (uint32_t d = 1; d <= 32u; ++d) {
+      if (!((present >> (d - 1u)) & 1u)) continue;
+      const uint32_t count = get32(q);
+      arr[d] = q + 4;
+      q += 4u + 4u * (size_t)d * ((count + 31u) / 32u);
+    }
+    uint64_t used[33] = {0};
+    uint32_t o = 0;
+    for (uint64_t k = k0; k < k1; ++k) {
+      const uint32_t b = m[o], c = m[o + 1], bp = v->widths[k], d = b - bp;
+      o += 2;
+      for (uint32_t e = 0; e < c; ++e) {
+        const uint64_t bit = used[d]++ * d;
+        const uint64_t w = bit / 32u, s = bit % 32u;
+        uint64_t window = get32(arr[d] + 4u * w);
+        if (s + d > 32u) window |= (uint64_t)get32(arr[d] + 4u * (w + 1u)) << 32;
+        const uint64_t mask = (d == 32u) ? 0xFFFFFFFFull : (((uint64_t)1 << d) - 1u);
+        const uint32_t high = (uint32_t)((window >> s) & mask);
+        out[128u * k + m[o + e]] += (uint32_t)((uint64_t)high << bp);
+      }
+      o += c;
+    }
+    p = q;
+  }
+}
+
 /* Decode: unpack every delta by random access, then invert the stream's
  * differential form over the whole list in index order, x_i = delta_i +
  * (the value the form subtracted) (Sec. 5), then copy the raw tail. */
@@ -268,6 +508,7 @@ int orc_decode(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, ui
       out[128u * k + p] = orc_extract(v.payload + 4u * word_base, b, p);
     word_base += 4u * b;
   }
+  if (v.flags & ORC_PATCHED) orc_patch_random(&v, out);
   const uint32_t mode = (v.flags >> 1) & 3u;
   for (uint64_t i = 0; i < 128u * v.nb; ++i) out[i] += orc_reference(out, i, mode);
   for (uint64_t i = 0; i < v.t; ++i) out[128u * v.nb + i] = get32(v.tail + 4u * i);
@@ -291,6 +532,8 @@ static void orc_prefix(uint32_t mode, uint32_t t[4], const uint32_t v[4]) {
       u[0] = t[0]; u[1] = t[1]; u[2] = t[2] + t[0]; u[3] = t[3] + t[1];
       t[0] = u[0]; t[1] = u[1] + u[0]; t[2] = u[2] + u[1]; t[3] = u[3] + u[2];
       for (int c = 0; c < 4; ++c) t[c] += v[3];
+      break;
+    case 4u: /* no differential coding: P(t, v) = t */
       break;
     default: /* D4: t + v */
       for (int c = 0; c < 4; ++c) t[c] += v[c];
@@ -341,12 +584,79 @@ static void orc_alg1_block(const uint8_t *y, uint32_t b, uint32_t mode, uint32_t
   }
 }
 
+/* Sequential reader of one exception array: LSB-first, d bits at a time. */
+typedef struct { const uint8_t *w; uint64_t acc; uint32_t have; } orc_bits;
+static uint32_t orc_bits_take(orc_bits *r, uint32_t d) {
+  while (r->have < d) {
+    r->acc |= (uint64_t)get32(r->w) << r->have;
+    r->w += 4;
+    r->have += 32;
+  }
+  const uint32_t v = (uint32_t)(r->acc & ((d == 32u) ? 0xFFFFFFFFull : (((uint64_t)1 << d) - 1u)));
+  r->acc = (d == 64u) ? 0 : (r->acc >> d);
+  r->have -= d;
+  return v;
+}
+
+/* S4-FastPFOR in the paper's three passes (Sec. 5: unpack, patch, prefix
+ * could not be fused): every block of a page is unpacked in the order of
+ * Alg. 1 with no prefix; the page's exceptions are then applied in stream
+ * order, each array read sequentially; last the form's P(t, v) runs over
+ * the page's 4-vectors, v carried from block to block. */
+static void orc_three_pass(const orc_view *v, uint32_t *out) {
+  const uint32_t mode = (v->flags >> 1) & 3u;
+  uint32_t seed[4] = {0, 0, 0, 0}, dummy[4];
+  const uint8_t *p = v->pages;
+  uint64_t word_base = 0;
+  for (uint64_t k0 = 0; k0 < v->nb; k0 += ORC_PAGE) {
+    const uint64_t k1 = (k0 + ORC_PAGE < v->nb) ? k0 + ORC_PAGE : v->nb;
+    for (uint64_t k = k0; k < k1; ++k) {
+      orc_alg1_block(v->payload + 4u * word_base, v->widths[k], 4u, dummy, out + 128u * k);
+      word_base += 4u * v->widths[k];
+    }
+    const uint32_t meta_len = get32(p);
+    const uint8_t *m = p + 4, *q = p + 4 + pad4(meta_len);
+    const uint32_t present = get32(q);
+    q += 4;
+    orc_bits rd[33];
+    memset(rd, 0, sizeof rd);
+    for (uint32_t d = 1; d <= 32u; ++d) {
+      if (!((present >> (d - 1u)) & 1u)) continue;
+      const uint32_t count = get32(q);
+      rd[d].w = q + 4;
+      q += 4u + 4u * (size_t)d * ((count + 31u) / 32u);
+    }
+    const uint8_t *mp = m;
+    for (uint64_t k = k0; k < k1; ++k) {
+      const uint32_t b = mp[0], c = mp[1], bp = v->widths[k];
+      for (uint32_t e = 0; e < c; ++e) {
+        const uint32_t high = orc_bits_take(&rd[b - bp], b - bp);
+        out[128u * k + mp[2 + e]] |= (uint32_t)((uint64_t)high << bp);
+      }
+      mp += 2u + c;
+    }
+    for (uint64_t k = k0; k < k1; ++k)
+      for (uint32_t r = 0; r < 32u; ++r) {
+        uint32_t t[4];
+        for (uint32_t c = 0; c < 4u; ++c) t[c] = out[128u * k + 4u * r + c];
+        orc_prefix(mode, t, seed);
+        for (uint32_t c = 0; c < 4u; ++c) { seed[c] = t[c]; out[128u * k + 4u * r + c] = t[c]; }
+      }
+    p = q;
+  }
+}
+
 int orc_decode_alg1(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, uint64_t *n_out) {
   orc_view v;
   int rc = orc_parse(enc, bytes, &v);
   if (rc) return rc;
   if (n_out) *n_out = v.n;
   if (cap < v.n) return ORC_ERANGE;
+  if (v.flags & ORC_PATCHED) {
+    orc_three_pass(&v, out);
+    for (uint64_t i = 0; i < v.t; ++i) out[128u * v.nb + i] = get32(v.tail + 4u * i);
+    return ORC_OK;
+  }
   uint32_t seed[4] = {0, 0, 0, 0};
   uint64_t word_base = 0;
   for (uint64_t k = 0; k < v.nb; ++k) {

@@ -33,10 +33,19 @@ MUTANTS = {
     "alg1_straddle_shift": ("<< (32u - i)) & M;", "<< (31u - i)) & M;"),
     "alg1_dropped_prefix": ("default: /* D4: t + v */\n      for (int c = 0; c < 4; ++c) t[c] += v[c];",
                             "default: /* D4: t + v */\n      for (int c = 0; c < 4; ++c) t[c] += 0;"),
-    "b32_mask": ("(b == 32u) ? 0xFFFFFFFFull", "(b == 32u) ? 0x7FFFFFFFull"),
+    "b32_mask": ("uint64_t mask = (b == 32u) ? 0xFFFFFFFFull", "uint64_t mask = (b == 32u) ? 0x7FFFFFFFull"),
     "tail_offset": ("out[128u * v.nb + i] = get32(v.tail + 4u * i);\n  return ORC_OK;\n}\n\n/* The vector",
                     "out[128u * v.nb + i] = get32(v.tail);\n  return ORC_OK;\n}\n\n/* The vector"),
-    "extract_shift": ("(uint32_t)((window >> s) & mask)", "(uint32_t)((window >> (s + 1)) & mask)"),
+    "extract_shift": ("return (uint32_t)((window >> s) & mask);", "return (uint32_t)((window >> (s + 1)) & mask);"),
+    "fp_tie_smaller": ("if (k == 0 || cost < best) { best = cost;", "if (k == 0 || cost <= best) { best = cost;"),
+    "fp_cost_seven": ("(uint64_t)c * (b - bp + 8u);", "(uint64_t)c * (b - bp + 7u);"),
+    "fp_exception_strict": ("if ((uint64_t)d[i] >= ((uint64_t)1 << bp)) ++c;", "if ((uint64_t)d[i] > ((uint64_t)1 << bp)) ++c;"),
+    "fp_patch_shift": ("out[128u * k + m[o + e]] += (uint32_t)((uint64_t)high << bp);",
+                       "out[128u * k + m[o + e]] += (uint32_t)((uint64_t)high << (bp + 1u));"),
+    "fp_page_256": ("#define ORC_PAGE 512u", "#define ORC_PAGE 256u"),
+    "fp_reader_drift": ("  r->have -= d;\n", "  r->have -= d - (d > 1u);\n"),
+    "fp_array_pad": ("if (cnt[e]) pages += 4u + 4u * (size_t)e * ((cnt[e] + 31u) / 32u);",
+                     "if (cnt[e]) pages += 4u + 4u * (size_t)e * ((cnt[e] + 127u) / 128u) * 4u;"),
     "hyb_rule_strict": ("return n >= (universe + B - 1u) / B;", "return n > (universe + B - 1u) / B;"),
     "hyb_rule_floor": ("return n >= (universe + B - 1u) / B;", "return n >= universe / B;"),
     "hyb_probe_msb_first": ("((bits[j][x / 32u] >> (x % 32u)) & 1u)", "((bits[j][x / 32u] >> (31u - x % 32u)) & 1u)"),
@@ -78,6 +87,14 @@ def battery():
     for name in pins.MODES:
         checks.append((f"modes_alg1_{name}", lambda n=name: pins.test_modes_random_access_matches_alg1_walk(n, 17)))
         checks.append((f"modes_rt_{name}", lambda n=name: pins.test_modes_round_trip(n, 2049)))
+    checks.append(("fig3_choice", pins.test_fig3_fastpfor_choice))
+    checks.append(("fig3_bytes", pins.test_fig3_fastpfor_stream_bytes))
+    checks.append(("fp_tie", pins.test_fastpfor_tie_goes_to_larger_width))
+    for i, (blk, want) in enumerate([([5] * 128, (3, 3, 0)), ([0] * 127 + [1 << 31], (32, 0, 1)),
+                                     ([7] * 120 + [1 << 20] * 8, (21, 3, 8))]):
+        checks.append((f"fp_hand_{i}", lambda blk=blk, want=want: pins.test_fastpfor_choice_by_hand(blk, want)))
+    for mode in (pins.oracle.D4, pins.oracle.D1):
+        checks.append((f"fp_pages_{mode}", lambda m=mode: pins.test_fastpfor_stream_size_and_pages(m, 128 * 700)))
     rule_cases = [(128, 1024, 8, True), (127, 1024, 8, False), (32, 1000, 32, True), (31, 1000, 32, False),
                   (5, 41, 8, False)]
     checks.append(("hyb_rule", lambda: [pins.test_hyb_bitmap_rule(*c) for c in rule_cases]))

@@ -515,3 +515,154 @@ def test_hyb_all_bitmaps_and_mixed_by_hand():
     assert oracle.hyb_intersect_k([m2], 100, 4).tolist() == m2.tolist()
     with pytest.raises(oracle.OracleError):  # a bitmap list reaching the universe
         oracle.hyb_intersect_k([np.arange(0, 101, 2, dtype=np.uint32)], 100, 4)
+
+
+# -------------------------------------------------- S4-FastPFOR (Sec. 4.4)
+
+def _fig3_block():
+    rows = {r[0]: [int(v) for v in r[1:]] for r in read_golden("fig3_fastpfor.txt")}
+    first, filler = rows["first"], rows["filler"]
+    blk = first + [filler[i % 9] for i in range(len(first), 128)]
+    return np.array(blk, dtype=np.uint32), rows
+
+
+def test_fig3_fastpfor_choice():
+    """Fig. 3's block: b = 28 (the printed 27 corrected by the width rule),
+    b' = 2, one exception."""
+    blk, rows = _fig3_block()
+    assert oracle.fp_choose(blk) == (rows["b"][0], rows["bprime"][0], rows["exceptions"][0])
+
+
+def test_fig3_fastpfor_stream_bytes():
+    """The same block as the first block of a D1 stream (x = running sums of
+    the block, so the D1 deltas are the block): the stored width is b', the
+    packed low bits are those of the figure, the page metadata records b, one
+    exception at position 3, and the array for 26 holds 134217729 >> 2."""
+    blk, rows = _fig3_block()
+    x = np.cumsum(blk.astype(np.uint64)).astype(np.uint32)
+    enc = oracle.encode(x, oracle.D1, patched=True)
+    # zero deltas repeat values: not strictly increasing (bit 0 clear)
+    assert int.from_bytes(enc[6:8].tobytes(), "little") == (oracle.D1 << 1) | 8
+    assert enc[32] == rows["bprime"][0]
+    pw = int.from_bytes(enc[24:32].tobytes(), "little")
+    assert pw == 4 * rows["bprime"][0]
+    words = np.frombuffer(enc[36: 36 + 4 * pw].tobytes(), dtype="<u4")
+    b = rows["bprime"][0]
+    low = []
+    for i in range(9):  # Fig. 2 layout: lane i % 4, position i // 4, LSB first
+        lane, q = i % 4, i // 4
+        bit = q * b
+        low.append(int(words[4 * (bit // 32) + lane] >> (bit % 32)) & ((1 << b) - 1))
+    assert low == rows["low"]
+    p = 36 + 4 * pw  # no tail: 128 values
+    meta_len = int.from_bytes(enc[p: p + 4].tobytes(), "little")
+    meta = enc[p + 4: p + 4 + meta_len].tolist()
+    assert meta == [rows["b"][0], 1, rows["position"][0]]
+    q = p + 4 + ((meta_len + 3) & ~3)
+    present = int.from_bytes(enc[q: q + 4].tobytes(), "little")
+    assert present == 1 << (rows["array"][0] - 1)
+    count = int.from_bytes(enc[q + 4: q + 8].tobytes(), "little")
+    first_word = int.from_bytes(enc[q + 8: q + 12].tobytes(), "little")
+    assert count == 1 and first_word == rows["high"][0]
+    assert enc.size == q + 8 + 4 * rows["array"][0]  # 26 words: one padded group of 32 values
+    assert np.array_equal(oracle.decode(enc), x) and np.array_equal(oracle.decode_alg1(enc), x)
+
+
+@pytest.mark.parametrize("blk, want", [
+    ([5] * 128, (3, 3, 0)),                       # no outlier: b' = b
+    ([0] * 128, (0, 0, 0)),
+    ([0] * 127 + [1 << 31], (32, 0, 1)),          # one 32-bit outlier among zeros: b' = 0, 40 bits
+    ([7] * 120 + [1 << 20] * 8, (21, 3, 8)),      # 8 exceptions of 18 + 8 bits beat 18 bits a value
+])
+def test_fastpfor_choice_by_hand(blk, want):
+    assert oracle.fp_choose(np.array(blk, dtype=np.uint32)) == want
+
+
+def test_fastpfor_tie_goes_to_larger_width():
+    """b = 11 with 8 values in [2^10, 2^11), 12 in [2^9, 2^10) and 108 in
+    [2^8, 2^9): b' = 10 costs 1280 + 8 * 9 and b' = 9 costs 1152 + 20 * 10,
+    both 1352, every other b' more; the reading breaks the tie toward 10."""
+    blk = np.array([1500] * 8 + [700] * 12 + [300] * 108, dtype=np.uint32)
+    assert oracle.fp_choose(blk) == (11, 10, 8)
+
+
+def _deltas(x, mode):
+    x = x.astype(np.int64)
+    ref = np.zeros_like(x)
+    if mode == oracle.D1:
+        ref[1:] = x[:-1]
+    elif mode == oracle.D2:
+        ref[2:] = x[:-2]
+    elif mode == oracle.D4:
+        ref[4:] = x[:-4]
+    else:
+        q = np.arange(x.size) // 4
+        ref[q >= 1] = x[4 * q[q >= 1] - 1]
+    return (x - ref).astype(np.uint32)
+
+
+@pytest.mark.parametrize("mode", [oracle.D4, oracle.DM, oracle.D2, oracle.D1])
+@pytest.mark.parametrize("n", [128 * 512 * 2 + 300, 128 * 700])
+def test_fastpfor_stream_size_and_pages(mode, n):
+    """Round trip through both decoders over several pages (512 blocks
+    each); the stream is exactly header + b' widths + 16 b' per block + raw
+    tail + per page (meta length, 2 bytes + positions per block padded to 4,
+    presence mask, per present d a count and d words per 32 values); every
+    block's chosen cost stays within plain packing's 128 b."""
+    rng = np.random.default_rng(n + mode)
+    gaps = rng.geometric(0.25, size=n).astype(np.uint64)
+    k = n // 97
+    gaps[rng.integers(0, n, size=k)] += rng.integers(1, 1 << 20, size=k).astype(np.uint64)
+    x = np.cumsum(gaps)
+    assert x[-1] < 1 << 32
+    x = x.astype(np.uint32)
+    enc = oracle.encode(x, mode, patched=True)
+    assert np.array_equal(oracle.decode(enc), x)
+    assert np.array_equal(oracle.decode_alg1(enc), x)
+    nb, t = n // 128, n % 128
+    d = _deltas(x, mode)
+    choice = [oracle.fp_choose(d[128 * kb: 128 * kb + 128]) for kb in range(nb)]
+    size = 32 + ((nb + 3) & ~3) + sum(16 * bp for _, bp, _ in choice) + 4 * t
+    for k0 in range(0, nb, 512):
+        page = choice[k0: k0 + 512]
+        meta = sum(2 + c for _, _, c in page)
+        size += 4 + ((meta + 3) & ~3) + 4
+        cnt = {}
+        for b, bp, c in page:
+            if c:
+                cnt[b - bp] = cnt.get(b - bp, 0) + c
+        size += sum(4 + 4 * dd * ((cc + 31) // 32) for dd, cc in cnt.items())
+    assert enc.size == size
+    for b, bp, c in choice:
+        assert 128 * bp + c * (b - bp + 8) <= 128 * b
+        assert (c > 0) == (bp < b)
+
+
+def test_fastpfor_compresses_at_least_as_well_on_clustered_data():
+    """Table 5's direction: on clustered lists S4-FastPFOR never needs more
+    bits per integer than S4-BP128 in the same form (D1: 4.4 vs 5.0 bits on
+    the paper's dense ClusterData)."""
+    x = workloads.sorted_list(workloads.CLUSTERED, 77, 1 << 26, 1 << 18)
+    for mode in (oracle.D4, oracle.DM, oracle.D2, oracle.D1):
+        plain = oracle.encode(x, mode).size
+        patched = oracle.encode(x, mode, patched=True).size
+        assert patched < plain, mode
+        assert np.array_equal(oracle.decode(oracle.encode(x, mode, patched=True)), x)
+
+
+def test_fastpfor_corrupt_streams_rejected():
+    x = np.cumsum(np.array([1] * 300 + [1 << 20] + [2] * 400, dtype=np.uint64)).astype(np.uint32)
+    enc = oracle.encode(x, oracle.D1, patched=True)
+    assert np.array_equal(oracle.decode(enc), x)
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(enc[:-4])                  # truncated array
+    bad = enc.copy()
+    bad[6] = bad[6] & 0xF7                       # patched flag cleared: trailing bytes
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(bad)
+    pw = int.from_bytes(enc[24:32].tobytes(), "little")
+    p = 32 + 8 + 4 * pw + 4 * (x.size % 128)      # 5 blocks: widths padded to 8
+    bad = enc.copy()
+    bad[p + 4 + 1] = 129                         # exception count > 128
+    with pytest.raises(oracle.OracleError):
+        oracle.decode(bad)
