@@ -156,13 +156,14 @@ def cpu_baseline(flat, offs, passes):
                       f"{threads} threads, {dt:.1f} s wall, {cpu:.1f} s CPU"}
 
 
-def delta_forms(s4, torch, flat, offs, outs, stream, steps, warmup):
-    """The bulk workload in each differential form (Sec. 5): payload bits per
-    integer and the single-launch decode rate."""
+def delta_forms(s4, torch, flat, offs, outs, stream, steps, warmup, patched=False):
+    """The bulk workload in each differential form (Sec. 5), as S4-BP128 or,
+    with patched, as S4-FastPFOR (Sec. 4.4): payload bits per integer and
+    the single-launch decode rate (unpack, patch and prefix in one pass)."""
     import numpy as np
     res = {}
     for name, delta in (("D4", s4.DELTA_D4), ("DM", s4.DELTA_DM), ("D2", s4.DELTA_D2), ("D1", s4.DELTA_D1)):
-        buf, soffs = s4.encode_many(flat, offs, delta=delta)
+        buf, soffs = s4.encode_many(flat, offs, delta=delta, patched=patched)
         lists = [s4.DeviceList.upload(buf[int(soffs[i]): int(soffs[i + 1])]) for i in range(len(offs) - 1)]
         n = float(sum(l.n for l in lists))
         pb = float(sum(l.payload_bytes for l in lists))
@@ -502,6 +503,8 @@ def main():
     if not args.decode_only:
         result["delta_forms"] = delta_forms(s4, torch, flat, offs, outs, stream, 20, 3)
         log(f"delta forms: {result['delta_forms']}")
+        result["fastpfor_forms"] = delta_forms(s4, torch, flat, offs, outs, stream, 20, 3, patched=True)
+        log(f"S4-FastPFOR forms: {result['fastpfor_forms']}")
     if not args.no_batched and not args.decode_only:
         try:
             result["batched"] = batched(s4, workloads, torch, args.batch_queries, args.plain_sample)

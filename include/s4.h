@@ -55,7 +55,7 @@ int s4_version(void); /* stream format version written by s4_encode (1) */
  * Serialized S4-BP128-D4 stream (little-endian, all offsets in bytes):
  *   0  u32 magic 0x34443453 ("S4D4")      4  u16 version = 1
  *   6  u16 flags (bit 0: strictly increasing; bits 1-2: differential form
- *                 S4_DELTA_*; other bits 0)
+ *                 S4_DELTA_*; bit 3: patched (S4-FastPFOR); other bits 0)
  *   8  u64 n      16 u32 nb = floor(n/128)  20 u32 t = n - 128 nb
  *   24 u64 pw = sum over blocks of 4 b_k (payload 32-bit words)
  *   32 u8 widths[nb], zero-padded to a multiple of 4 bytes
@@ -71,13 +71,30 @@ int s4_version(void); /* stream format version written by s4_encode (1) */
  *   S4_DELTA_DM  delta_{4i+j} = x_{4i+j} - x_{4i-1}
  *   S4_DELTA_D2  delta_i = x_i - x_{i-2}
  *   S4_DELTA_D1  delta_i = x_i - x_{i-1}
+ *
+ * Patched streams (S4-FastPFOR, Sec. 4.4; flag bit 3): block k is packed
+ * at a width b'_k <= b_k (widths[] and pw count b'), keeping each delta's
+ * low b' bits; deltas >= 2^b' are exceptions.  b' minimises 128 b' +
+ * c(b') (b - b' + 8), c(b') the number of exceptions; ties go to the
+ * larger b'.  After the tail come the pages of up to 512 blocks, each:
+ *      u32 meta_len; per block u8 b, u8 c, then c u8 positions (increasing,
+ *      < 128); zero-padded to a multiple of 4 bytes;
+ *      u32 present: bit d-1 set when some block of the page has c > 0 and
+ *      b - b' = d; then for each such d ascending: u32 count, and the
+ *      count high parts (delta >> b', d bits each, in block then position
+ *      order) packed LSB-first, value e at bit e d, padded to a multiple of
+ *      32 values (d words per 32).
  */
 #define S4_DELTA_D4 0u
 #define S4_DELTA_DM 1u
 #define S4_DELTA_D2 2u
 #define S4_DELTA_D1 3u
+/* OR into the `delta` argument of s4_encode_ex / s4_encode_many to write a
+ * patched (S4-FastPFOR) stream in that form. */
+#define S4_CODEC_FASTPFOR 0x100u
 
-/* Worst-case stream size for n integers (every block at b = 32). */
+/* Worst-case stream size for n integers (every block at b = 32; covers
+ * patched streams too). */
 size_t s4_encoded_bound(uint64_t n);
 
 /* Encode host list in[n] (non-decreasing, duplicates allowed) into host
@@ -86,7 +103,8 @@ size_t s4_encoded_bound(uint64_t n);
  * decreases. Sec. 4.2-4.3, Sec. 5. */
 int s4_encode(const uint32_t *in, uint64_t n, uint8_t *out, size_t cap, size_t *out_bytes);
 
-/* s4_encode with an explicit differential form (S4_DELTA_*). */
+/* s4_encode with an explicit differential form (S4_DELTA_*), optionally
+ * ORed with S4_CODEC_FASTPFOR for a patched stream. */
 int s4_encode_ex(const uint32_t *in, uint64_t n, uint32_t delta, uint8_t *out, size_t cap, size_t *out_bytes);
 
 /* Encode `count` host lists in parallel with differential form `delta`:
@@ -124,8 +142,9 @@ int s4_list_upload(const uint8_t *enc, size_t bytes, void *stream, s4_list **out
 int s4_list_free(s4_list *list);
 
 /* Length facts of an uploaded list (host values, no device access).
- * payload_bytes counts widths + payload + tail (the paper's size);
- * index_bytes counts block offsets + skip index. */
+ * payload_bytes counts widths + payload + tail (+ the pages of a patched
+ * stream: the paper's size); index_bytes counts block offsets + skip index
+ * (+ 16 bytes per block of exception records for a patched list). */
 int s4_list_info(const s4_list *list, uint64_t *n, uint32_t *nb, uint32_t *flags,
                  uint64_t *payload_bytes, uint64_t *index_bytes);
 

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libs4.so")
 
 OK, EINVAL, EUNSORTED, ERANGE, ECORRUPT, ENOMEM, EDEVICE, EAGAIN = 0, -1, -2, -3, -4, -5, -6, -7
 DELTA_D4, DELTA_DM, DELTA_D2, DELTA_D1 = 0, 1, 2, 3
+CODEC_FASTPFOR = 0x100  # OR into `delta`: patched (S4-FastPFOR) stream
 
 # every symbol declared in include/s4.h, with (restype, argtypes)
 _vp = ctypes.c_void_p
@@ -168,20 +169,23 @@ def encoded_bound(n: int) -> int:
     return int(require_library().s4_encoded_bound(n))
 
 
-def encode(x, delta: int = DELTA_D4) -> np.ndarray:
-    """Host encode of a non-decreasing uint32 list (s4_encode_ex)."""
+def encode(x, delta: int = DELTA_D4, patched: bool = False) -> np.ndarray:
+    """Host encode of a non-decreasing uint32 list (s4_encode_ex); patched
+    selects S4-FastPFOR."""
     lib = require_library()
     x = np.ascontiguousarray(x, dtype=np.uint32)
     cap = encoded_bound(x.size)
     out = np.zeros(cap, dtype=np.uint8)
     nbytes = ctypes.c_size_t(0)
-    _check(lib.s4_encode_ex(_ptr(x, ctypes.c_uint32), x.size, delta, _ptr(out, ctypes.c_uint8), cap,
+    code = delta | (CODEC_FASTPFOR if patched else 0)
+    _check(lib.s4_encode_ex(_ptr(x, ctypes.c_uint32), x.size, code, _ptr(out, ctypes.c_uint8), cap,
                             ctypes.byref(nbytes)), "s4_encode_ex")
     return out[: nbytes.value].copy()
 
 
-def encode_many(flat, offsets, nthreads: int = 0, delta: int = DELTA_D4):
+def encode_many(flat, offsets, nthreads: int = 0, delta: int = DELTA_D4, patched: bool = False):
     """Encode many lists at once: returns (streams buffer, stream offsets)."""
+    delta = delta | (CODEC_FASTPFOR if patched else 0)
     lib = require_library()
     flat = np.ascontiguousarray(flat, dtype=np.uint32)
     offsets = np.ascontiguousarray(offsets, dtype=np.uint64)

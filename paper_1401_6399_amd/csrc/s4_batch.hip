@@ -361,18 +361,20 @@ static int index_build(const uint8_t *encs, const uint64_t *enc_offsets, uint64_
   ix->lengths.resize(count);
   ix->flags.resize(count);
   ix->pw.resize(count);
+  ix->data_bytes.resize(count);
   for (uint64_t i = 0; i < count; ++i) {
     const StreamView &v = views[i];
     ix->lengths[i] = v.n;
     ix->flags[i] = v.flags;
+    ix->data_bytes[i] = v.data_bytes();
     ix->total_ints += v.n;
     if (ix->kinds[i]) {
       ix->pw[i] = 0;
       ++ix->bitmap_lists;
     } else {
       ix->pw[i] = v.pw;
-      ix->payload_bytes += uint64_t(v.nb) + 4 * v.pw + 4ull * v.t;
-      ix->index_bytes += uint64_t(v.nb) * (4 + 4 + 16);
+      ix->payload_bytes += v.data_bytes();
+      ix->index_bytes += uint64_t(v.nb) * (4 + 4 + 16 + (v.patched() ? 16 : 0));
     }
   }
   ix->payload_bytes += ix->bitmap_bytes;
@@ -454,8 +456,8 @@ int s4_index_list(const s4_index *ix, uint64_t i, s4_list **out) {
   l->flags = ix->flags[i];
   l->arena = nullptr;
   l->pw = ix->pw[i];
-  l->payload_bytes = uint64_t(d.nb) + 4 * l->pw + 4ull * d.t;
-  l->index_bytes = uint64_t(d.nb) * (4 + 4 + 16);
+  l->payload_bytes = ix->data_bytes[i];
+  l->index_bytes = uint64_t(d.nb) * (4 + 4 + 16 + (d.exc ? 16 : 0));
   *out = l;
   return S4_OK;
 }

@@ -84,21 +84,28 @@ __global__ __launch_bounds__(256) void k_block_sums(const DList *__restrict__ li
   const uint32_t lane = lane_id();
   const uint64_t wave = uint64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const uint64_t g = wave * 4 + (lane >> 4);
+  __shared__ __align__(16) uint32_t slices[4][4][kBlock];  // per wave, per row
   const bool active = g < total_blocks;
   uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
   uint32_t mode = S4_DELTA_D4;
+  uint32_t lo = 0, k = 0;
+  bool patched = false;
   if (active) {
     // list of block g: last l with blk_prefix[l] <= g
-    uint32_t lo = 0, hi = nlists;
+    uint32_t hi = nlists;
     while (hi - lo > 1) {
       uint32_t mid = (lo + hi) >> 1;
       if (blk_prefix[mid] <= g) lo = mid; else hi = mid;
     }
     const DList &L = lists[lo];
-    const uint32_t k = uint32_t(g - blk_prefix[lo]);
+    k = uint32_t(g - blk_prefix[lo]);
     mode = L.mode;
+    patched = L.exc != nullptr;
     extract_row(L.payload + L.offs[k], L.widths[k], lane & 15u, d0, d1);
   }
+  // rows of patched lists add their exceptions before the prefix
+  if (__ballot(patched))
+    patch_row(lists[lo], k, patched, lane & 15u, slices[threadIdx.x >> 6][lane >> 4], d0, d1);
   // rows of one wave may belong to lists of different forms: evaluate each
   // form the wave holds (row scans keep the rows apart)
   uint32_t x0[4], x1[4], y0[4], y1[4];
@@ -189,7 +196,9 @@ constexpr uint32_t kPassWords = 4u * kBlock;
 //  3. The pass's 512 values go through the wave's LDS slice so that each
 //     store instruction writes 1 KiB of contiguous output (lane l stores
 //     values 4l .. 4l + 3 of each half): whole cache lines per instruction.
-template <int P, uint32_t MODE>
+//  (Patched lists, PATCHED: before its prefix each pass's deltas go through
+//  the same LDS slice once, where the rows add their blocks' exceptions.)
+template <int P, uint32_t MODE, bool PATCHED>
 __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
                                                  uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
   static_assert(P >= 1 && P <= 16, "4 P blocks per wave must fit 64 lanes");
@@ -217,6 +226,7 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const uint32_t k0 = kbase + 4u * p;
+    if (PATCHED) patch_row(L, k0 + row, k0 + row < full_end, i, tb + row * kBlock, d0[p], d1[p]);
     uint32_t x0[4], x1[4];
     prefix_form<false, MODE>(d0[p], d1[p], c, x0, x1);
 #pragma unroll
@@ -239,11 +249,20 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
 template <int P>
 __device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
                                             uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
+  if (L.exc) {
+    switch (uniform(L.mode)) {
+      case S4_DELTA_D1: decode_wave_form<P, S4_DELTA_D1, true>(L, first, full_end, kbase, out, tb); break;
+      case S4_DELTA_D2: decode_wave_form<P, S4_DELTA_D2, true>(L, first, full_end, kbase, out, tb); break;
+      case S4_DELTA_DM: decode_wave_form<P, S4_DELTA_DM, true>(L, first, full_end, kbase, out, tb); break;
+      default: decode_wave_form<P, S4_DELTA_D4, true>(L, first, full_end, kbase, out, tb); break;
+    }
+    return;
+  }
   switch (uniform(L.mode)) {
-    case S4_DELTA_D1: decode_wave_form<P, S4_DELTA_D1>(L, first, full_end, kbase, out, tb); break;
-    case S4_DELTA_D2: decode_wave_form<P, S4_DELTA_D2>(L, first, full_end, kbase, out, tb); break;
-    case S4_DELTA_DM: decode_wave_form<P, S4_DELTA_DM>(L, first, full_end, kbase, out, tb); break;
-    default: decode_wave_form<P, S4_DELTA_D4>(L, first, full_end, kbase, out, tb); break;
+    case S4_DELTA_D1: decode_wave_form<P, S4_DELTA_D1, false>(L, first, full_end, kbase, out, tb); break;
+    case S4_DELTA_D2: decode_wave_form<P, S4_DELTA_D2, false>(L, first, full_end, kbase, out, tb); break;
+    case S4_DELTA_DM: decode_wave_form<P, S4_DELTA_DM, false>(L, first, full_end, kbase, out, tb); break;
+    default: decode_wave_form<P, S4_DELTA_D4, false>(L, first, full_end, kbase, out, tb); break;
   }
 }
 
@@ -411,12 +430,21 @@ static void plan_arena(Upload &u) {
   u.blk_prefix.assign(L + 1, 0);
   u.pay_base.assign(L, 0);
   u.tail_base.assign(L, 0);
+  u.exc_base.assign(L, 0);
+  u.xd_base.assign(L, 0);
   for (size_t i = 0; i < L; ++i) {
-    u.blk_prefix[i + 1] = u.blk_prefix[i] + u.views[i].nb;
+    const StreamView &v = u.views[i];
+    u.blk_prefix[i + 1] = u.blk_prefix[i] + v.nb;
     u.pay_base[i] = u.total_words;
-    u.total_words += u.views[i].pw;
+    u.total_words += v.pw;
     u.tail_base[i] = u.total_tail;
-    u.total_tail += u.views[i].t;
+    u.total_tail += v.t;
+    if (v.patched()) {
+      u.exc_base[i] = u.total_exc;
+      u.total_exc += v.nb;
+      u.xd_base[i] = u.total_xwords;
+      u.total_xwords += (v.x_positions + 3) / 4 + v.x_array_words;
+    }
   }
   u.total_blocks = u.blk_prefix[L];
   ArenaLayout &a = u.lay;
@@ -434,6 +462,8 @@ static void plan_arena(Upload &u) {
   a.seeds_off = take(16 * u.total_blocks);
   a.tail_off = take(4 * u.total_tail);
   a.payload_off = take(4 * u.total_words + kPayloadPadBytes);
+  a.exc_off = take(16 * u.total_exc);
+  a.xdata_off = take(4 * u.total_xwords);
   a.total = off;
 }
 
@@ -452,7 +482,56 @@ static DList make_desc(const Upload &u, size_t i, char *base) {
   d.t = u.views[i].t;
   d.mode = (u.views[i].flags >> 1) & 3u;
   d.words = 0;
+  d.exc = nullptr;
+  d.xdata = nullptr;
+  if (u.views[i].patched()) {
+    d.exc = reinterpret_cast<const uint4 *>(base + a.exc_off) + u.exc_base[i];
+    d.xdata = reinterpret_cast<const uint32_t *>(base + a.xdata_off) + u.xd_base[i];
+  }
   return d;
+}
+
+// Host image of a patched list's exceptions: one record per block (count,
+// d = b - b', b'; byte offset of its positions; word offset of its page's
+// array for d; index of its first exception there), the positions bytes,
+// then every page's arrays, each followed by one zero word.
+static void fill_exceptions(const StreamView &v, uint4 *rec, uint8_t *xd) {
+  uint64_t pos = 0;                                  // bytes of positions so far
+  uint64_t arr = (v.x_positions + 3) / 4;            // words: arrays follow the positions
+  const uint8_t *p = v.pages;
+  for (uint64_t k0 = 0; k0 < v.nb; k0 += kPage) {
+    const uint64_t k1 = std::min<uint64_t>(v.nb, k0 + kPage);
+    uint32_t meta_len;
+    std::memcpy(&meta_len, p, 4);
+    const uint8_t *m = p + 4;
+    const uint8_t *q = m + align_up(meta_len, 4);
+    uint32_t present;
+    std::memcpy(&present, q, 4);
+    q += 4;
+    uint64_t at[33] = {0};
+    for (uint32_t d = 1; d <= 32; ++d) {
+      if (!((present >> (d - 1)) & 1u)) continue;
+      uint32_t count;
+      std::memcpy(&count, q, 4);
+      const uint64_t words = uint64_t(d) * ((count + 31u) / 32u);
+      at[d] = arr;
+      std::memcpy(xd + 4 * arr, q + 4, 4 * words);
+      arr += words + 1;
+      q += 4 + 4 * words;
+    }
+    uint32_t used[33] = {0};
+    uint64_t o = 0;
+    for (uint64_t k = k0; k < k1; ++k) {
+      const uint32_t b = m[o], c = m[o + 1], bp = v.widths[k], d = b - bp;
+      o += 2;
+      rec[k] = make_uint4(c | (d << 8) | (bp << 16), uint32_t(pos), uint32_t(at[d]), used[d]);
+      std::memcpy(xd + pos, m + o, c);
+      pos += c;
+      used[d] += c;
+      o += c;
+    }
+    p = q;
+  }
 }
 
 // Copy the parsed streams into a new device arena and build the skip
@@ -491,6 +570,9 @@ int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DLi
     }
     std::memcpy(img.data() + a.payload_off + 4 * u.pay_base[i], v.payload, 4 * v.pw);
     std::memcpy(img.data() + a.tail_off + 4 * u.tail_base[i], v.tail, 4 * size_t(v.t));
+    if (v.patched())
+      fill_exceptions(v, reinterpret_cast<uint4 *>(img.data() + a.exc_off) + u.exc_base[i],
+                      reinterpret_cast<uint8_t *>(img.data() + a.xdata_off) + 4 * u.xd_base[i]);
   }
   e = hipMemcpyAsync(dev, img.data(), a.total, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -686,8 +768,8 @@ int s4_list_upload(const uint8_t *enc, size_t bytes, void *stream, s4_list **out
   l->t = v.t;
   l->pw = v.pw;
   l->flags = v.flags;
-  l->payload_bytes = uint64_t(v.nb) + 4 * v.pw + 4ull * v.t;
-  l->index_bytes = uint64_t(v.nb) * (4 + 4 + 16);
+  l->payload_bytes = v.data_bytes();
+  l->index_bytes = uint64_t(v.nb) * (4 + 4 + 16 + (v.patched() ? 16 : 0));
   *out = l;
   return S4_OK;
 }

@@ -19,6 +19,8 @@ constexpr uint32_t kBlock = 128;          // integers per block (Sec. 4.3)
 constexpr uint32_t kPayloadPadBytes = 64; // lets extraction read 3 rows past any block
 constexpr uint32_t kMaxGallopBlocks = 512;
 constexpr uint32_t kMaxTerms = 32;  // lists after the shortest one in a conjunction
+constexpr uint32_t kPage = 512;     // blocks whose exceptions a patched stream pools
+constexpr uint16_t kFlagPatched = 8;  // stream flag bit 3: S4-FastPFOR
 
 // Device view of one list: structure of arrays in HBM.
 struct DList {
@@ -28,6 +30,11 @@ struct DList {
   const uint32_t *bmax;     // [nb]  x[128k + 127]
   const uint4 *seeds;       // [nb]  x[128k-4 .. 128k-1]
   const uint32_t *tail;     // [t]
+  // patched lists (S4-FastPFOR, Sec. 4.4), else null: per block
+  // {c | d << 8 | b' << 16, position byte offset, array word offset, index
+  // of the block's first exception in that array}, offsets into xdata
+  const uint4 *exc;         // [nb]
+  const uint32_t *xdata;    // exception positions (bytes), then the arrays
   uint64_t n;
   uint32_t nb;
   uint32_t t;
@@ -46,9 +53,16 @@ struct StreamView {
   uint64_t n = 0, pw = 0;
   uint32_t nb = 0, t = 0;
   uint16_t flags = 0;
-  const uint8_t *widths = nullptr;
+  const uint8_t *widths = nullptr;   // packed widths (b' for patched streams)
   const uint8_t *payload = nullptr;  // byte pointer (4-byte aligned within the stream)
   const uint8_t *tail = nullptr;
+  // patched streams: the pages, their size, and what the device copy of the
+  // exceptions needs (positions, array words incl. one pad word per array)
+  const uint8_t *pages = nullptr;
+  uint64_t pages_bytes = 0, x_positions = 0, x_array_words = 0;
+  bool patched() const { return (flags & kFlagPatched) != 0; }
+  // bytes of the stream that are data: width bytes, payload, tail, pages
+  uint64_t data_bytes() const { return uint64_t(nb) + 4 * pw + 4ull * t + pages_bytes; }
 };
 
 // error reporting
@@ -73,14 +87,14 @@ s4_tuning &tuning();
 // Host-side layout of a device arena holding `count` lists.
 struct ArenaLayout {
   size_t widths_off = 0, offs_off = 0, bmax_off = 0, seeds_off = 0, payload_off = 0, tail_off = 0,
-         desc_off = 0, blkpre_off = 0, total = 0;
+         desc_off = 0, blkpre_off = 0, exc_off = 0, xdata_off = 0, total = 0;
 };
 
 // Parsed streams to be placed in one device arena.
 struct Upload {
   std::vector<StreamView> views;
-  std::vector<uint64_t> blk_prefix, pay_base, tail_base;
-  uint64_t total_blocks = 0, total_words = 0, total_tail = 0;
+  std::vector<uint64_t> blk_prefix, pay_base, tail_base, exc_base, xd_base;
+  uint64_t total_blocks = 0, total_words = 0, total_tail = 0, total_exc = 0, total_xwords = 0;
   ArenaLayout lay;
 };
 
@@ -163,7 +177,7 @@ struct s4_index {
   uint64_t universe = 0, bitmap_lists = 0, bitmap_bytes = 0, select_bytes = 0;
   uint32_t gap = 0;         // hyb+m2 parameter B (0: no bitmaps)
   std::vector<s4::DList> lists;    // host copy of the descriptors
-  std::vector<uint64_t> lengths, pw;
+  std::vector<uint64_t> lengths, pw, data_bytes;
   std::vector<uint32_t> flags;
   std::vector<uint8_t> kinds;      // 1: bitmap
   const s4::DList *d_lists = nullptr;  // device copy

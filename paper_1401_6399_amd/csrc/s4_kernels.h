@@ -193,18 +193,62 @@ __device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4
   }
 }
 
-// Decode block k of L with one 16-lane row per block: extract, then the
-// integrated prefix sum of the list's differential form (Alg. 1 with the
-// form's P(t, v)) seeded from the skip index.  Rows whose `active` is
-// false compute zeros.  All 64 lanes must call this together.
+// Patching (S4-FastPFOR, Sec. 4.4) of block k of a patched list, on the
+// block's 128 deltas staged in LDS v[0..127] in block order: the row's 16
+// lanes take its exceptions e = i, i + 16, ...; each adds its high part,
+// d = b - b' bits read from the page's array for d at the block's running
+// index, above the b' low bits unpacked at its position.  Exceptions of a
+// block sit at distinct positions, so the adds never collide.
+__device__ __forceinline__ void patch_block(const DList &L, uint32_t k, uint32_t i, uint32_t *v) {
+  const uint4 x = L.exc[k];
+  const uint32_t c = x.x & 0xFFu, d = (x.x >> 8) & 0x3Fu, bp = (x.x >> 16) & 0x3Fu;
+  const uint8_t *pos = reinterpret_cast<const uint8_t *>(L.xdata) + x.y;
+  const uint32_t *arr = L.xdata + x.z;
+  for (uint32_t e = i; e < c; e += 16) {
+    const uint32_t bit = (x.w + e) * d;
+    const uint32_t w = bit >> 5, s = bit & 31u;
+    const uint32_t lo = arr[w], hi = arr[w + 1];  // the array's pad word keeps w + 1 inside
+    const uint32_t h = funnel(hi, lo, s) & width_mask(d);
+    v[pos[e]] += h << bp;
+  }
+}
+
+// Stage a row's deltas (positions 8i .. 8i + 7) in its LDS slice v, patch
+// them, and load them back.  Whole-wave call (it synchronises the wave);
+// only rows with `active` touch their slice.
+__device__ __forceinline__ void patch_row(const DList &L, uint32_t k, bool active, uint32_t i, uint32_t *v,
+                                          uint32_t d0[4], uint32_t d1[4]) {
+  u32x4 *t = reinterpret_cast<u32x4 *>(v + 8u * i);
+  if (active) {
+    t[0] = u32x4{d0[0], d0[1], d0[2], d0[3]};
+    t[1] = u32x4{d1[0], d1[1], d1[2], d1[3]};
+  }
+  wave_sync();
+  if (active) patch_block(L, k, i, v);
+  wave_sync();
+  if (active) {
+    const u32x4 a = t[0], b = t[1];
+    d0[0] = a.x; d0[1] = a.y; d0[2] = a.z; d0[3] = a.w;
+    d1[0] = b.x; d1[1] = b.y; d1[2] = b.z; d1[3] = b.w;
+  }
+  wave_sync();
+}
+
+// Decode block k of L with one 16-lane row per block: extract, patch when
+// the list is patched (its exceptions, staged through the row's 128-word
+// LDS slice `scratch`), then the integrated prefix sum of the list's
+// differential form (Alg. 1 with the form's P(t, v)) seeded from the skip
+// index.  Rows whose `active` is false compute zeros.  All 64 lanes must
+// call this together, for one list.
 __device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool active, uint32_t i,
-                                           uint32_t x0[4], uint32_t x1[4]) {
+                                           uint32_t x0[4], uint32_t x1[4], uint32_t *scratch) {
   uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
   uint4 seed = make_uint4(0, 0, 0, 0);
   if (active) {
     extract_row(L.payload + L.offs[k], L.widths[k], i, d0, d1);
     seed = L.seeds[k];
   }
+  if (L.exc) patch_row(L, k, active, i, scratch, d0, d1);
   const uint32_t sv[4] = {seed.x, seed.y, seed.z, seed.w};
   prefix_deltas<true>(L.mode, d0, d1, sv, x0, x1);
 }
@@ -362,13 +406,14 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     cnt = kBlock;
     tr.bytes += 16u * uniform(r.L.widths[item]) + 1u + 4u + 16u;
     tr.blocks += 1;
-    if (r.L.mode == S4_DELTA_D4) {
+    if (r.L.mode == S4_DELTA_D4 && !r.L.exc) {
       decode_block_wave(r.L, item, s.r);
     } else {
-      // other forms: row 0 decodes the block in the row layout
+      // other forms and patched lists: row 0 decodes the block in the row
+      // layout (patching through s.r)
       uint32_t x0[4], x1[4];
       const uint32_t ri = lane & 15u;
-      decode_row(r.L, item, lane < 16, ri, x0, x1);
+      decode_row(r.L, item, lane < 16, ri, x0, x1, s.r);
       if (lane < 16) {
         *reinterpret_cast<uint4 *>(&s.r[8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
         *reinterpret_cast<uint4 *>(&s.r[8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
@@ -466,7 +511,7 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
                   uint32_t(__builtin_amdgcn_readlane(int(tb), 32)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 48));
       tr.blocks += min(4u, U - g);
       uint32_t x0[4], x1[4];
-      decode_row(f, blk, blk < nbf, ri, x0, x1);
+      decode_row(f, blk, blk < nbf, ri, x0, x1, s.f[row]);
       if (blk < nbf) {
         *reinterpret_cast<uint4 *>(&s.f[row][8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
         *reinterpret_cast<uint4 *>(&s.f[row][8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);

@@ -108,6 +108,56 @@ def test_encode_many_forms_match_oracle():
             assert np.array_equal(buf[int(soffs[i]): int(soffs[i + 1])], oracle.encode(x, delta))
 
 
+def _with_outliers(seed, n, universe=1 << 31):
+    """Clustered-like gaps with sparse large jumps (exceptions at many
+    widths), strictly increasing below the universe."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.geometric(0.3, size=n).astype(np.uint64)
+    k = max(1, n // 150)
+    if n:
+        gaps[rng.integers(0, n, size=k)] += (np.uint64(1) << rng.integers(4, 22, size=k).astype(np.uint64))
+    x = np.cumsum(gaps)
+    assert n == 0 or x[-1] < universe
+    return x.astype(np.uint32)
+
+
+@pytest.mark.parametrize("delta", [0, 1, 2, 3])
+@pytest.mark.parametrize("n", [0, 5, 128, 129, 4097, 70001, 128 * 1100 + 77])
+def test_encode_patched_matches_oracle(delta, n):
+    """S4-FastPFOR streams (Sec. 4.4) are byte-identical to the oracle's,
+    over several 512-block pages, for clustered data and for data with
+    exceptions at many widths."""
+    x = workloads.sorted_list(workloads.CLUSTERED, 500 + n, 1 << 26, n)
+    assert np.array_equal(s4.encode(x, delta, patched=True), oracle.encode(x, delta, patched=True))
+    y = _with_outliers(n + delta, n)
+    enc = s4.encode(y, delta, patched=True)
+    assert np.array_equal(enc, oracle.encode(y, delta, patched=True))
+    assert enc.size <= s4.encoded_bound(n)
+
+
+def test_encode_many_patched_matches_oracle():
+    kinds, lens = workloads.bulk_lengths(8)
+    lens = (lens // 32).astype(np.uint64)
+    flat, offs = workloads.lists(kinds, lens, 99, 1 << 26)
+    for delta in (0, 3):
+        buf, soffs = s4.encode_many(flat, offs, nthreads=3, delta=delta, patched=True)
+        for i in range(len(lens)):
+            x = flat[int(offs[i]): int(offs[i + 1])]
+            assert np.array_equal(buf[int(soffs[i]): int(soffs[i + 1])], oracle.encode(x, delta, patched=True))
+
+
+def test_patched_bound_holds_for_worst_blocks():
+    """Blocks whose every delta needs 32 bits, and blocks of one huge delta
+    among zeros, stay within s4_encoded_bound."""
+    n = 128 * 600
+    for y in (np.sort(np.random.default_rng(3).integers(0, 1 << 32, size=n, dtype=np.uint64)).astype(np.uint32),
+              np.repeat(np.arange(n // 128, dtype=np.uint64) * (1 << 22), 128).astype(np.uint32)):
+        for delta in range(4):
+            enc = s4.encode(y, delta, patched=True)
+            assert enc.size <= s4.encoded_bound(n)
+            assert np.array_equal(enc, oracle.encode(y, delta, patched=True))
+
+
 def test_encode_rejects_unknown_form():
     with pytest.raises(s4.S4Error) as e:
         s4.encode(np.arange(10, dtype=np.uint32), 4)
