@@ -27,7 +27,7 @@ __global__ void k_batch_begin(BatchDev b) {
 // Persistent chunk kernel: every wave takes `grab` chunks at a time from
 // the queue until it is empty; a chunk of query q is 128 values of q's
 // shortest list carried through all of q's other lists (SvS per chunk).
-template <int WAVES>
+template <int WAVES, uint32_t FEAT>
 __global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_t grab, uint32_t gallop_blocks) {
   __shared__ ItemLds lds[WAVES];
   const uint32_t w = threadIdx.x >> 6;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_
       const DList f1 = b.lists[id1];
       r.raw = nullptr;
       r.len = r.L.n;
-      const uint32_t cnt = chain_chunk(
+      const uint32_t cnt = chain_chunk<FEAT>(
           r, local, [&](uint32_t j) -> DList { return j == 0 ? f1 : b.lists[b.sterms[tq + 1 + j]]; }, k - 1,
           lds[w], gallop_blocks, tr);
       store_chunk(cnt, lds[w], b.stage + uint64_t(item) * kBlock, b.counts + item);
@@ -141,7 +141,7 @@ __device__ uint32_t lookback(uint64_t *__restrict__ state, uint32_t item, uint32
 // and the first chunk of each entry writes that entry's CSR offset (and
 // those of any chunkless entries just before it; the last chunk closes the
 // table).  No staging, no per-query stamps.
-template <int WAVES>
+template <int WAVES, uint32_t FEAT>
 __global__ __launch_bounds__(WAVES * 64) void k_serve_chunks(BatchDev b, uint32_t grab, uint32_t gallop_blocks,
                                                              uint32_t *__restrict__ out, uint64_t out_cap,
                                                              uint64_t *__restrict__ offs) {
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_serve_chunks(BatchDev b, uint32_
       const DList f1 = b.lists[id1];
       r.raw = nullptr;
       r.len = r.L.n;
-      const uint32_t cnt = chain_chunk(
+      const uint32_t cnt = chain_chunk<FEAT>(
           r, local, [&](uint32_t j) -> DList { return j == 0 ? f1 : b.lists[b.sterms[tq + 1 + j]]; }, k - 1,
           lds[w], gallop_blocks, tr);
       bool ok = true;
@@ -223,7 +223,7 @@ struct s4_batch {
 
 static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-template <int W>
+template <int W, uint32_t F>
 static void launch_chunks(const BatchDev &d, const s4_tuning &t, hipStream_t st) {
   // chunks per queue fetch: the tuned value, but small batches spread over
   // every resident wave (at least ~4 fetches per wave)
@@ -232,11 +232,22 @@ static void launch_chunks(const BatchDev &d, const s4_tuning &t, hipStream_t st)
   const uint32_t per_group = W * grab;
   uint32_t groups = uint32_t(cu_count()) * t.groups_per_cu;
   groups = std::max<uint32_t>(1, std::min<uint32_t>(groups, (d.items + per_group - 1) / per_group));
-  hipLaunchKernelGGL(k_batch_chunks<W>, dim3(groups), dim3(W * 64), 0, st, d, grab,
+  hipLaunchKernelGGL((k_batch_chunks<W, F>), dim3(groups), dim3(W * 64), 0, st, d, grab,
                      std::min(t.gallop_blocks, kMaxGallopBlocks));
 }
 
+// The instantiation for the kinds of list the index holds.
 template <int W>
+static void launch_chunks_w(const BatchDev &d, const s4_tuning &t, hipStream_t st) {
+  switch (d.feat & (kFeatBitmap | kFeatPatched)) {
+    case kFeatBitmap: launch_chunks<W, kFeatBitmap>(d, t, st); break;
+    case kFeatPatched: launch_chunks<W, kFeatPatched>(d, t, st); break;
+    case kFeatBitmap | kFeatPatched: launch_chunks<W, kFeatBitmap | kFeatPatched>(d, t, st); break;
+    default: launch_chunks<W, 0>(d, t, st); break;
+  }
+}
+
+template <int W, uint32_t F>
 static void launch_serve(const BatchDev &d, const s4_tuning &t, uint32_t *out, uint64_t out_cap, uint64_t *offs,
                          hipStream_t st) {
   const uint32_t resident = uint32_t(cu_count()) * t.groups_per_cu * W;
@@ -244,8 +255,19 @@ static void launch_serve(const BatchDev &d, const s4_tuning &t, uint32_t *out, u
   const uint32_t per_group = W * grab;
   uint32_t groups = uint32_t(cu_count()) * t.groups_per_cu;
   groups = std::max<uint32_t>(1, std::min<uint32_t>(groups, (d.items + per_group - 1) / per_group));
-  hipLaunchKernelGGL(k_serve_chunks<W>, dim3(groups), dim3(W * 64), 0, st, d, grab,
+  hipLaunchKernelGGL((k_serve_chunks<W, F>), dim3(groups), dim3(W * 64), 0, st, d, grab,
                      std::min(t.gallop_blocks, kMaxGallopBlocks), out, out_cap, offs);
+}
+
+template <int W>
+static void launch_serve_w(const BatchDev &d, const s4_tuning &t, uint32_t *out, uint64_t out_cap, uint64_t *offs,
+                           hipStream_t st) {
+  switch (d.feat & (kFeatBitmap | kFeatPatched)) {
+    case kFeatBitmap: launch_serve<W, kFeatBitmap>(d, t, out, out_cap, offs, st); break;
+    case kFeatPatched: launch_serve<W, kFeatPatched>(d, t, out, out_cap, offs, st); break;
+    case kFeatBitmap | kFeatPatched: launch_serve<W, kFeatBitmap | kFeatPatched>(d, t, out, out_cap, offs, st); break;
+    default: launch_serve<W, 0>(d, t, out, out_cap, offs, st); break;
+  }
 }
 
 namespace s4 {
@@ -259,10 +281,10 @@ int enqueue_serve_dev(const BatchDev &d, uint32_t *out, uint64_t out_cap, uint64
     return fail(S4_EINVAL, "single-pass run: needs chunks, scan words and an epoch in 1 .. 2^30 - 1");
   const s4_tuning t = tuning();
   switch (t.waves_per_group) {
-    case 1: launch_serve<1>(d, t, out, out_cap, d_offs, st); break;
-    case 2: launch_serve<2>(d, t, out, out_cap, d_offs, st); break;
-    case 8: launch_serve<8>(d, t, out, out_cap, d_offs, st); break;
-    default: launch_serve<4>(d, t, out, out_cap, d_offs, st); break;
+    case 1: launch_serve_w<1>(d, t, out, out_cap, d_offs, st); break;
+    case 2: launch_serve_w<2>(d, t, out, out_cap, d_offs, st); break;
+    case 8: launch_serve_w<8>(d, t, out, out_cap, d_offs, st); break;
+    default: launch_serve_w<4>(d, t, out, out_cap, d_offs, st); break;
   }
   S4_HIP(hipGetLastError());
   return S4_OK;
@@ -275,10 +297,10 @@ int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, u
   hipLaunchKernelGGL(k_batch_begin, dim3(begin_groups), dim3(256), 0, st, d);
   if (d.items) {
     switch (t.waves_per_group) {
-      case 1: launch_chunks<1>(d, t, st); break;
-      case 2: launch_chunks<2>(d, t, st); break;
-      case 8: launch_chunks<8>(d, t, st); break;
-      default: launch_chunks<4>(d, t, st); break;
+      case 1: launch_chunks_w<1>(d, t, st); break;
+      case 2: launch_chunks_w<2>(d, t, st); break;
+      case 8: launch_chunks_w<8>(d, t, st); break;
+      default: launch_chunks_w<4>(d, t, st); break;
     }
   }
   S4_HIP(hipGetLastError());
@@ -379,6 +401,9 @@ static int index_build(const uint8_t *encs, const uint64_t *enc_offsets, uint64_
   }
   ix->payload_bytes += ix->bitmap_bytes;
   ix->index_bytes += ix->select_bytes;
+  ix->feat = (ix->bitmap_lists ? kFeatBitmap : 0u);
+  for (uint64_t i = 0; i < count; ++i)
+    if (!ix->kinds[i] && views[i].patched()) ix->feat |= kFeatPatched;
   *out = ix;
   return S4_OK;
 }
@@ -457,7 +482,7 @@ int s4_index_list(const s4_index *ix, uint64_t i, s4_list **out) {
   l->arena = nullptr;
   l->pw = ix->pw[i];
   l->payload_bytes = ix->data_bytes[i];
-  l->index_bytes = uint64_t(d.nb) * (4 + 4 + 16 + (d.exc ? 16 : 0));
+  l->index_bytes = uint64_t(d.nb) * (4 + 4 + 16 + (is_patched(d) ? 16 : 0));
   *out = l;
   return S4_OK;
 }
@@ -540,6 +565,7 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   }
   BatchDev &d = bt->dev;
   d.lists = ix->d_lists;
+  d.feat = ix->feat;
   d.sterms = reinterpret_cast<const uint32_t *>(m + o_sterms);
   d.qoff = reinterpret_cast<const uint32_t *>(m + o_qoff);
   d.item_base = reinterpret_cast<const uint32_t *>(m + o_ib);

@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_block_sums(const DList *__restrict__ li
     const DList &L = lists[lo];
     k = uint32_t(g - blk_prefix[lo]);
     mode = L.mode;
-    patched = L.exc != nullptr;
+    patched = is_patched(L);
     extract_row(L.payload + L.offs[k], L.widths[k], lane & 15u, d0, d1);
   }
   // rows of patched lists add their exceptions before the prefix
@@ -249,7 +249,7 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
 template <int P>
 __device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
                                             uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
-  if (L.exc) {
+  if (is_patched(L)) {
     switch (uniform(L.mode)) {
       case S4_DELTA_D1: decode_wave_form<P, S4_DELTA_D1, true>(L, first, full_end, kbase, out, tb); break;
       case S4_DELTA_D2: decode_wave_form<P, S4_DELTA_D2, true>(L, first, full_end, kbase, out, tb); break;
@@ -330,7 +330,7 @@ struct ChainArgs {
 // compressed list or raw values whose length lives on the device.  Writes
 // the chunk's survivors to stage[128 item ..] and their number to
 // counts[item]; chunks past the end of r get 0.
-template <int WAVES>
+template <int WAVES, uint32_t FEAT>
 __global__ __launch_bounds__(WAVES * 64) void k_chain(DList rl, const uint32_t *__restrict__ r_raw,
                                                       const uint64_t *__restrict__ r_len_dev, ChainArgs args,
                                                       uint32_t items_cap, uint32_t *__restrict__ stage,
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_chain(DList rl, const uint32_t *
     return;
   }
   Traffic tr;
-  const uint32_t cnt = chain_chunk(r, item, [&](uint32_t j) -> const DList & { return args.f[j]; }, args.nf,
+  const uint32_t cnt = chain_chunk<FEAT>(r, item, [&](uint32_t j) -> const DList & { return args.f[j]; }, args.nf,
                                    lds[w], gallop_blocks, tr);
   store_chunk(cnt, lds[w], stage + uint64_t(item) * kBlock, counts + item);
 }
@@ -430,21 +430,16 @@ static void plan_arena(Upload &u) {
   u.blk_prefix.assign(L + 1, 0);
   u.pay_base.assign(L, 0);
   u.tail_base.assign(L, 0);
-  u.exc_base.assign(L, 0);
-  u.xd_base.assign(L, 0);
   for (size_t i = 0; i < L; ++i) {
     const StreamView &v = u.views[i];
     u.blk_prefix[i + 1] = u.blk_prefix[i] + v.nb;
     u.pay_base[i] = u.total_words;
     u.total_words += v.pw;
+    // each list's tail region starts 16-byte aligned; a patched list's
+    // exception records and data follow its tail there
     u.tail_base[i] = u.total_tail;
-    u.total_tail += v.t;
-    if (v.patched()) {
-      u.exc_base[i] = u.total_exc;
-      u.total_exc += v.nb;
-      u.xd_base[i] = u.total_xwords;
-      u.total_xwords += (v.x_positions + 3) / 4 + v.x_array_words;
-    }
+    u.total_tail += (v.t + 3) & ~uint64_t(3);
+    if (v.patched()) u.total_tail += 4ull * v.nb + (v.x_positions + 3) / 4 + v.x_array_words;
   }
   u.total_blocks = u.blk_prefix[L];
   ArenaLayout &a = u.lay;
@@ -462,8 +457,6 @@ static void plan_arena(Upload &u) {
   a.seeds_off = take(16 * u.total_blocks);
   a.tail_off = take(4 * u.total_tail);
   a.payload_off = take(4 * u.total_words + kPayloadPadBytes);
-  a.exc_off = take(16 * u.total_exc);
-  a.xdata_off = take(4 * u.total_xwords);
   a.total = off;
 }
 
@@ -481,13 +474,7 @@ static DList make_desc(const Upload &u, size_t i, char *base) {
   d.nb = u.views[i].nb;
   d.t = u.views[i].t;
   d.mode = (u.views[i].flags >> 1) & 3u;
-  d.words = 0;
-  d.exc = nullptr;
-  d.xdata = nullptr;
-  if (u.views[i].patched()) {
-    d.exc = reinterpret_cast<const uint4 *>(base + a.exc_off) + u.exc_base[i];
-    d.xdata = reinterpret_cast<const uint32_t *>(base + a.xdata_off) + u.xd_base[i];
-  }
+  d.aux = u.views[i].patched() ? 1u : 0u;
   return d;
 }
 
@@ -570,9 +557,11 @@ int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DLi
     }
     std::memcpy(img.data() + a.payload_off + 4 * u.pay_base[i], v.payload, 4 * v.pw);
     std::memcpy(img.data() + a.tail_off + 4 * u.tail_base[i], v.tail, 4 * size_t(v.t));
-    if (v.patched())
-      fill_exceptions(v, reinterpret_cast<uint4 *>(img.data() + a.exc_off) + u.exc_base[i],
-                      reinterpret_cast<uint8_t *>(img.data() + a.xdata_off) + 4 * u.xd_base[i]);
+    if (v.patched()) {
+      // records and data right after the tail, as exc_records / exc_data expect
+      uint32_t *tl = reinterpret_cast<uint32_t *>(img.data() + a.tail_off) + u.tail_base[i] + ((v.t + 3) & ~3u);
+      fill_exceptions(v, reinterpret_cast<uint4 *>(tl), reinterpret_cast<uint8_t *>(tl + 4ull * v.nb));
+    }
   }
   e = hipMemcpyAsync(dev, img.data(), a.total, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -630,12 +619,20 @@ static size_t pair_scratch_layout(uint64_t cap_r, char *base, PairScratch *ps) {
   return off;
 }
 
+// Lists given as handles are never bitmaps; the patched instantiation is
+// used only when a patched list takes part.
 template <int WAVES>
 static void launch_chain_w(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const ChainArgs &args,
                            const PairScratch &ps, hipStream_t stream) {
   const uint32_t groups = std::max<uint32_t>(1, (ps.items_cap + WAVES - 1) / WAVES);
-  hipLaunchKernelGGL(k_chain<WAVES>, dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len, args, ps.items_cap,
-                     ps.stage, ps.counts, std::min(tuning().gallop_blocks, kMaxGallopBlocks));
+  bool patched = !r_raw && is_patched(r);
+  for (uint32_t j = 0; j < args.nf; ++j) patched |= is_patched(args.f[j]);
+  if (patched)
+    hipLaunchKernelGGL((k_chain<WAVES, kFeatPatched>), dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len,
+                       args, ps.items_cap, ps.stage, ps.counts, std::min(tuning().gallop_blocks, kMaxGallopBlocks));
+  else
+    hipLaunchKernelGGL((k_chain<WAVES, 0>), dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len, args,
+                       ps.items_cap, ps.stage, ps.counts, std::min(tuning().gallop_blocks, kMaxGallopBlocks));
 }
 
 // chunk kernel -> tile scan -> top scan -> ordered compaction; count to d_count.

@@ -105,7 +105,7 @@ int build_bitmaps(Upload &u, uint64_t universe, hipStream_t stream, void **mem, 
     d.nb = uint32_t((n + kBlock - 1) / kBlock);
     d.t = 0;
     d.mode = kBitmapList;
-    d.words = uint32_t(words);
+    d.aux = uint32_t(words);
     (*descs)[i] = d;
   }
   uint32_t h_err = 0;

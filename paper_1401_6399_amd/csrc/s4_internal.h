@@ -29,18 +29,29 @@ struct DList {
   const uint32_t *payload;  // [pw] + padding, 16-byte aligned
   const uint32_t *bmax;     // [nb]  x[128k + 127]
   const uint4 *seeds;       // [nb]  x[128k-4 .. 128k-1]
-  const uint32_t *tail;     // [t]
-  // patched lists (S4-FastPFOR, Sec. 4.4), else null: per block
-  // {c | d << 8 | b' << 16, position byte offset, array word offset, index
-  // of the block's first exception in that array}, offsets into xdata
-  const uint4 *exc;         // [nb]
-  const uint32_t *xdata;    // exception positions (bytes), then the arrays
+  const uint32_t *tail;     // [t]; patched lists: then their exception data (exc_records)
   uint64_t n;
   uint32_t nb;
   uint32_t t;
-  uint32_t mode;   // differential form, S4_DELTA_*, or kBitmapList
-  uint32_t words;  // bitmap lists: bitmap length in 32-bit words (else 0)
+  uint32_t mode;  // differential form, S4_DELTA_*, or kBitmapList
+  uint32_t aux;   // bitmap lists: bitmap length in 32-bit words; compressed lists: 1 if patched
 };
+// The descriptor stays at 72 bytes: chunk kernels copy several per chunk,
+// and a larger one measurably slows them.
+static_assert(sizeof(DList) == 72, "list descriptor size");
+
+__host__ __device__ inline bool is_patched(const DList &L) { return L.mode < 4u && L.aux != 0; }
+// Patched lists (S4-FastPFOR, Sec. 4.4): after the raw tail, padded to 16
+// bytes, one record per block {c | d << 8 | b' << 16, byte offset of its
+// positions, word offset of its page's array for d, index of its first
+// exception there} (offsets into exc_data), then the positions bytes and
+// the arrays (each followed by one zero word).
+__host__ __device__ inline const uint4 *exc_records(const DList &L) {
+  return reinterpret_cast<const uint4 *>(L.tail + ((L.t + 3u) & ~3u));
+}
+__host__ __device__ inline const uint32_t *exc_data(const DList &L) {
+  return reinterpret_cast<const uint32_t *>(exc_records(L) + L.nb);
+}
 // DList.mode of a list stored as a bitmap (hybrid index): payload holds
 // ceil(U / 32) words, bit x of the list being bit x % 32 of word x / 32;
 // bmax holds one select sample per 128 values (chunk k: the value of rank
@@ -87,14 +98,14 @@ s4_tuning &tuning();
 // Host-side layout of a device arena holding `count` lists.
 struct ArenaLayout {
   size_t widths_off = 0, offs_off = 0, bmax_off = 0, seeds_off = 0, payload_off = 0, tail_off = 0,
-         desc_off = 0, blkpre_off = 0, exc_off = 0, xdata_off = 0, total = 0;
+         desc_off = 0, blkpre_off = 0, total = 0;
 };
 
 // Parsed streams to be placed in one device arena.
 struct Upload {
   std::vector<StreamView> views;
-  std::vector<uint64_t> blk_prefix, pay_base, tail_base, exc_base, xd_base;
-  uint64_t total_blocks = 0, total_words = 0, total_tail = 0, total_exc = 0, total_xwords = 0;
+  std::vector<uint64_t> blk_prefix, pay_base, tail_base;
+  uint64_t total_blocks = 0, total_words = 0, total_tail = 0;
   ArenaLayout lay;
 };
 
@@ -142,6 +153,7 @@ struct BatchDev {
   uint32_t *err;              // set to 1 by the single-pass kernel on a failed look-back or overflow
   uint32_t items, nq, ntiles;
   uint32_t epoch;             // single-pass scan generation, 1 .. 2^30 - 1
+  uint32_t feat;              // kinds of list in the index (kFeat* of the chunk pipeline)
 };
 // Enqueue one run of a batch on st: persistent chunk kernel, scan,
 // compaction into d_results, per-query counts / CSR offsets.
@@ -176,6 +188,7 @@ struct s4_index {
   uint64_t count = 0, total_ints = 0, payload_bytes = 0, index_bytes = 0;
   uint64_t universe = 0, bitmap_lists = 0, bitmap_bytes = 0, select_bytes = 0;
   uint32_t gap = 0;         // hyb+m2 parameter B (0: no bitmaps)
+  uint32_t feat = 0;        // kinds of list held: bitmap 1, patched 2 (chunk-kernel instantiation)
   std::vector<s4::DList> lists;    // host copy of the descriptors
   std::vector<uint64_t> lengths, pw, data_bytes;
   std::vector<uint32_t> flags;

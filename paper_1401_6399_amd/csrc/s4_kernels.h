@@ -200,10 +200,11 @@ __device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4
 // index, above the b' low bits unpacked at its position.  Exceptions of a
 // block sit at distinct positions, so the adds never collide.
 __device__ __forceinline__ void patch_block(const DList &L, uint32_t k, uint32_t i, uint32_t *v) {
-  const uint4 x = L.exc[k];
+  const uint4 x = exc_records(L)[k];
   const uint32_t c = x.x & 0xFFu, d = (x.x >> 8) & 0x3Fu, bp = (x.x >> 16) & 0x3Fu;
-  const uint8_t *pos = reinterpret_cast<const uint8_t *>(L.xdata) + x.y;
-  const uint32_t *arr = L.xdata + x.z;
+  const uint32_t *xd = exc_data(L);
+  const uint8_t *pos = reinterpret_cast<const uint8_t *>(xd) + x.y;
+  const uint32_t *arr = xd + x.z;
   for (uint32_t e = i; e < c; e += 16) {
     const uint32_t bit = (x.w + e) * d;
     const uint32_t w = bit >> 5, s = bit & 31u;
@@ -234,12 +235,19 @@ __device__ __forceinline__ void patch_row(const DList &L, uint32_t k, bool activ
   wave_sync();
 }
 
+// Feature set of a chunk-pipeline instantiation: the kinds of list it can
+// meet beyond plain compressed lists.  Kernels are instantiated per set so
+// that work with neither pays nothing for them (registers, branches).
+constexpr uint32_t kFeatBitmap = 1;   // hybrid-index bitmap lists
+constexpr uint32_t kFeatPatched = 2;  // patched (S4-FastPFOR) lists
+
 // Decode block k of L with one 16-lane row per block: extract, patch when
 // the list is patched (its exceptions, staged through the row's 128-word
-// LDS slice `scratch`), then the integrated prefix sum of the list's
-// differential form (Alg. 1 with the form's P(t, v)) seeded from the skip
-// index.  Rows whose `active` is false compute zeros.  All 64 lanes must
-// call this together, for one list.
+// LDS slice `scratch`; only with PATCHED), then the integrated prefix sum
+// of the list's differential form (Alg. 1 with the form's P(t, v)) seeded
+// from the skip index.  Rows whose `active` is false compute zeros.  All
+// 64 lanes must call this together, for one list.
+template <bool PATCHED>
 __device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool active, uint32_t i,
                                            uint32_t x0[4], uint32_t x1[4], uint32_t *scratch) {
   uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
@@ -248,7 +256,7 @@ __device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool acti
     extract_row(L.payload + L.offs[k], L.widths[k], i, d0, d1);
     seed = L.seeds[k];
   }
-  if (L.exc) patch_row(L, k, active, i, scratch, d0, d1);
+  if (PATCHED && is_patched(L)) patch_row(L, k, active, i, scratch, d0, d1);
   const uint32_t sv[4] = {seed.x, seed.y, seed.z, seed.w};
   prefix_deltas<true>(L.mode, d0, d1, sv, x0, x1);
 }
@@ -370,11 +378,11 @@ __device__ __forceinline__ uint32_t load_bitmap_chunk(const DList &L, uint32_t i
     const uint32_t first = uniform(L.bmax[item]);
     const uint32_t w0 = first >> 5;
     tr.bytes += 4u;
-    for (uint32_t w = w0; got < want && w < L.words; w += 64) {
+    for (uint32_t w = w0; got < want && w < L.aux; w += 64) {
       const uint32_t wi = w + lane;
-      uint32_t word = wi < L.words ? L.payload[wi] : 0u;
+      uint32_t word = wi < L.aux ? L.payload[wi] : 0u;
       if (wi == w0) word &= ~((1u << (first & 31u)) - 1u);  // bits of earlier chunks
-      tr.bytes += 4u * min(64u, L.words - w);
+      tr.bytes += 4u * min(64u, L.aux - w);
       const uint32_t pc = uint32_t(__popc(word));
       const uint32_t incl = scan_wave64(pc);
       uint32_t pos = got + incl - pc;
@@ -391,6 +399,7 @@ __device__ __forceinline__ uint32_t load_bitmap_chunk(const DList &L, uint32_t i
 
 // Load chunk `item` of r (values 128 item .. 128 item + 127) into s.r;
 // returns how many values it has.  The whole wave calls this.
+template <uint32_t FEAT>
 __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, ItemLds &s, Traffic &tr) {
   const uint32_t lane = lane_id();
   uint32_t cnt;
@@ -400,20 +409,20 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     cnt = left < kBlock ? uint32_t(left) : kBlock;
     if (lane < cnt) s.r[lane] = r.raw[base + lane];
     if (lane + 64 < cnt) s.r[lane + 64] = r.raw[base + 64 + lane];
-  } else if (r.L.mode == kBitmapList) {
+  } else if ((FEAT & kFeatBitmap) && r.L.mode == kBitmapList) {
     return load_bitmap_chunk(r.L, item, s, tr);
   } else if (item < r.L.nb) {
     cnt = kBlock;
     tr.bytes += 16u * uniform(r.L.widths[item]) + 1u + 4u + 16u;
     tr.blocks += 1;
-    if (r.L.mode == S4_DELTA_D4 && !r.L.exc) {
+    if (r.L.mode == S4_DELTA_D4 && !((FEAT & kFeatPatched) && is_patched(r.L))) {
       decode_block_wave(r.L, item, s.r);
     } else {
       // other forms and patched lists: row 0 decodes the block in the row
       // layout (patching through s.r)
       uint32_t x0[4], x1[4];
       const uint32_t ri = lane & 15u;
-      decode_row(r.L, item, lane < 16, ri, x0, x1, s.r);
+      decode_row<(FEAT & kFeatPatched) != 0>(r.L, item, lane < 16, ri, x0, x1, s.r);
       if (lane < 16) {
         *reinterpret_cast<uint4 *>(&s.r[8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
         *reinterpret_cast<uint4 *>(&s.r[8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
@@ -448,6 +457,7 @@ __device__ __forceinline__ uint32_t compact_chunk(bool f0, bool f1, uint32_t a0,
 // value the first block whose bmax is >= the value (Sec. 6: the search of
 // the long list for each value of the short one, done here per lane over
 // the skip index), each distinct candidate once.
+template <bool PATCHED>
 __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f, ItemLds &s,
                                                     uint32_t gallop_blocks, Traffic &tr) {
   const uint32_t lane = lane_id();
@@ -511,7 +521,7 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
                   uint32_t(__builtin_amdgcn_readlane(int(tb), 32)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 48));
       tr.blocks += min(4u, U - g);
       uint32_t x0[4], x1[4];
-      decode_row(f, blk, blk < nbf, ri, x0, x1, s.f[row]);
+      decode_row<PATCHED>(f, blk, blk < nbf, ri, x0, x1, s.f[row]);
       if (blk < nbf) {
         *reinterpret_cast<uint4 *>(&s.f[row][8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
         *reinterpret_cast<uint4 *>(&s.f[row][8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
@@ -547,8 +557,8 @@ __device__ __forceinline__ uint32_t probe_chunk(uint32_t cnt, const DList &f, It
   const uint32_t a0 = v0 ? s.r[lane] : 0u;
   const uint32_t a1 = v1 ? s.r[lane + 64] : 0u;
   bool f0 = false, f1 = false;
-  if (v0 && (a0 >> 5) < f.words) f0 = (f.payload[a0 >> 5] >> (a0 & 31u)) & 1u;
-  if (v1 && (a1 >> 5) < f.words) f1 = (f.payload[a1 >> 5] >> (a1 & 31u)) & 1u;
+  if (v0 && (a0 >> 5) < f.aux) f0 = (f.payload[a0 >> 5] >> (a0 & 31u)) & 1u;
+  if (v1 && (a1 >> 5) < f.aux) f1 = (f.payload[a1 >> 5] >> (a1 & 31u)) & 1u;
   tr.bytes += 4u * cnt;
   return compact_chunk(f0, f1, a0, a1, s);
 }
@@ -566,13 +576,16 @@ __device__ __forceinline__ void store_chunk(uint32_t cnt, const ItemLds &s, uint
 // order, stopping early when nothing survives (Sec. 6: pairwise, from the
 // shortest list up).  Intersection distributes over a partition of the
 // shortest list, so chunks are independent.
-template <class FList>
+template <uint32_t FEAT, class FList>
 __device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, FList f, uint32_t nf, ItemLds &s,
                                                 uint32_t gallop_blocks, Traffic &tr) {
-  uint32_t cnt = load_chunk(r, item, s, tr);
+  uint32_t cnt = load_chunk<FEAT>(r, item, s, tr);
   for (uint32_t j = 0; j < nf && cnt > 0; ++j) {
     const DList fj = f(j);
-    cnt = fj.mode == kBitmapList ? probe_chunk(cnt, fj, s, tr) : intersect_chunk(cnt, fj, s, gallop_blocks, tr);
+    if ((FEAT & kFeatBitmap) && fj.mode == kBitmapList)
+      cnt = probe_chunk(cnt, fj, s, tr);
+    else
+      cnt = intersect_chunk<(FEAT & kFeatPatched) != 0>(cnt, fj, s, gallop_blocks, tr);
   }
   tr.bytes += 4u * cnt;  // the chunk's results
   return cnt;

@@ -171,6 +171,7 @@ int alloc_context(s4_server *s, Context &c) {
   S4_HIP(hipMemset(c.state, 0, 8 * items));  // no word carries a live epoch
   s4::BatchDev &d = c.dev;
   d.lists = s->index->d_lists;
+  d.feat = s->index->feat;
   d.head = reinterpret_cast<uint32_t *>(c.d_tab);
   d.sterms = reinterpret_cast<const uint32_t *>(c.d_tab + terms_at());
   d.state = c.state;
