@@ -235,7 +235,41 @@ def batched(s4, workloads, torch, nq, plain_sample):
         log(f"{name}: {out[name]}")
         del b
     out["hybrid"] = hybrid(s4, workloads, torch, index, buf, soffs, nq, {k: out[k] for k in ("pairwise", "multiterm")})
+    out["partitioned"] = partitioned(s4, workloads, torch, nq, {k: out[k] for k in ("pairwise", "multiterm")})
     return out
+
+
+def partitioned(s4, workloads, torch, nq, plain):
+    """Doc-ID partitioned index (Sec. 7.7's partitioning, one part per XCD
+    and finer): every list split by value range and each part encoded
+    alone; a query runs part by part in each part's own length order, chunks
+    queued per part and drained XCD-first.  Same queries, results identical
+    to the unpartitioned batch (checked by the tests); each workload
+    autotuned, replayed as a graph."""
+    flat, offs = workloads.pairwise_index()
+    res = {}
+    for parts in (8, 16):
+        sub = s4.partition_offsets(flat, offs, parts, 1 << 26)
+        buf, soffs = s4.encode_many(flat, sub)
+        ix = s4.Index(buf, soffs, parts=parts)
+        row = {"bits_per_int": round(8 * ix.payload_bytes / ix.total_ints, 3)}
+        for name, qfn in (("pairwise", workloads.pairwise_queries), ("multiterm", workloads.multiterm_queries)):
+            terms, qoffs = qfn(ix.lengths, nq)
+            b = s4.Batch(ix, terms, qoffs)
+            best, _ = b.autotune(reps=2)
+            stream = torch.cuda.Stream()
+            ms, _ = time_graph(torch, lambda: b.run(use_graph=False), stream, steps=5, warmup=2)
+            abytes, _ = b.traffic()
+            row[f"{name}_qps"] = round(b.nq / (ms / 1e3), 1)
+            row[f"{name}_ms"] = round(ms, 3)
+            row[f"{name}_algorithmic_mb"] = round(abytes / 1e6, 2)
+            row[f"{name}_speedup_vs_one_part"] = round(plain[name]["batched_ms"] / ms, 3)
+            row[f"{name}_tuning"] = best
+            del b
+        res[f"parts={parts}"] = row
+        log(f"partitioned {parts}: {row}")
+        del ix
+    return res
 
 
 def hybrid(s4, workloads, torch, index, buf, soffs, nq, plain):

@@ -288,6 +288,32 @@ int s4_index_list(const s4_index *index, uint64_t i, s4_list **out);
  * samples.  Synchronises `stream`. */
 int s4_index_build_hybrid(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count,
                           uint64_t universe, uint32_t bitmap_gap, void *stream, s4_index **out);
+/* Doc-ID partitioned index (Sec. 7.7: the paper splits its corpora into
+ * 32 or 64 independent parts by document ID and answers a query part by
+ * part, joining the results).  Stream t * parts + p (enc_offsets has
+ * count * parts + 1 entries) is part p of list t; every list's parts must
+ * hold ascending value ranges (each non-empty part starting above the end
+ * of the previous one: S4_EINVAL otherwise, checked on the device).  A
+ * batch over such an index runs each query once per part, in that part's
+ * length order, and writes the parts' results one after the other; its
+ * chunks are queued per part, and workgroups drain first the parts of
+ * their own XCD (part x mod parts for fewer than 8 parts, x, x + 8, ...
+ * otherwise; workgroups go to the 8 XCDs round-robin by id) so that each
+ * XCD's L2 holds one part's lists.  s4_index_lengths gives each list's
+ * total length; s4_index_list and the server refuse a partitioned index.
+ * parts in [1, 1024]; parts = 1 is s4_index_build.  Synchronises `stream`. */
+int s4_index_build_parts(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count,
+                         uint32_t parts, void *stream, s4_index **out);
+/* Host helper for s4_index_build_parts: for count sorted host lists
+ * in[in_offsets[t] .. in_offsets[t+1]) with every value below `universe`,
+ * sub_offsets[t * parts + p] (count * parts + 1 entries) receives where
+ * part p of list t starts in `in`: part p holds the values in
+ * [floor(p U / parts), floor((p + 1) U / parts)).  The parts of all lists
+ * are consecutive in `in`, so s4_encode_many(in, sub_offsets, count *
+ * parts, ...) encodes them.  S4_EINVAL for a value >= universe or parts
+ * outside [1, universe]. */
+int s4_partition_offsets(const uint32_t *in, const uint64_t *in_offsets, uint64_t count,
+                         uint32_t parts, uint64_t universe, uint64_t *sub_offsets);
 /* kinds[count]: 0 for a compressed list, 1 for a bitmap. */
 int s4_index_kinds(const s4_index *index, uint8_t *kinds);
 /* Hybrid parameters and sizes (all 0 for an index built without bitmaps);

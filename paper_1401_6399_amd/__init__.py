@@ -95,6 +95,8 @@ SIGNATURES = {
     "s4_index_list": (_i, [_vp, _u64, ctypes.POINTER(_vp)]),
     "s4_index_build_hybrid": (_i, [_u8p, _u64p, _u64, _u64, _u32, _vp, ctypes.POINTER(_vp)]),
     "s4_index_kinds": (_i, [_vp, _u8p]),
+    "s4_index_build_parts": (_i, [_u8p, _u64p, _u64, _u32, _vp, ctypes.POINTER(_vp)]),
+    "s4_partition_offsets": (_i, [_u32p, _u64p, _u64, _u32, _u64, _u64p]),
     "s4_index_hybrid_info": (_i, [_vp, _u64p, ctypes.POINTER(_u32), _u64p, _u64p, _u64p]),
     "s4_batch_plan": (_i, [_vp, _u32p, _u64p, _u64, _vp, ctypes.POINTER(_vp)]),
     "s4_batch_free": (_i, [_vp]),
@@ -181,6 +183,20 @@ def encode(x, delta: int = DELTA_D4, patched: bool = False) -> np.ndarray:
     _check(lib.s4_encode_ex(_ptr(x, ctypes.c_uint32), x.size, code, _ptr(out, ctypes.c_uint8), cap,
                             ctypes.byref(nbytes)), "s4_encode_ex")
     return out[: nbytes.value].copy()
+
+
+def partition_offsets(flat, offsets, parts: int, universe: int) -> np.ndarray:
+    """Where each part of each sorted list starts in `flat` (s4_partition_offsets):
+    sub-list t * parts + p holds list t's values in part p of [0, universe)."""
+    lib = require_library()
+    flat = np.ascontiguousarray(flat, dtype=np.uint32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    count = offsets.size - 1
+    sub = np.zeros(count * parts + 1, dtype=np.uint64)
+    _check(lib.s4_partition_offsets(_ptr(flat if flat.size else np.zeros(1, np.uint32), ctypes.c_uint32),
+                                    _ptr(offsets, ctypes.c_uint64), count, int(parts), int(universe),
+                                    _ptr(sub, ctypes.c_uint64)), "s4_partition_offsets")
+    return sub
 
 
 def encode_many(flat, offsets, nthreads: int = 0, delta: int = DELTA_D4, patched: bool = False):
@@ -419,20 +435,27 @@ class Index:
     index is a hyb+m2 hybrid: lists with universe / n <= B are bitmaps over
     [0, universe) (s4_index_build_hybrid)."""
 
-    def __init__(self, streams, offsets, stream=None, universe=0, bitmap_gap=0):
+    def __init__(self, streams, offsets, stream=None, universe=0, bitmap_gap=0, parts=1):
         lib = require_library()
         streams = np.ascontiguousarray(streams, dtype=np.uint8)
         offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
         self.h = ctypes.c_void_p()
+        self.parts = int(parts)
         sp = _ptr(streams if streams.size else np.zeros(1, np.uint8), ctypes.c_uint8)
-        if bitmap_gap:
+        if parts > 1:
+            if bitmap_gap:
+                raise ValueError("a partitioned index has no bitmap lists")
+            _check(lib.s4_index_build_parts(sp, _ptr(offsets, ctypes.c_uint64), (offsets.size - 1) // parts,
+                                            int(parts), _stream(stream), ctypes.byref(self.h)),
+                   "s4_index_build_parts")
+        elif bitmap_gap:
             _check(lib.s4_index_build_hybrid(sp, _ptr(offsets, ctypes.c_uint64), offsets.size - 1, int(universe),
                                              int(bitmap_gap), _stream(stream), ctypes.byref(self.h)),
                    "s4_index_build_hybrid")
         else:
             _check(lib.s4_index_build(sp, _ptr(offsets, ctypes.c_uint64), offsets.size - 1, _stream(stream),
                                       ctypes.byref(self.h)), "s4_index_build")
-        self.count = offsets.size - 1
+        self.count = (offsets.size - 1) // max(1, self.parts)
         self.lengths = np.zeros(max(1, self.count), np.uint64)
         _check(lib.s4_index_lengths(self.h, _ptr(self.lengths, ctypes.c_uint64)), "s4_index_lengths")
         self.lengths = self.lengths[: self.count]

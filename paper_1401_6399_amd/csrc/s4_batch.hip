@@ -12,21 +12,28 @@
 
 namespace s4 {
 
-// Reset the work queue and the per-query completion stamps.
+// Reset the work queues and the per-query completion stamps.
 __global__ void k_batch_begin(BatchDev b) {
   const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
-    *b.head = 0;
     *b.start = wall_clock64();
     b.stats[0] = 0;
     b.stats[1] = 0;
   }
+  for (uint32_t p = t; p < max(b.parts, 1u); p += gridDim.x * blockDim.x) b.head[p] = 0;
   for (uint32_t q = t; q < b.nq; q += gridDim.x * blockDim.x) b.qtick[q] = 0;
 }
+
+// XCDs of the device; workgroups are dispatched to them round-robin by id.
+constexpr uint32_t kXcds = 8;
 
 // Persistent chunk kernel: every wave takes `grab` chunks at a time from
 // the queue until it is empty; a chunk of query q is 128 values of q's
 // shortest list carried through all of q's other lists (SvS per chunk).
+// With a doc-ID partitioned index each part has its own queue; a
+// workgroup first drains the parts of its own XCD (part x mod P for fewer
+// than 8 parts, parts x, x + 8, ... otherwise), so each XCD's L2 holds one
+// part's lists, then helps every other queue.
 template <int WAVES, uint32_t FEAT>
 __global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_t grab, uint32_t gallop_blocks) {
   __shared__ ItemLds lds[WAVES];
@@ -37,38 +44,53 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_
   // completion stamps: one atomic per run of consecutive chunks of a query
   uint32_t run_q = kInvalid;
   uint64_t run_t = 0;
-  for (;;) {
-    uint32_t it0 = 0;
-    if (lane == 0) it0 = atomicAdd(b.head, grab);
-    it0 = uint32_t(__shfl(int(it0), 0));
-    if (it0 >= b.items) break;
-    const uint32_t it1 = min(it0 + grab, b.items);
-    for (uint32_t item = it0; item < it1; ++item) {
-      // one record per chunk: query, chunk within the query, first term, terms
-      const uint4 info = b.item_info[item];
-      const uint32_t q = uniform(info.x), local = uniform(info.y), tq = uniform(info.z), k = uniform(info.w);
-      // the two shortest lists' descriptors, loaded together up front
-      const uint32_t id0 = b.sterms[tq], id1 = b.sterms[tq + (k > 1 ? 1 : 0)];
-      RSide r;
-      r.L = b.lists[id0];
-      const DList f1 = b.lists[id1];
-      r.raw = nullptr;
-      r.len = r.L.n;
-      const uint32_t cnt = chain_chunk<FEAT>(
-          r, local, [&](uint32_t j) -> DList { return j == 0 ? f1 : b.lists[b.sterms[tq + 1 + j]]; }, k - 1,
-          lds[w], gallop_blocks, tr);
-      store_chunk(cnt, lds[w], b.stage + uint64_t(item) * kBlock, b.counts + item);
-      const uint64_t now = wall_clock64() - t0;
-      if (q != run_q) {
-        if (run_q != kInvalid && lane == 0)
-          atomicMax(reinterpret_cast<unsigned long long *>(b.qtick + run_q), static_cast<unsigned long long>(run_t));
-        run_q = q;
+  // drain queue p: chunks base .. base + size in queue order
+  auto drain = [&](uint32_t p, uint32_t base, uint32_t size) {
+    for (;;) {
+      uint32_t it0 = 0;
+      if (lane == 0) it0 = atomicAdd(b.head + p, grab);
+      it0 = uint32_t(__shfl(int(it0), 0));
+      if (it0 >= size) break;
+      const uint32_t it1 = min(it0 + grab, size);
+      for (uint32_t rel = it0; rel < it1; ++rel) {
+        const uint32_t item = base + rel;
+        // one record per chunk: query, chunk within the query, first term, terms
+        const uint4 info = b.item_info[item];
+        const uint32_t q = uniform(info.x), local = uniform(info.y), tq = uniform(info.z), k = uniform(info.w);
+        // the two shortest lists' descriptors, loaded together up front
+        const uint32_t id0 = b.sterms[tq], id1 = b.sterms[tq + (k > 1 ? 1 : 0)];
+        RSide r;
+        r.L = b.lists[id0];
+        const DList f1 = b.lists[id1];
+        r.raw = nullptr;
+        r.len = r.L.n;
+        const uint32_t cnt = chain_chunk<FEAT>(
+            r, local, [&](uint32_t j) -> DList { return j == 0 ? f1 : b.lists[b.sterms[tq + 1 + j]]; }, k - 1,
+            lds[w], gallop_blocks, tr);
+        const uint32_t slot = (FEAT & kFeatParts) ? b.item_rank[item] : item;
+        store_chunk(cnt, lds[w], b.stage + uint64_t(slot) * kBlock, b.counts + slot);
+        const uint64_t now = wall_clock64() - t0;
+        if (q != run_q) {
+          if (run_q != kInvalid && lane == 0)
+            atomicMax(reinterpret_cast<unsigned long long *>(b.qtick + run_q), static_cast<unsigned long long>(run_t));
+          run_q = q;
+        }
+        run_t = now;
       }
-      run_t = now;
+      if (run_q != kInvalid && lane == 0)
+        atomicMax(reinterpret_cast<unsigned long long *>(b.qtick + run_q), static_cast<unsigned long long>(run_t));
+      run_q = kInvalid;
     }
-    if (run_q != kInvalid && lane == 0)
-      atomicMax(reinterpret_cast<unsigned long long *>(b.qtick + run_q), static_cast<unsigned long long>(run_t));
-    run_q = kInvalid;
+  };
+  if (!(FEAT & kFeatParts)) {
+    drain(0, 0, b.items);
+  } else {
+    const uint32_t P = b.parts, x = blockIdx.x % kXcds;
+    const uint32_t own = P >= kXcds ? (P - x + kXcds - 1) / kXcds : 1u;
+    for (uint32_t v = 0; v < own + P; ++v) {
+      const uint32_t p = v < own ? (P >= kXcds ? x + kXcds * v : x % P) : (x + v - own) % P;
+      drain(p, b.part_base[p], b.part_base[p + 1] - b.part_base[p]);
+    }
   }
   if (lane == 0) {
     atomicAdd(reinterpret_cast<unsigned long long *>(b.stats), static_cast<unsigned long long>(tr.bytes));
@@ -236,13 +258,16 @@ static void launch_chunks(const BatchDev &d, const s4_tuning &t, hipStream_t st)
                      std::min(t.gallop_blocks, kMaxGallopBlocks));
 }
 
-// The instantiation for the kinds of list the index holds.
+// The instantiation for the kinds of list the index holds (bitmap lists
+// and parts never come together).
 template <int W>
 static void launch_chunks_w(const BatchDev &d, const s4_tuning &t, hipStream_t st) {
-  switch (d.feat & (kFeatBitmap | kFeatPatched)) {
+  switch ((d.feat & (kFeatBitmap | kFeatPatched)) | (d.parts > 1 ? kFeatParts : 0u)) {
     case kFeatBitmap: launch_chunks<W, kFeatBitmap>(d, t, st); break;
     case kFeatPatched: launch_chunks<W, kFeatPatched>(d, t, st); break;
     case kFeatBitmap | kFeatPatched: launch_chunks<W, kFeatBitmap | kFeatPatched>(d, t, st); break;
+    case kFeatParts: launch_chunks<W, kFeatParts>(d, t, st); break;
+    case kFeatParts | kFeatPatched: launch_chunks<W, kFeatParts | kFeatPatched>(d, t, st); break;
     default: launch_chunks<W, 0>(d, t, st); break;
   }
 }
@@ -321,6 +346,25 @@ static void drop_graph(s4_batch *b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+}
+
+// First and last value of each of n lists (one wave each; row 0 decodes
+// the first block, patching it when the list is patched).
+__global__ __launch_bounds__(256) void k_list_bounds(const DList *__restrict__ lists, uint32_t n,
+                                                      uint32_t *__restrict__ bounds) {
+  __shared__ __align__(16) uint32_t scratch[4][kBlock];
+  const uint32_t w = threadIdx.x >> 6, lane = lane_id();
+  const uint32_t i = blockIdx.x * 4 + w;
+  if (i >= n) return;
+  const DList L = lists[i];
+  uint32_t x0[4], x1[4];
+  decode_row<true>(L, 0, L.nb > 0 && lane < 16, lane & 15u, x0, x1, scratch[w]);
+  if (lane == 0) {
+    const uint32_t first = L.nb ? x0[0] : (L.t ? L.tail[0] : 0u);
+    const uint32_t last = L.t ? L.tail[L.t - 1] : (L.nb ? L.bmax[L.nb - 1] : 0u);
+    bounds[2 * i] = first;
+    bounds[2 * i + 1] = last;
+  }
 }
 
 // Index over count serialized lists; with gap > 0 (hyb+m2) the lists whose
@@ -415,6 +459,85 @@ int s4_index_build(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t co
   return index_build(encs, enc_offsets, count, 0, 0, as_stream(stream), out);
 }
 
+int s4_partition_offsets(const uint32_t *in, const uint64_t *in_offsets, uint64_t count, uint32_t parts,
+                         uint64_t universe, uint64_t *sub_offsets) {
+  if (!in_offsets || !sub_offsets || (count && !in)) return fail(S4_EINVAL, "null argument");
+  if (parts == 0 || universe == 0 || universe > (1ull << 32) || parts > universe)
+    return fail(S4_EINVAL, "need 1 <= parts <= universe <= 2^32");
+  for (uint64_t t = 0; t < count; ++t) {
+    const uint64_t a = in_offsets[t], b = in_offsets[t + 1];
+    if (b < a) return fail(S4_EINVAL, "offsets decrease");
+    if (b > a && in[b - 1] >= universe) return fail(S4_EINVAL, "list " + std::to_string(t) + " reaches the universe");
+    sub_offsets[t * parts] = a;
+    for (uint32_t p = 1; p < parts; ++p) {
+      const uint64_t edge = uint64_t(p) * universe / parts;  // part p starts at floor(p U / parts)
+      sub_offsets[t * parts + p] = uint64_t(std::lower_bound(in + a, in + b, edge, [](uint32_t v, uint64_t e) {
+                                              return uint64_t(v) < e;
+                                            }) - in);
+    }
+  }
+  sub_offsets[count * parts] = count ? in_offsets[count] : 0;
+  return S4_OK;
+}
+
+int s4_index_build_parts(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count, uint32_t parts,
+                         void *stream, s4_index **out) {
+  if (!out) return fail(S4_EINVAL, "null argument");
+  if (parts < 1 || parts > 1024) return fail(S4_EINVAL, "parts must be in [1, 1024]");
+  if (count * parts > 0xFFFFFFFFull) return fail(S4_EINVAL, "too many lists");
+  s4_index *ix = nullptr;
+  int rc = index_build(encs, enc_offsets, count * parts, 0, 0, as_stream(stream), &ix);
+  if (rc || parts == 1) {
+    if (!rc) *out = ix;
+    return rc;
+  }
+  // each list's parts must hold ascending, disjoint value ranges: results
+  // are joined in part order
+  const uint64_t ns = count * parts;
+  uint32_t *d_bounds = nullptr;
+  std::vector<uint32_t> bounds(2 * ns);
+  hipError_t e = hipMalloc(&d_bounds, 8 * std::max<uint64_t>(ns, 1));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_list_bounds, dim3(uint32_t((ns + 3) / 4)), dim3(256), 0, as_stream(stream), ix->d_lists,
+                       uint32_t(ns), d_bounds);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(bounds.data(), d_bounds, 8 * ns, hipMemcpyDeviceToHost, as_stream(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(as_stream(stream));
+    (void)hipFree(d_bounds);
+  }
+  if (e != hipSuccess) {
+    s4_index_free(ix);
+    return hip_fail(e, "partition check");
+  }
+  ix->part_len = ix->lengths;
+  ix->parts = parts;
+  ix->count = count;
+  ix->lengths.assign(count, 0);
+  std::vector<uint32_t> flags(count, 1u);
+  for (uint64_t t = 0; t < count; ++t) {
+    bool any = false;
+    uint32_t last = 0;
+    for (uint32_t p = 0; p < parts; ++p) {
+      const uint64_t s = t * parts + p;
+      ix->lengths[t] += ix->part_len[s];
+      flags[t] &= ix->flags[s];
+      if (!ix->part_len[s]) continue;
+      if (any && bounds[2 * s] <= last) {
+        s4_index_free(ix);
+        return fail(S4_EINVAL, "list " + std::to_string(t) + ": part " + std::to_string(p) +
+                                   " does not start above the previous part");
+      }
+      any = true;
+      last = bounds[2 * s + 1];
+    }
+  }
+  ix->flags = flags;
+  ix->kinds.assign(count, 0);
+  *out = ix;
+  return S4_OK;
+}
+
 int s4_index_build_hybrid(const uint8_t *encs, const uint64_t *enc_offsets, uint64_t count, uint64_t universe,
                           uint32_t bitmap_gap, void *stream, s4_index **out) {
   if (bitmap_gap == 0) return fail(S4_EINVAL, "bitmap_gap must be > 0 (s4_index_build builds without bitmaps)");
@@ -470,6 +593,7 @@ int s4_index_info(const s4_index *ix, uint64_t *count, uint64_t *total_ints, uin
 int s4_index_list(const s4_index *ix, uint64_t i, s4_list **out) {
   if (!ix || !out) return fail(S4_EINVAL, "null argument");
   if (i >= ix->count) return fail(S4_ERANGE, "list id out of range");
+  if (ix->parts > 1) return fail(S4_EINVAL, "a partitioned index holds each list in parts");
   if (ix->kinds[i]) return fail(S4_EINVAL, "list " + std::to_string(i) + " is held as a bitmap (hybrid index)");
   s4_list *l = new (std::nothrow) s4_list;
   if (!l) return fail(S4_ENOMEM, "handle allocation failed");
@@ -494,11 +618,66 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   int rc = ensure_device();
   if (rc) return rc;
   const uint64_t nterms = h_q_offsets[nq];
-  if (nterms >= 0xFFFFFFFFull) return fail(S4_EINVAL, "too many terms");
-  std::vector<uint32_t> sterms(nterms);
+  const uint32_t P = ix->parts;
+  if (nterms * P >= 0xFFFFFFFFull) return fail(S4_EINVAL, "too many terms");
+  std::vector<uint32_t> sterms(nterms * P);
   std::vector<uint32_t> qoff(nq + 1), item_base(nq + 1);
+  std::vector<uint32_t> item_info, item_rank, part_base;
   uint64_t items = 0, bound = 0;
-  for (uint64_t q = 0; q < nq; ++q) {
+  if (P > 1) {
+    // doc-ID partitioned index: query q runs once per part p, with terms
+    // (descriptors t * P + p) in that part's length order at
+    // sterms[P qoff[q] + p k ..]; chunks are numbered query-major (slots,
+    // the result order) and queued part-major
+    std::vector<uint64_t> qitems(nq * P);
+    for (uint64_t q = 0; q < nq; ++q) {
+      const uint64_t a = h_q_offsets[q], b = h_q_offsets[q + 1];
+      if (b < a || b > nterms) return fail(S4_EINVAL, "query offsets not increasing");
+      const uint64_t k = b - a;
+      if (k == 0 || k > kMaxTerms + 1) return fail(S4_EINVAL, "query " + std::to_string(q) + ": need 1..33 terms");
+      for (uint64_t t = a; t < b; ++t) {
+        if (h_terms[t] >= ix->count) return fail(S4_EINVAL, "query " + std::to_string(q) + ": term out of range");
+        if (k > 1 && !(ix->flags[h_terms[t]] & 1u))
+          return fail(S4_EUNSORTED, "list " + std::to_string(h_terms[t]) + " is not strictly increasing");
+      }
+      qoff[q] = uint32_t(a);
+      item_base[q] = uint32_t(items);
+      for (uint32_t p = 0; p < P; ++p) {
+        uint32_t *seg = sterms.data() + P * a + p * k;
+        for (uint64_t j = 0; j < k; ++j) seg[j] = uint32_t(h_terms[a + j] * uint64_t(P) + p);
+        std::stable_sort(seg, seg + k, [&](uint32_t x, uint32_t y) { return ix->part_len[x] < ix->part_len[y]; });
+        const uint64_t m = ix->part_len[seg[0]];
+        qitems[q * P + p] = (m + kBlock - 1) / kBlock;
+        items += qitems[q * P + p];
+        bound += m;
+      }
+      if (items >= 0xFFFFFFFFull / kBlock || bound >= 0xFFFFFFFFull)
+        return fail(S4_EINVAL, "batch too large for one plan; split it");
+    }
+    qoff[nq] = uint32_t(nterms);
+    item_base[nq] = uint32_t(items);
+    item_info.resize(4 * items);
+    item_rank.resize(items);
+    part_base.assign(P + 1, 0);
+    uint64_t it = 0;
+    for (uint32_t p = 0; p < P; ++p) {
+      part_base[p] = uint32_t(it);
+      for (uint64_t q = 0; q < nq; ++q) {
+        uint64_t slot = item_base[q];
+        for (uint32_t pp = 0; pp < p; ++pp) slot += qitems[q * P + pp];
+        const uint32_t k = uint32_t(h_q_offsets[q + 1] - h_q_offsets[q]);
+        for (uint64_t i = 0; i < qitems[q * P + p]; ++i, ++it) {
+          item_info[4 * it] = uint32_t(q);
+          item_info[4 * it + 1] = uint32_t(i);
+          item_info[4 * it + 2] = uint32_t(P * h_q_offsets[q] + uint64_t(p) * k);
+          item_info[4 * it + 3] = k;
+          item_rank[it] = uint32_t(slot + i);
+        }
+      }
+    }
+    part_base[P] = uint32_t(it);
+  }
+  for (uint64_t q = 0; P == 1 && q < nq; ++q) {
     const uint64_t a = h_q_offsets[q], b = h_q_offsets[q + 1];
     if (b < a || b > nterms) return fail(S4_EINVAL, "query offsets not increasing");
     const uint64_t k = b - a;
@@ -519,10 +698,12 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
     if (items >= 0xFFFFFFFFull / kBlock || bound >= 0xFFFFFFFFull)
       return fail(S4_EINVAL, "batch too large for one plan; split it");
   }
-  qoff[nq] = uint32_t(nterms);
-  item_base[nq] = uint32_t(items);
-  std::vector<uint32_t> item_info(4 * items);
-  for (uint64_t q = 0; q < nq; ++q)
+  if (P == 1) {
+    qoff[nq] = uint32_t(nterms);
+    item_base[nq] = uint32_t(items);
+    item_info.resize(4 * items);
+  }
+  for (uint64_t q = 0; P == 1 && q < nq; ++q)
     for (uint32_t i = item_base[q]; i < item_base[q + 1]; ++i) {
       item_info[4 * size_t(i)] = uint32_t(q);
       item_info[4 * size_t(i) + 1] = i - item_base[q];
@@ -537,10 +718,11 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
     off = align_up(off + std::max<size_t>(bytes, 4), 256);
     return o;
   };
-  const size_t o_sterms = take(4 * nterms), o_qoff = take(4 * (nq + 1)), o_ib = take(4 * (nq + 1)),
+  const size_t o_sterms = take(4 * nterms * P), o_qoff = take(4 * (nq + 1)), o_ib = take(4 * (nq + 1)),
                o_iq = take(16 * items), o_stage = take(4 * kBlock * items), o_counts = take(4 * items),
                o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)), o_ctrl = take(64),
-               o_qtick = take(8 * nq);
+               o_qtick = take(8 * nq), o_heads = take(4 * P), o_rank = take(4 * item_rank.size()),
+               o_pbase = take(4 * part_base.size());
   s4_batch *bt = new (std::nothrow) s4_batch;
   if (!bt) return fail(S4_ENOMEM, "handle allocation failed");
   if (hipMalloc(&bt->mem, off) != hipSuccess) {
@@ -553,7 +735,9 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   auto up = [&](size_t o, const void *src, size_t bytes) {
     if (e == hipSuccess && bytes) e = hipMemcpyAsync(m + o, src, bytes, hipMemcpyHostToDevice, st);
   };
-  up(o_sterms, sterms.data(), 4 * nterms);
+  up(o_sterms, sterms.data(), 4 * nterms * P);
+  up(o_rank, item_rank.data(), 4 * item_rank.size());
+  up(o_pbase, part_base.data(), 4 * part_base.size());
   up(o_qoff, qoff.data(), 4 * (nq + 1));
   up(o_ib, item_base.data(), 4 * (nq + 1));
   up(o_iq, item_info.data(), 16 * items);
@@ -574,11 +758,14 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   d.counts = reinterpret_cast<uint32_t *>(m + o_counts);
   d.excl = reinterpret_cast<uint32_t *>(m + o_excl);
   d.tiles = reinterpret_cast<uint32_t *>(m + o_tiles);
-  d.head = reinterpret_cast<uint32_t *>(m + o_ctrl);
+  d.head = reinterpret_cast<uint32_t *>(m + o_heads);
   d.total = reinterpret_cast<uint64_t *>(m + o_ctrl + 8);
   d.start = reinterpret_cast<uint64_t *>(m + o_ctrl + 16);
   d.qtick = reinterpret_cast<uint64_t *>(m + o_qtick);
   d.stats = reinterpret_cast<uint64_t *>(m + o_ctrl + 24);
+  d.parts = P;
+  d.item_rank = P > 1 ? reinterpret_cast<const uint32_t *>(m + o_rank) : nullptr;
+  d.part_base = P > 1 ? reinterpret_cast<const uint32_t *>(m + o_pbase) : nullptr;
   d.items = uint32_t(items);
   d.nq = uint32_t(nq);
   d.ntiles = ntiles;

@@ -144,11 +144,17 @@ struct BatchDev {
   uint32_t *counts;           // [items]
   uint32_t *excl;             // [items]
   uint32_t *tiles;            // [ntiles + 1]
-  uint32_t *head;             // work-queue head
+  uint32_t *head;             // work-queue head (one per part)
   uint64_t *total;            // number of results
   uint64_t *start;            // device clock at the start of the run
   uint64_t *qtick;            // [nq] completion time of each query
   uint64_t *stats;            // [2] algorithmic bytes read + written, blocks decoded
+  // doc-ID partitioned index: chunks are queued per part (head[p], chunks
+  // part_base[p] .. part_base[p + 1] in queue order) and chunk i's result
+  // goes to slot item_rank[i] (query-major order); null / 1 otherwise
+  const uint32_t *item_rank;
+  const uint32_t *part_base;
+  uint32_t parts;
   uint64_t *state;            // [items] single-pass scan words (see enqueue_serve_dev)
   uint32_t *err;              // set to 1 by the single-pass kernel on a failed look-back or overflow
   uint32_t items, nq, ntiles;
@@ -189,6 +195,8 @@ struct s4_index {
   uint64_t universe = 0, bitmap_lists = 0, bitmap_bytes = 0, select_bytes = 0;
   uint32_t gap = 0;         // hyb+m2 parameter B (0: no bitmaps)
   uint32_t feat = 0;        // kinds of list held: bitmap 1, patched 2 (chunk-kernel instantiation)
+  uint32_t parts = 1;       // doc-ID parts: descriptor t * parts + p is part p of list t
+  std::vector<uint64_t> part_len;  // [count * parts] (parts > 1)
   std::vector<s4::DList> lists;    // host copy of the descriptors
   std::vector<uint64_t> lengths, pw, data_bytes;
   std::vector<uint32_t> flags;

@@ -240,6 +240,7 @@ __device__ __forceinline__ void patch_row(const DList &L, uint32_t k, bool activ
 // that work with neither pays nothing for them (registers, branches).
 constexpr uint32_t kFeatBitmap = 1;   // hybrid-index bitmap lists
 constexpr uint32_t kFeatPatched = 2;  // patched (S4-FastPFOR) lists
+constexpr uint32_t kFeatParts = 4;    // doc-ID partitioned index (per-part queues; batch kernel only)
 
 // Decode block k of L with one 16-lane row per block: extract, patch when
 // the list is patched (its exceptions, staged through the row's 128-word

@@ -537,6 +537,9 @@ int s4_server_create(const s4_index *index, const s4_server_config *cfg, s4_serv
   if (!index || !cfg || !out) return fail(S4_EINVAL, "null argument");
   if (!cfg->max_slots || !cfg->pool_bytes || !cfg->max_terms || cfg->max_terms > kMaxTerms + 1)
     return fail(S4_EINVAL, "server config: need max_slots, pool_bytes > 0 and 1 <= max_terms <= 33");
+  // single-pass iterations take chunks in result order; a partitioned
+  // index queues them per part
+  if (index->parts > 1) return fail(S4_EINVAL, "the server needs an index built without doc-ID parts");
   int rc = ensure_device();
   if (rc) return rc;
   s4_server *s = new (std::nothrow) s4_server;

@@ -162,3 +162,33 @@ def test_encode_rejects_unknown_form():
     with pytest.raises(s4.S4Error) as e:
         s4.encode(np.arange(10, dtype=np.uint32), 4)
     assert e.value.code == s4.EINVAL
+
+
+@pytest.mark.parametrize("parts", [1, 2, 8, 13])
+def test_partition_offsets(parts):
+    """Each part of each sorted list starts at the first value >= floor(p U / parts)."""
+    universe = 1 << 20
+    lens = np.array([0, 1, 5, 1000, 77777, 3], dtype=np.uint64)
+    kinds = np.full(lens.size, workloads.CLUSTERED, dtype=np.int32)
+    flat, offs = workloads.lists(kinds, lens, 31, universe)
+    sub = s4.partition_offsets(flat, offs, parts, universe)
+    assert sub.size == lens.size * parts + 1 and sub[-1] == offs[-1]
+    for t in range(lens.size):
+        a, b = int(offs[t]), int(offs[t + 1])
+        edges = [p * universe // parts for p in range(parts)]
+        want = a + np.searchsorted(flat[a:b], np.array(edges, dtype=np.uint64), side="left")
+        assert np.array_equal(sub[t * parts: t * parts + parts], want)
+        for p in range(parts):
+            part = flat[int(sub[t * parts + p]): int(sub[t * parts + p + 1])]
+            lo, hi = p * universe // parts, (p + 1) * universe // parts
+            assert part.size == 0 or (part[0] >= lo and part[-1] < hi)
+
+
+def test_partition_offsets_errors():
+    flat = np.array([1, 5, 1 << 20], dtype=np.uint32)
+    offs = np.array([0, 3], dtype=np.uint64)
+    with pytest.raises(s4.S4Error) as e:
+        s4.partition_offsets(flat, offs, 4, 1 << 20)  # a value reaches the universe
+    assert e.value.code == s4.EINVAL
+    with pytest.raises(s4.S4Error):
+        s4.partition_offsets(flat[:2], np.array([0, 2], np.uint64), 0, 1 << 20)
