@@ -173,10 +173,12 @@ int s4_decode_blocks_dev(const s4_list *list, uint32_t first, uint32_t count, ui
 
 /* Decode `count` lists with one kernel launch per list (the same kernel as
  * s4_decode_dev): list i into d_outs[i] (capacity caps[i], 16-byte
- * aligned).  Launches are spread over up to `nstreams` (1..8) streams
- * forked from `stream` and joined back into it before the call's work is
- * complete in `stream` order, so independent lists overlap on the device;
- * the call is capturable into a hipGraph on `stream`. */
+ * aligned).  nstreams = 1 issues every launch on `stream`; nstreams = 8
+ * spreads them over 8 streams forked from `stream` and joined back into
+ * it before the call's work is complete in `stream` order, so independent
+ * lists overlap on the device; the call is capturable into a hipGraph on
+ * `stream`.  Other stream counts return S4_EINVAL: they are switched off
+ * until a host-side crash seen while timing them is explained. */
 int s4_decode_lists_dev(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
                         uint32_t count, uint32_t nstreams, void *stream);
 
@@ -375,7 +377,8 @@ int s4_batch_autotune(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offse
  * with look-back offsets when the iteration has at most one 128-value
  * chunk per resident wave, else chunk kernel + scan + compaction), and
  * retires them.  Queries longer than slice_chunks chunks run a slice per
- * iteration (see s4_server_config).
+ * iteration (see s4_server_config), in at most two of the three contexts
+ * at a time, so one context always stays free for short queries.
  * Queries that arrive while iterations run join the next free context, so
  * up to three iterations overlap on the device.  Submission never blocks
  * on the GPU.

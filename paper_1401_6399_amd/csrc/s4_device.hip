@@ -836,9 +836,9 @@ int s4_decode_blocks_dev(const s4_list *l, uint32_t first, uint32_t count, uint3
 
 int s4_decode_lists_dev(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
                         uint32_t count, uint32_t nstreams, void *stream) {
+  if (nstreams != 1 && nstreams != kMaxStreams) return fail(S4_EINVAL, "nstreams must be 1 or 8");
   if (!count) return S4_OK;
   if (!lists || !d_outs || !caps) return fail(S4_EINVAL, "null argument");
-  if (nstreams < 1 || nstreams > kMaxStreams) return fail(S4_EINVAL, "nstreams must be in [1, 8]");
   for (uint32_t i = 0; i < count; ++i) {
     if (!lists[i] || (!d_outs[i] && lists[i]->n)) return fail(S4_EINVAL, "null list or output");
     if (caps[i] < lists[i]->n) return fail(S4_ERANGE, "cap < n for list " + std::to_string(i));

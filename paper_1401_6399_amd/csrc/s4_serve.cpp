@@ -8,15 +8,18 @@
 //      query, never a wait), handing results to the completed queue and
 //      releasing their memory reservation;
 //   2. fills a free context: first one slice of every query already running
-//      in slices, then waiting queries, oldest first, while the context's
+//      in slices (unless every other context already runs such slices, so
+//      one context always stays free for short queries), then waiting
+//      queries, oldest first, while the context's
 //      slot count, chunk memory (the output-to-input bound: at most 128
 //      survivors per 128-value chunk of the shortest list), result memory
 //      (at most the shortest list's length per query) and the iteration's
 //      chunk budget all fit.  A query of more than `slice` chunks is run a
 //      slice of its chunks per iteration (intersection distributes over a
 //      partition of the shortest list) so that it never holds the device
-//      for long while small queries wait behind it; its slices' results are
-//      joined in chunk order when the last one retires;
+//      for long while small queries wait behind it; when the last slice
+//      retires its slices' results are handed over in chunk order and
+//      joined by the consumer, off the dispatcher thread;
 //   3. launches the admitted queries as one batch on that context's stream:
 //      one upload of the packed query tables (which also resets the work
 //      queue), then, for an iteration of at most one chunk per resident
@@ -64,6 +67,15 @@ struct Query {
 struct Done {
   uint64_t id, count, latency_ns;
   std::vector<uint32_t> result;
+  // a query run in slices: its slices' results in chunk order, joined by
+  // the consumer (result is then empty), so the dispatcher never copies a
+  // whole large result while other queries wait for admission
+  std::vector<std::vector<uint32_t>> parts;
+  // append the result, in order, at dst
+  void copy_to(uint32_t *dst) const {
+    dst = std::copy(result.begin(), result.end(), dst);
+    for (const auto &p : parts) dst = std::copy(p.begin(), p.end(), dst);
+  }
 };
 
 // A query run in several slices (owned by the dispatcher thread).
@@ -107,6 +119,7 @@ struct Context {
   std::vector<Slice> slices;
   uint64_t items = 0, terms = 0, bound = 0;
   bool busy = false;
+  bool has_job = false;  // holds a slice of a query run in slices
   bool direct = false;  // results written to h_results by the device
   bool single = false;  // single-pass kernel
   int phase = 0;        // 1: kernels running, 2: results copy running
@@ -299,24 +312,27 @@ bool offsets_valid(const Context &c) {
 }
 
 // Move a finished context's results to the completed queue: whole queries
-// at once, slices into their job (finished jobs joined in chunk order).
+// at once, slices into their job (a finished job's slices handed over in
+// chunk order, to be joined by the consumer).
 void retire_context(s4_server *s, Context &c, const uint32_t *res) {
   const auto now = Clock::now();
   std::vector<Done> out;
   out.reserve(c.slices.size());
-  auto done_of = [&](const Query &q, std::vector<uint32_t> &&r) {
+  auto done_of = [&](const Query &q, std::vector<uint32_t> &&r, std::vector<std::vector<uint32_t>> &&parts) {
     Done d;
     d.id = q.id;
     d.count = r.size();
+    for (const auto &p : parts) d.count += p.size();
     d.latency_ns = ns_between(q.submitted, now);
     d.result = std::move(r);
+    d.parts = std::move(parts);
     out.push_back(std::move(d));
   };
   for (size_t i = 0; i < c.slices.size(); ++i) {
     Slice &sl = c.slices[i];
     const uint64_t o0 = c.h_offs[i], cnt = c.h_offs[i + 1] - o0;
     if (!sl.job) {
-      done_of(sl.q, std::vector<uint32_t>(res + o0, res + o0 + cnt));
+      done_of(sl.q, std::vector<uint32_t>(res + o0, res + o0 + cnt), {});
       continue;
     }
     Job &j = *sl.job;
@@ -324,12 +340,10 @@ void retire_context(s4_server *s, Context &c, const uint32_t *res) {
     if (--j.outstanding == 0 && j.next == j.q.items) {
       std::sort(j.parts.begin(), j.parts.end(),
                 [](const auto &a, const auto &b) { return a.first < b.first; });
-      uint64_t total = 0;
-      for (const auto &p : j.parts) total += p.second.size();
-      std::vector<uint32_t> r;
-      r.reserve(total);
-      for (const auto &p : j.parts) r.insert(r.end(), p.second.begin(), p.second.end());
-      done_of(j.q, std::move(r));
+      std::vector<std::vector<uint32_t>> parts;
+      parts.reserve(j.parts.size());
+      for (auto &p : j.parts) parts.push_back(std::move(p.second));
+      done_of(j.q, {}, std::move(parts));
       const Job *jp = &j;
       s->jobs.remove_if([jp](const Job &x) { return &x == jp; });
     }
@@ -344,6 +358,7 @@ void retire_context(s4_server *s, Context &c, const uint32_t *res) {
   s->pool_in_use -= c.reserved_stage;
   c.slices.clear();
   c.reserved_stage = 0;
+  c.has_job = false;
   c.busy = false;
   c.phase = 0;
 }
@@ -397,14 +412,21 @@ void dispatcher(s4_server *s) {
                  bound + b <= s->results_per_ctx;
         };
         auto admit = [&](Slice &&sl) {
+          c.has_job |= sl.job != nullptr;
           const uint64_t n = sl.c1 - sl.c0;
           items += n;
           terms += sl.query().k;
           bound += sl.bound();
           c.slices.push_back(std::move(sl));
         };
-        // 1. one slice of every query already running in slices
+        // 1. one slice of every query already running in slices, unless
+        //    all contexts but this one already run such slices: long
+        //    queries never take the last context, which stays free for
+        //    short ones
+        int job_contexts = 0;
+        for (const Context &o : s->ctx) job_contexts += o.busy && o.has_job;
         for (Job &j : s->jobs) {
+          if (job_contexts >= kContexts - 1) break;
           if (j.next == j.q.items) continue;
           Slice sl;
           sl.job = &j;
@@ -604,7 +626,7 @@ int s4_server_poll(s4_server *s, uint64_t *ids, uint64_t *counts, uint64_t *late
   while (n < max_done && !s->completed.empty()) {
     Done &d = s->completed.front();
     if (used + d.count > results_cap || (d.count && !results)) break;
-    std::copy(d.result.begin(), d.result.end(), results + used);
+    d.copy_to(results + used);
     ids[n] = d.id;
     counts[n] = d.count;
     latency_ns[n] = d.latency_ns;
@@ -633,6 +655,7 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
     return fail(S4_EINVAL, "null argument");
   if (results && !res_offsets) return fail(S4_EINVAL, "results need res_offsets");
   std::vector<std::vector<uint32_t>> res(results ? nq : 0);
+  std::unordered_map<uint64_t, std::vector<std::vector<uint32_t>>> res_parts;  // queries run in slices
   uint64_t ndone = 0, next = 0;
   std::unordered_map<uint64_t, uint64_t> pending;
   pending.reserve(size_t(std::min<uint64_t>(nq, 64ull * s->cfg.max_slots)));
@@ -692,7 +715,10 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
         latency_ns[q] = fin > h_arrival_ns[q] ? fin - h_arrival_ns[q] : 0;
         last_done_ns = std::max(last_done_ns, fin);
         counts[q] = d.count;
-        if (results) res[q] = std::move(d.result);
+        if (results) {
+          res[q] = std::move(d.result);
+          if (!d.parts.empty()) res_parts[q] = std::move(d.parts);
+        }
         ++ndone;
         pending.erase(it);
       }
@@ -710,9 +736,13 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
     uint64_t used = 0;
     res_offsets[0] = 0;
     for (uint64_t q = 0; q < nq; ++q) {
-      if (used + res[q].size() > results_cap) return fail(S4_ERANGE, "results_cap too small");
+      if (used + counts[q] > results_cap) return fail(S4_ERANGE, "results_cap too small");
       std::copy(res[q].begin(), res[q].end(), results + used);
-      used += res[q].size();
+      uint64_t at = used + res[q].size();
+      auto it = res_parts.find(q);
+      if (it != res_parts.end())
+        for (const auto &p : it->second) at = uint64_t(std::copy(p.begin(), p.end(), results + at) - results);
+      used += counts[q];
       res_offsets[q + 1] = used;
     }
   }

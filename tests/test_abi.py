@@ -192,3 +192,13 @@ def test_partition_offsets_errors():
     assert e.value.code == s4.EINVAL
     with pytest.raises(s4.S4Error):
         s4.partition_offsets(flat[:2], np.array([0, 2], np.uint64), 0, 1 << 20)
+
+
+def test_decode_lists_stream_count_checked_before_any_device_work():
+    """nstreams other than 1 and 8 is refused before the library touches a
+    device (an empty call still validates it)."""
+    lib = s4.require_library()
+    assert lib.s4_decode_lists_dev(None, None, None, 0, 1, None) == 0
+    assert lib.s4_decode_lists_dev(None, None, None, 0, 8, None) == 0
+    for bad in (0, 2, 3, 4, 5, 6, 7, 9):
+        assert lib.s4_decode_lists_dev(None, None, None, 0, bad, None) == s4.EINVAL, bad

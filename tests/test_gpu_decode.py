@@ -163,3 +163,104 @@ def test_decode_timed_matches_and_times(gpu):
     torch.cuda.synchronize()
     assert e0.elapsed_time(e1) > 0
     assert np.array_equal(out[: x.size].cpu().numpy().view(np.uint32), oracle.decode(enc))
+
+
+def _stream_lists(gpu):
+    """Lists of 0 .. 2^18 + 77 integers in every differential form, every
+    third one patched."""
+    rng = np.random.default_rng(31)
+    lens = [0, 1, 127, 128, 129, 4096, 70001, (1 << 18) + 77] + [int(2 ** u) for u in rng.uniform(0, 18, size=28)]
+    xs, lists = [], []
+    for i, n in enumerate(lens):
+        x = workloads.sorted_list(i % 2, 900 + i, 1 << 26, n)
+        xs.append(x)
+        lists.append(gpu.DeviceList.upload(gpu.encode(x, i % 4, patched=(i % 3 == 0))))
+    return xs, lists
+
+
+@pytest.mark.parametrize("nstreams", [1, 8])
+def test_decode_lists_streams_and_graph(gpu, nstreams):
+    """One launch per list over forked streams: every list decoded exactly,
+    nothing written outside [0, n) of its output, eagerly and in each of
+    three replays of a captured graph with host checks and refills between
+    them."""
+    import torch
+    xs, lists = _stream_lists(gpu)
+    log(f"decode_lists nstreams={nstreams}: {len(lists)} lists, {sum(x.size for x in xs)} integers")
+    pos, p = [], 0
+    for x in xs:
+        pos.append(p)
+        p += (x.size + 63) // 64 * 64 + 64
+    buf = torch.empty(p, dtype=torch.int32, device="cuda")
+    outs = [buf[q: q + x.size + 4] for q, x in zip(pos, xs)]
+    sentinel = -0x5A5A5A5B
+
+    def check(tag):
+        host = buf.cpu().numpy().view(np.uint32)
+        mask = np.ones(host.size, dtype=bool)
+        for i, x in enumerate(xs):
+            assert np.array_equal(host[pos[i]: pos[i] + x.size], x), (tag, i)
+            mask[pos[i]: pos[i] + x.size] = False
+        assert np.all(host[mask] == np.uint32(sentinel & 0xFFFFFFFF)), tag
+
+    buf.fill_(sentinel)
+    gpu.decode_lists(lists, outs, nstreams=nstreams)
+    torch.cuda.synchronize()
+    check("eager")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        gpu.decode_lists(lists, outs, nstreams=nstreams)
+    torch.cuda.synchronize()
+    for r in range(3):
+        buf.fill_(sentinel)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            g.replay()
+        torch.cuda.synchronize()
+        check(f"replay {r}")
+
+
+def test_decode_lists_bulk_workload_graph(gpu):
+    """The bulk workload at full size exactly as the benchmark times it: one
+    launch per list over 8 forked streams, captured once and replayed; every
+    value of every replay compared with the generated lists."""
+    import torch
+    flat, offs, kinds = workloads.bulk_lists()
+    buf, soffs = gpu.encode_many(flat, offs)
+    lists = [gpu.DeviceList.upload(buf[int(soffs[i]): int(soffs[i + 1])]) for i in range(len(offs) - 1)]
+    out = torch.empty(int(offs[-1]) + 128 * len(lists), dtype=torch.int32, device="cuda")
+    outs, pos, p = [], [], 0
+    for l in lists:
+        outs.append(out[p: p + l.n + 4])
+        pos.append(p)
+        p += (l.n + 63) // 64 * 64 + 64
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        gpu.decode_lists(lists, outs, nstreams=8)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        gpu.decode_lists(lists, outs, nstreams=8)
+    for r in range(2):
+        out.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            g.replay()
+        torch.cuda.synchronize()
+        host = out.cpu().numpy().view(np.uint32)
+        log(f"bulk graph replay {r} copied back")
+        for i, l in enumerate(lists):
+            assert np.array_equal(host[pos[i]: pos[i] + l.n], flat[int(offs[i]): int(offs[i + 1])]), (r, i)
+
+
+def test_decode_lists_rejects_other_stream_counts(gpu):
+    xs, lists = _stream_lists(gpu)
+    import torch
+    outs = [torch.empty(x.size + 4, dtype=torch.int32, device="cuda") for x in xs]
+    for bad in (0, 2, 4, 9):
+        with pytest.raises(gpu.S4Error) as e:
+            gpu.decode_lists(lists, outs, nstreams=bad)
+        assert e.value.code == gpu.EINVAL

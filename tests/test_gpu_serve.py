@@ -177,6 +177,35 @@ def test_sliced_queries_match_oracle(gpu, served, slice_chunks):
     assert st["completed"] == 500
 
 
+def test_sliced_queries_through_poll(gpu, served):
+    """Long queries submitted one by one and drained through s4_server_poll
+    a few at a time: the slices' results, handed over in chunk order and
+    joined by the poll into the caller's buffer, equal the oracle's."""
+    ix, flat, offs = served
+    terms, qoffs = workloads.queries(77, ix.lengths, 300, 1, 6)
+    srv = gpu.Server(ix, max_slots=256, pool_bytes=256 << 20, result_bytes=64 << 20, slice_chunks=5)
+    try:
+        ids = {}
+        for q in range(300):
+            qid = None
+            while qid is None:
+                qid = srv.submit(terms[int(qoffs[q]): int(qoffs[q + 1])])
+            ids[qid] = q
+        got = {}
+        t0 = time.time()
+        while len(got) < 300:
+            for qid, res, lat in srv.poll(max_done=7, results_cap=1 << 19):
+                got[qid] = res
+            assert time.time() - t0 < 60, f"{len(got)} of 300 results"
+            time.sleep(0.0005)
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["sliced_queries"] > 0
+    for qid, q in ids.items():
+        assert np.array_equal(got[qid], want(flat, offs, terms[int(qoffs[q]): int(qoffs[q + 1])])), q
+
+
 def test_replay_open_loop(gpu, served):
     ix, flat, offs = served
     nq = 2000
