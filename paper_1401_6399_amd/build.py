@@ -16,6 +16,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     # packed fp32 instructions stay off in every device compilation
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # kernel arguments preloaded into scalar registers at wave launch (the
+    # leading 14 dwords; kernels put what a wave needs first there)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-result",
     f"-I{os.path.join(ROOT, 'include')}",
 ]

@@ -58,14 +58,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_batch_chunks(BatchDev b, uint32_
         const uint4 info = b.item_info[item];
         const uint32_t q = uniform(info.x), local = uniform(info.y), tq = uniform(info.z), k = uniform(info.w);
         // the two shortest lists' descriptors, loaded together up front
-        const uint32_t id0 = b.sterms[tq], id1 = b.sterms[tq + (k > 1 ? 1 : 0)];
+        const uint32_t id0 = uniform(b.sterms[tq]), id1 = uniform(b.sterms[tq + (k > 1 ? 1 : 0)]);
         RSide r;
-        r.L = b.lists[id0];
-        const DList f1 = b.lists[id1];
+        r.L = cst(b.lists)[id0];
+        const DList f1 = cst(b.lists)[id1];
         r.raw = nullptr;
         r.len = r.L.n;
         const uint32_t cnt = chain_chunk<FEAT>(
-            r, local, [&](uint32_t j) -> DList { return j == 0 ? f1 : b.lists[b.sterms[tq + 1 + j]]; }, k - 1,
+            r, local, f1, [&](uint32_t j) -> DList { return cst(b.lists)[uniform(b.sterms[tq + 1 + j])]; }, k - 1,
             lds[w], gallop_blocks, tr);
         const uint32_t slot = (FEAT & kFeatParts) ? b.item_rank[item] : item;
         store_chunk(cnt, lds[w], b.stage + uint64_t(slot) * kBlock, b.counts + slot);
@@ -180,14 +180,14 @@ __global__ __launch_bounds__(WAVES * 64) void k_serve_chunks(BatchDev b, uint32_
     for (uint32_t item = it0; item < it1; ++item) {
       const uint4 info = b.item_info[item];
       const uint32_t q = uniform(info.x), local = uniform(info.y), tq = uniform(info.z), k = uniform(info.w);
-      const uint32_t id0 = b.sterms[tq], id1 = b.sterms[tq + (k > 1 ? 1 : 0)];
+      const uint32_t id0 = uniform(b.sterms[tq]), id1 = uniform(b.sterms[tq + (k > 1 ? 1 : 0)]);
       RSide r;
-      r.L = b.lists[id0];
-      const DList f1 = b.lists[id1];
+      r.L = cst(b.lists)[id0];
+      const DList f1 = cst(b.lists)[id1];
       r.raw = nullptr;
       r.len = r.L.n;
       const uint32_t cnt = chain_chunk<FEAT>(
-          r, local, [&](uint32_t j) -> DList { return j == 0 ? f1 : b.lists[b.sterms[tq + 1 + j]]; }, k - 1,
+          r, local, f1, [&](uint32_t j) -> DList { return cst(b.lists)[uniform(b.sterms[tq + 1 + j])]; }, k - 1,
           lds[w], gallop_blocks, tr);
       bool ok = true;
       const uint32_t excl = lookback(b.state, item, b.epoch, cnt, b.err, ok);

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_block_sums(const DList *__restrict__ li
     k = uint32_t(g - blk_prefix[lo]);
     mode = L.mode;
     patched = is_patched(L);
-    extract_row(L.payload + L.offs[k], L.widths[k], lane & 15u, d0, d1);
+    extract_row(L.payload + gbl(L.offs)[k], gbl(L.widths)[k], lane & 15u, d0, d1);
   }
   // rows of patched lists add their exceptions before the prefix
   if (__ballot(patched))
@@ -207,21 +207,29 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
   kbase = uniform(kbase);
   const uint32_t kl = kbase + lane;
   const bool vl = lane < 4u * P && kl < full_end;
-  const uint32_t bl = vl ? uint32_t(L.widths[kl]) : 0u;
-  const uint32_t base_off = L.offs[kbase];
+  // The block offset, the seeds and the widths are independent loads: all
+  // three are issued before any is waited for.  Every lane loads an
+  // in-range width (block kbase exists) and drops it when not its own, so
+  // no branch around the load makes the others wait for it.
+  const uint32_t base_off = gbl(L.offs)[kbase];
+  const uint4 s = gbl(L.seeds)[kbase];
+  const uint32_t wraw = gbl(L.widths)[vl ? kl : kbase];
+  const uint32_t bl = vl ? wraw : 0u;
   const uint32_t wl = 4u * bl;
   const uint32_t ol = base_off + scan_wave64(wl) - wl;
-  const uint4 s = L.seeds[kbase];
   uint32_t c[4] = {s.x, s.y, s.z, s.w};
   uint32_t d0[P][4], d1[P][4];
+  // Rows past the range's last block read that last block instead: every
+  // row's loads are then unconditional and all 4 P rows are in flight at
+  // once.  Their values only reach rows and carries after the range, which
+  // are never stored.
+  const uint32_t last = full_end - 1u - kbase;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    const uint32_t src = 4u * p + row;
+    const uint32_t src = min(4u * p + row, last);
     const uint32_t b = uint32_t(__shfl(int(bl), int(src)));
     const uint32_t off = uint32_t(__shfl(int(ol), int(src)));
-#pragma unroll
-    for (int j = 0; j < 4; ++j) d0[p][j] = d1[p][j] = 0;
-    if (kbase + src < full_end) extract_row(L.payload + off, b, i, d0[p], d1[p]);
+    extract_row(L.payload + off, b, i, d0[p], d1[p]);
   }
 #pragma unroll
   for (int p = 0; p < P; ++p) {
@@ -268,25 +276,45 @@ __device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint
 
 __device__ __forceinline__ void copy_tail(const DList &L, uint32_t *__restrict__ dst) {
   const uint32_t lane = lane_id();
-  if (lane < L.t) dst[lane] = L.tail[lane];
-  if (lane + 64 < L.t) dst[lane + 64] = L.tail[lane + 64];
+  if (lane < L.t) gbl_out(dst)[lane] = gbl(L.tail)[lane];
+  if (lane + 64 < L.t) gbl_out(dst)[lane + 64] = gbl(L.tail)[lane + 64];
 }
 
-// Bulk decode of blocks [first, first + count) of L (index nb = raw tail):
-// waves [0, block_waves) decode 4 passes-worth of blocks each, the next
-// wave copies the tail when the range covers it.
+// Bulk decode of blocks [first, full_end) of one list, then its raw tail
+// when `form` has kDecodeTail (the range then ends at the last full block,
+// so the tail goes right after it): waves [0, block_waves) decode 4
+// passes-worth of blocks each, wave block_waves copies the tail.  The list
+// comes as scalar arguments, those a wave needs first leading, so that they
+// arrive preloaded in scalar registers and a wave's first loads do not wait
+// for an argument fetch; the tail pointer and nb (needed by the tail wave
+// and by patched lists only) follow.  form = differential form |
+// kDecodePatched if patched | kDecodeTail | t << 16.
+constexpr uint32_t kDecodePatched = 1u << 8, kDecodeTail = 1u << 9;
 template <int P>
-__global__ __launch_bounds__(256) void k_decode(DList L, uint32_t first, uint32_t count, uint32_t block_waves,
-                                                uint32_t *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_decode(const uint8_t *widths, const uint32_t *offs, const uint4 *seeds,
+                                                const uint32_t *payload, uint32_t *__restrict__ out, uint32_t first,
+                                                uint32_t full_end, uint32_t block_waves, uint32_t form,
+                                                const uint32_t *tail, uint32_t nb) {
   __shared__ __align__(16) uint32_t stage[4][kPassWords];
+  DList L;
+  L.widths = widths;
+  L.offs = offs;
+  L.payload = payload;
+  L.bmax = nullptr;
+  L.seeds = seeds;
+  L.tail = tail;
+  L.n = 0;  // not used by the decode
+  L.nb = nb;
+  L.t = form >> 16;
+  L.mode = form & 0xffu;
+  L.aux = (form & kDecodePatched) ? 1u : 0u;
   const uint32_t w = threadIdx.x >> 6;
-  const uint32_t wave = blockIdx.x * (blockDim.x >> 6) + w;
-  const uint32_t end = first + count;
+  const uint32_t wave = blockIdx.x * 4u + w;  // always launched with 4 waves per group
   if (wave >= block_waves) {
-    if (wave == block_waves && end > L.nb && L.t > 0) copy_tail(L, out + uint64_t(L.nb - first) * kBlock);
+    if (wave == block_waves && (form & kDecodeTail)) copy_tail(L, out + uint64_t(full_end - first) * kBlock);
     return;
   }
-  decode_wave<P>(L, first, min(end, L.nb), first + wave * 4u * P, out, stage[w]);
+  decode_wave<P>(L, first, full_end, first + wave * 4u * P, out, stage[w]);
 }
 
 // Multi-list decode in one launch: wave w decodes for list wave_list[w];
@@ -303,9 +331,9 @@ __global__ __launch_bounds__(256) void k_decode_multi(const DList *__restrict__ 
   const uint32_t wave = uniform(blockIdx.x * (blockDim.x >> 6) + w);
   if (wave >= waves) return;
   const uint32_t l = uniform(wave_list[wave]);
-  const DList L = lists[l];
-  uint32_t *out = outs[l];
-  const uint32_t local = wave - wave_prefix[l];
+  const DList L = cst(lists)[l];
+  uint32_t *out = cst(outs)[l];
+  const uint32_t local = wave - cst(wave_prefix)[l];
   const uint32_t block_waves = (L.nb + 4 * P - 1) / (4 * P);
   if (local >= block_waves) {
     copy_tail(L, out + uint64_t(L.nb) * kBlock);
@@ -349,8 +377,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_chain(DList rl, const uint32_t *
     return;
   }
   Traffic tr;
-  const uint32_t cnt = chain_chunk<FEAT>(r, item, [&](uint32_t j) -> const DList & { return args.f[j]; }, args.nf,
-                                   lds[w], gallop_blocks, tr);
+  const uint32_t cnt = chain_chunk<FEAT>(r, item, args.f[0], [&](uint32_t j) -> const DList & { return args.f[j]; },
+                                         args.nf, lds[w], gallop_blocks, tr);
   store_chunk(cnt, lds[w], stage + uint64_t(item) * kBlock, counts + item);
 }
 
@@ -671,13 +699,14 @@ static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len
 }
 
 template <int P>
-static void launch_decode(const DList &L, uint32_t first, uint32_t count, uint32_t block_waves, uint32_t waves,
-                          uint32_t *d_out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+static void launch_decode(const DList &L, uint32_t first, uint32_t full_end, uint32_t block_waves, uint32_t waves,
+                          uint32_t form, uint32_t *d_out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0)
-    hipExtLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, ev0, ev1, 0, L, first, count,
-                          block_waves, d_out);
+    hipExtLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, ev0, ev1, 0, L.widths, L.offs,
+                          L.seeds, L.payload, d_out, first, full_end, block_waves, form, L.tail, L.nb);
   else
-    hipLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, L, first, count, block_waves, d_out);
+    hipLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, L.widths, L.offs, L.seeds,
+                       L.payload, d_out, first, full_end, block_waves, form, L.tail, L.nb);
 }
 
 int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream) {
@@ -696,11 +725,13 @@ int decode_range_timed(const DList &L, uint32_t first, uint32_t count, uint32_t 
   const bool tail = end > L.nb && L.t > 0;
   const uint32_t waves = block_waves + (tail ? 1 : 0);
   if (waves == 0) return S4_OK;
+  const uint32_t full_end = first + full;
+  const uint32_t form = L.mode | (is_patched(L) ? kDecodePatched : 0u) | (tail ? kDecodeTail : 0u) | (L.t << 16);
   switch (P) {
-    case 8: launch_decode<8>(L, first, count, block_waves, waves, d_out, stream, ev0, ev1); break;
-    case 4: launch_decode<4>(L, first, count, block_waves, waves, d_out, stream, ev0, ev1); break;
-    case 2: launch_decode<2>(L, first, count, block_waves, waves, d_out, stream, ev0, ev1); break;
-    default: launch_decode<1>(L, first, count, block_waves, waves, d_out, stream, ev0, ev1); break;
+    case 8: launch_decode<8>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1); break;
+    case 4: launch_decode<4>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1); break;
+    case 2: launch_decode<2>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1); break;
+    default: launch_decode<1>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1); break;
   }
   S4_HIP(hipGetLastError());
   return S4_OK;

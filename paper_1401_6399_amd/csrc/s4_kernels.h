@@ -63,6 +63,39 @@ __device__ __forceinline__ uint32_t scan_wave64(uint32_t v) {
   return v;
 }
 
+// Global-memory views of device pointers.  Lists, tables and outputs live
+// in global memory, but pointers read from descriptor tables reach the
+// compiler as generic ones, whose loads and stores become flat accesses that
+// count against the LDS wait counter too, so every wait for memory would
+// also hold LDS work back and the other way round.  Accesses through these
+// views are global ones.
+// (The qualifiers apply in the device compilation; the host pass, which
+// emits no device code, sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define S4_ADDRSPACE(n) __attribute__((address_space(n)))
+#else
+#define S4_ADDRSPACE(n)
+#endif
+template <class T>
+using gconst = const S4_ADDRSPACE(1) T *;
+template <class T>
+using gmut = S4_ADDRSPACE(1) T *;
+template <class T>
+__device__ __forceinline__ gconst<T> gbl(const T *p) {
+  return (gconst<T>)p;
+}
+template <class T>
+__device__ __forceinline__ gmut<T> gbl_out(T *p) {
+  return (gmut<T>)p;
+}
+// Read-only view of a table that no kernel writes while it runs (list
+// descriptors): uniform loads through it go through the scalar cache into
+// scalar registers.
+template <class T>
+__device__ __forceinline__ const S4_ADDRSPACE(4) T *cst(const T *p) {
+  return (const S4_ADDRSPACE(4) T *)p;
+}
+
 // Streaming 16-byte store that does not keep the line in cache.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void store_nt4(uint32_t *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
@@ -70,14 +103,14 @@ __device__ __forceinline__ void store_nt4(uint32_t *p, uint32_t a, uint32_t b, u
 #ifdef S4_PLAIN_STORES
   *reinterpret_cast<u32x4 *>(p) = v;
 #else
-  __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+  __builtin_nontemporal_store(v, gbl_out(reinterpret_cast<u32x4 *>(p)));
 #endif
 }
 
 // 16-byte store of decoded output (plain; whole lines per instruction).
 __device__ __forceinline__ void store4(uint32_t *p, u32x4 v) {
 #ifndef S4_PLAIN_STORES
-  __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+  __builtin_nontemporal_store(v, gbl_out(reinterpret_cast<u32x4 *>(p)));
 #else
   *reinterpret_cast<u32x4 *>(p) = v;
 #endif
@@ -103,7 +136,7 @@ __device__ __forceinline__ void extract_row(const uint32_t *__restrict__ blk, ui
   const uint32_t bit1 = bit0 + b;
   const uint32_t s1 = bit1 & 31u;
   const bool step = (bit1 >> 5) != m0;
-  const uint4 *p = reinterpret_cast<const uint4 *>(blk) + m0;
+  const gconst<uint4> p = gbl(reinterpret_cast<const uint4 *>(blk)) + m0;
   const uint4 r0 = p[0], r1 = p[1], r2 = p[2];
   const uint32_t mask = width_mask(b);
   d0[0] = funnel(r1.x, r0.x, s0) & mask;
@@ -172,11 +205,14 @@ __device__ __forceinline__ void prefix_form(const uint32_t d0[4], const uint32_t
       x1[j] = y1 + d1[j];
     }
   } else {
+    // x0 before x1, as in the other forms: with one store order in every
+    // form the compiler merges the forms' stores without taking the
+    // arrays' addresses (which would put them in scratch memory)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const uint32_t sc = scan(d0[j] + d1[j]);
-      x1[j] = seed[j] + sc;
-      x0[j] = x1[j] - d1[j];
+      const uint32_t hi = seed[j] + scan(d0[j] + d1[j]);
+      x0[j] = hi - d1[j];
+      x1[j] = hi;
     }
   }
 }
@@ -200,11 +236,11 @@ __device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4
 // index, above the b' low bits unpacked at its position.  Exceptions of a
 // block sit at distinct positions, so the adds never collide.
 __device__ __forceinline__ void patch_block(const DList &L, uint32_t k, uint32_t i, uint32_t *v) {
-  const uint4 x = exc_records(L)[k];
+  const uint4 x = gbl(exc_records(L))[k];
   const uint32_t c = x.x & 0xFFu, d = (x.x >> 8) & 0x3Fu, bp = (x.x >> 16) & 0x3Fu;
   const uint32_t *xd = exc_data(L);
-  const uint8_t *pos = reinterpret_cast<const uint8_t *>(xd) + x.y;
-  const uint32_t *arr = xd + x.z;
+  const gconst<uint8_t> pos = gbl(reinterpret_cast<const uint8_t *>(xd)) + x.y;
+  const gconst<uint32_t> arr = gbl(xd) + x.z;
   for (uint32_t e = i; e < c; e += 16) {
     const uint32_t bit = (x.w + e) * d;
     const uint32_t w = bit >> 5, s = bit & 31u;
@@ -254,8 +290,8 @@ __device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool acti
   uint32_t d0[4] = {0, 0, 0, 0}, d1[4] = {0, 0, 0, 0};
   uint4 seed = make_uint4(0, 0, 0, 0);
   if (active) {
-    extract_row(L.payload + L.offs[k], L.widths[k], i, d0, d1);
-    seed = L.seeds[k];
+    extract_row(L.payload + gbl(L.offs)[k], gbl(L.widths)[k], i, d0, d1);
+    seed = gbl(L.seeds)[k];
   }
   if (PATCHED && is_patched(L)) patch_row(L, k, active, i, scratch, d0, d1);
   const uint32_t sv[4] = {seed.x, seed.y, seed.z, seed.w};
@@ -268,24 +304,25 @@ __device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool acti
 __device__ __forceinline__ void decode_block_wave(const DList &L, uint32_t k, uint32_t *dst) {
   const uint32_t l = lane_id();
   const uint32_t q = l & 31u, j0 = (l >> 5) * 2u;
-  const uint32_t b = L.widths[k];
-  const uint32_t *w = L.payload + L.offs[k];
+  const uint32_t b = gbl(L.widths)[k];
+  const uint32_t *w = L.payload + gbl(L.offs)[k];
   const uint32_t bit = q * b, m = bit >> 5, s = bit & 31u;
-  const uint2 lo = *reinterpret_cast<const uint2 *>(w + 4u * m + j0);
-  const uint2 hi = *reinterpret_cast<const uint2 *>(w + 4u * m + 4u + j0);
+  const uint2 lo = *gbl(reinterpret_cast<const uint2 *>(w + 4u * m + j0));
+  const uint2 hi = *gbl(reinterpret_cast<const uint2 *>(w + 4u * m + 4u + j0));
   const uint32_t mask = width_mask(b);
   const uint32_t d0 = funnel(hi.x, lo.x, s) & mask;
   const uint32_t d1 = funnel(hi.y, lo.y, s) & mask;
-  const uint4 seed = L.seeds[k];
+  const uint4 seed = gbl(L.seeds)[k];
   const uint32_t s0 = j0 ? seed.z : seed.x, s1 = j0 ? seed.w : seed.y;
   const uint32_t x0 = s0 + scan_half32(d0);
   const uint32_t x1 = s1 + scan_half32(d1);
   *reinterpret_cast<uint2 *>(dst + 4u * q + j0) = make_uint2(x0, x1);
 }
 
-// First index c in [lo, hi) with v[c] >= key, else hi.
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__ v, uint32_t lo, uint32_t hi,
-                                                    uint32_t key) {
+// First index c in [lo, hi) with v[c] >= key, else hi (v: an LDS array or a
+// global view).
+template <class Ptr>
+__device__ __forceinline__ uint32_t lower_bound_u32(Ptr v, uint32_t lo, uint32_t hi, uint32_t key) {
   uint32_t len = hi - lo;
   while (len > 0) {
     const uint32_t half = len >> 1;
@@ -306,8 +343,8 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t *__restrict__
 // piece between the last entry below the key and the first one not below,
 // so a range of n entries takes about log_32 n rounds of loads instead of
 // log_2 n dependent ones.  All 64 lanes call this; the results are uniform.
-__device__ __forceinline__ void coop_lower_bound2(const uint32_t *__restrict__ v, uint32_t n, uint32_t key0,
-                                                  uint32_t key1, uint32_t &r0, uint32_t &r1) {
+__device__ __forceinline__ void coop_lower_bound2(gconst<uint32_t> v, uint32_t n, uint32_t key0, uint32_t key1,
+                                                  uint32_t &r0, uint32_t &r1) {
   const uint32_t lane = lane_id();
   const bool upper = lane >= 32;
   const uint32_t sub = lane & 31u;
@@ -376,12 +413,12 @@ __device__ __forceinline__ uint32_t load_bitmap_chunk(const DList &L, uint32_t i
   const uint32_t want = L.n > base ? uint32_t(min<uint64_t>(kBlock, L.n - base)) : 0u;
   uint32_t got = 0;
   if (want) {
-    const uint32_t first = uniform(L.bmax[item]);
+    const uint32_t first = uniform(gbl(L.bmax)[item]);
     const uint32_t w0 = first >> 5;
     tr.bytes += 4u;
     for (uint32_t w = w0; got < want && w < L.aux; w += 64) {
       const uint32_t wi = w + lane;
-      uint32_t word = wi < L.aux ? L.payload[wi] : 0u;
+      uint32_t word = wi < L.aux ? gbl(L.payload)[wi] : 0u;
       if (wi == w0) word &= ~((1u << (first & 31u)) - 1u);  // bits of earlier chunks
       tr.bytes += 4u * min(64u, L.aux - w);
       const uint32_t pc = uint32_t(__popc(word));
@@ -408,13 +445,13 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     const uint64_t base = uint64_t(item) * kBlock;
     const uint64_t left = r.len > base ? r.len - base : 0;
     cnt = left < kBlock ? uint32_t(left) : kBlock;
-    if (lane < cnt) s.r[lane] = r.raw[base + lane];
-    if (lane + 64 < cnt) s.r[lane + 64] = r.raw[base + 64 + lane];
+    if (lane < cnt) s.r[lane] = gbl(r.raw)[base + lane];
+    if (lane + 64 < cnt) s.r[lane + 64] = gbl(r.raw)[base + 64 + lane];
   } else if ((FEAT & kFeatBitmap) && r.L.mode == kBitmapList) {
     return load_bitmap_chunk(r.L, item, s, tr);
   } else if (item < r.L.nb) {
     cnt = kBlock;
-    tr.bytes += 16u * uniform(r.L.widths[item]) + 1u + 4u + 16u;
+    tr.bytes += 16u * uniform(gbl(r.L.widths)[item]) + 1u + 4u + 16u;
     tr.blocks += 1;
     if (r.L.mode == S4_DELTA_D4 && !((FEAT & kFeatPatched) && is_patched(r.L))) {
       decode_block_wave(r.L, item, s.r);
@@ -431,8 +468,8 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     }
   } else {
     cnt = item == r.L.nb ? r.L.t : 0u;
-    if (lane < cnt) s.r[lane] = r.L.tail[lane];
-    if (lane + 64 < cnt) s.r[lane + 64] = r.L.tail[lane + 64];
+    if (lane < cnt) s.r[lane] = gbl(r.L.tail)[lane];
+    if (lane + 64 < cnt) s.r[lane + 64] = gbl(r.L.tail)[lane + 64];
   }
   if (r.raw || item >= r.L.nb) tr.bytes += 4u * cnt;
   wave_sync();
@@ -473,9 +510,9 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
   // (index nb stands for the raw tail, bmax taken as +infinity there); the
   // two are independent, so their loads overlap
   uint32_t fmax = 0;
-  if (f.n > 0) fmax = ftail ? f.tail[f.t - 1] : f.bmax[nbf - 1];
+  if (f.n > 0) fmax = ftail ? gbl(f.tail)[f.t - 1] : gbl(f.bmax)[nbf - 1];
   uint32_t lo = 0, hi = 0;
-  if (cnt > 0) coop_lower_bound2(f.bmax, nbf, first, last, lo, hi);
+  if (cnt > 0) coop_lower_bound2(gbl(f.bmax), nbf, first, last, lo, hi);
   const bool any = cnt > 0 && f.n > 0 && first <= fmax;
   bool f0 = false, f1 = false;
   if (any) {
@@ -483,15 +520,15 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
     uint32_t c0, c1;
     if (span <= gallop_blocks) {
       // merge regime: stage the spanned bmax entries in LDS, search there
-      for (uint32_t e = lane; e < span; e += 64) s.bm[e] = (lo + e < nbf) ? f.bmax[lo + e] : kInvalid;
+      for (uint32_t e = lane; e < span; e += 64) s.bm[e] = (lo + e < nbf) ? gbl(f.bmax)[lo + e] : kInvalid;
       tr.bytes += 4u * span;
       wave_sync();
       c0 = lo + lower_bound_u32(s.bm, 0, span - 1, a0);
       c1 = lo + lower_bound_u32(s.bm, 0, span - 1, a1);
     } else {
       // galloping regime: each lane searches the skip index in memory
-      c0 = lower_bound_u32(f.bmax, lo, hi, a0);
-      c1 = lower_bound_u32(f.bmax, lo, hi, a1);
+      c0 = lower_bound_u32(gbl(f.bmax), lo, hi, a0);
+      c1 = lower_bound_u32(gbl(f.bmax), lo, hi, a1);
     }
     const bool ok0 = v0 && a0 <= fmax;
     const bool ok1 = v1 && a1 <= fmax;
@@ -517,7 +554,7 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
       const uint32_t blk = cs < U ? s.cand[cs] : kInvalid;
       // traffic of the four rows' blocks, summed from each row's first lane
       uint32_t tb = 0;
-      if (ri == 0) tb = blk < nbf ? 16u * f.widths[blk] + 21u : (blk == nbf ? 4u * f.t : 0u);
+      if (ri == 0) tb = blk < nbf ? 16u * gbl(f.widths)[blk] + 21u : (blk == nbf ? 4u * f.t : 0u);
       tr.bytes += uint32_t(__builtin_amdgcn_readlane(int(tb), 0)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 16)) +
                   uint32_t(__builtin_amdgcn_readlane(int(tb), 32)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 48));
       tr.blocks += min(4u, U - g);
@@ -528,7 +565,7 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
         *reinterpret_cast<uint4 *>(&s.f[row][8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
       } else if (blk == nbf) {
         for (uint32_t e = 0; e < 8; ++e)
-          if (8 * ri + e < f.t) s.f[row][8 * ri + e] = f.tail[8 * ri + e];
+          if (8 * ri + e < f.t) s.f[row][8 * ri + e] = gbl(f.tail)[8 * ri + e];
       }
       wave_sync();
       if (slot0 - g < 4u) {
@@ -558,8 +595,8 @@ __device__ __forceinline__ uint32_t probe_chunk(uint32_t cnt, const DList &f, It
   const uint32_t a0 = v0 ? s.r[lane] : 0u;
   const uint32_t a1 = v1 ? s.r[lane + 64] : 0u;
   bool f0 = false, f1 = false;
-  if (v0 && (a0 >> 5) < f.aux) f0 = (f.payload[a0 >> 5] >> (a0 & 31u)) & 1u;
-  if (v1 && (a1 >> 5) < f.aux) f1 = (f.payload[a1 >> 5] >> (a1 & 31u)) & 1u;
+  if (v0 && (a0 >> 5) < f.aux) f0 = (gbl(f.payload)[a0 >> 5] >> (a0 & 31u)) & 1u;
+  if (v1 && (a1 >> 5) < f.aux) f1 = (gbl(f.payload)[a1 >> 5] >> (a1 & 31u)) & 1u;
   tr.bytes += 4u * cnt;
   return compact_chunk(f0, f1, a0, a1, s);
 }
@@ -568,9 +605,9 @@ __device__ __forceinline__ uint32_t probe_chunk(uint32_t cnt, const DList &f, It
 __device__ __forceinline__ void store_chunk(uint32_t cnt, const ItemLds &s, uint32_t *__restrict__ out,
                                             uint32_t *__restrict__ count) {
   const uint32_t lane = lane_id();
-  if (lane < cnt) out[lane] = s.r[lane];
-  if (lane + 64 < cnt) out[lane + 64] = s.r[lane + 64];
-  if (lane == 0) *count = cnt;
+  if (lane < cnt) gbl_out(out)[lane] = s.r[lane];
+  if (lane + 64 < cnt) gbl_out(out)[lane + 64] = s.r[lane + 64];
+  if (lane == 0) *gbl_out(count) = cnt;
 }
 
 // SvS over one chunk: intersect chunk `item` of r with lists f[0 .. nf) in
@@ -578,11 +615,14 @@ __device__ __forceinline__ void store_chunk(uint32_t cnt, const ItemLds &s, uint
 // shortest list up).  Intersection distributes over a partition of the
 // shortest list, so chunks are independent.
 template <uint32_t FEAT, class FList>
-__device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, FList f, uint32_t nf, ItemLds &s,
-                                                uint32_t gallop_blocks, Traffic &tr) {
+__device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, const DList &f0, FList f, uint32_t nf,
+                                                ItemLds &s, uint32_t gallop_blocks, Traffic &tr) {
   uint32_t cnt = load_chunk<FEAT>(r, item, s, tr);
+  // f0 (the second-shortest list, j = 0) comes in already loaded; later
+  // lists are loaded as the chain reaches them
+  DList fj = f0;
   for (uint32_t j = 0; j < nf && cnt > 0; ++j) {
-    const DList fj = f(j);
+    if (j > 0) fj = f(j);
     if ((FEAT & kFeatBitmap) && fj.mode == kBitmapList)
       cnt = probe_chunk(cnt, fj, s, tr);
     else
