@@ -36,9 +36,10 @@ constexpr uint32_t kXcds = 8;
 // part's lists, then helps every other queue.
 // The chunk kernels are latency-bound, so resident waves matter most: the
 // plain instantiation is held to 64 VGPRs (8 waves per SIMD, whose LDS,
-// 5 KB per wave, then just fills a CU), which it fits without spilling.
+// 5 KB per wave, then just fills a CU) and the others to 80 (6 waves), all
+// without spilling.
 template <int WAVES, uint32_t FEAT>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT == 0 ? 8 : 1))) void k_batch_chunks(
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT == 0 ? 8 : 6))) void k_batch_chunks(
     BatchDev b, uint32_t grab, uint32_t gallop_blocks) {
   __shared__ ItemLds lds[WAVES];
   const uint32_t w = threadIdx.x >> 6;
@@ -168,7 +169,7 @@ __device__ uint32_t lookback(uint64_t *__restrict__ state, uint32_t item, uint32
 // those of any chunkless entries just before it; the last chunk closes the
 // table).  No staging, no per-query stamps.
 template <int WAVES, uint32_t FEAT>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT == 0 ? 8 : 1))) void k_serve_chunks(
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT == 0 ? 8 : 6))) void k_serve_chunks(
     BatchDev b, uint32_t grab, uint32_t gallop_blocks, uint32_t *__restrict__ out, uint64_t out_cap,
     uint64_t *__restrict__ offs) {
   __shared__ ItemLds lds[WAVES];

@@ -198,7 +198,7 @@ constexpr uint32_t kPassWords = 4u * kBlock;
 //     values 4l .. 4l + 3 of each half): whole cache lines per instruction.
 //  (Patched lists, PATCHED: before its prefix each pass's deltas go through
 //  the same LDS slice once, where the rows add their blocks' exceptions.)
-template <int P, uint32_t MODE, bool PATCHED>
+template <int P, uint32_t MODE, bool PATCHED, bool PIPE>
 __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
                                                  uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
   static_assert(P >= 1 && P <= 16, "4 P blocks per wave must fit 64 lanes");
@@ -218,25 +218,20 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
   const uint32_t wl = 4u * bl;
   const uint32_t ol = base_off + scan_wave64(wl) - wl;
   uint32_t c[4] = {s.x, s.y, s.z, s.w};
-  uint32_t d0[P][4], d1[P][4];
-  // Rows past the range's last block read that last block instead: every
-  // row's loads are then unconditional and all 4 P rows are in flight at
-  // once.  Their values only reach rows and carries after the range, which
-  // are never stored.
+  // Rows past the range's last block read that last block instead, so every
+  // row's loads are unconditional (their values only reach rows and carries
+  // after the range, which are never stored).
   const uint32_t last = full_end - 1u - kbase;
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const uint32_t src = min(4u * p + row, last);
-    const uint32_t b = uint32_t(__shfl(int(bl), int(src)));
-    const uint32_t off = uint32_t(__shfl(int(ol), int(src)));
-    extract_row(L.payload + off, b, i, d0[p], d1[p]);
-  }
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
+  auto width_of = [&](int p) { return uint32_t(__shfl(int(bl), int(min(4u * p + row, last)))); };
+  auto row_of = [&](int p, uint32_t b) {
+    return load_row(L.payload + uint32_t(__shfl(int(ol), int(min(4u * p + row, last)))), b, i);
+  };
+  // one pass: patch, scan (carry across passes in c), transpose, store
+  auto pass = [&](int p, uint32_t d0[4], uint32_t d1[4]) {
     const uint32_t k0 = kbase + 4u * p;
-    if (PATCHED) patch_row(L, k0 + row, k0 + row < full_end, i, tb + row * kBlock, d0[p], d1[p]);
+    if (PATCHED) patch_row(L, k0 + row, k0 + row < full_end, i, tb + row * kBlock, d0, d1);
     uint32_t x0[4], x1[4];
-    prefix_form<false, MODE>(d0[p], d1[p], c, x0, x1);
+    prefix_form<false, MODE>(d0, d1, c, x0, x1);
 #pragma unroll
     for (int j = 0; j < 4; ++j) c[j] = uint32_t(__builtin_amdgcn_readlane(int(x1[j]), 63));
     u32x4 *t = reinterpret_cast<u32x4 *>(tb + row * kBlock + 8u * i);
@@ -249,29 +244,64 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
     uint32_t *dst = out + uint64_t(k0 - first) * kBlock + 4u * lane;
     if (k0 + (lane >> 5) < full_end) store4(dst, y0);
     if (k0 + 2u + (lane >> 5) < full_end) store4(dst + 256, y1);
+  };
+  if constexpr (!PIPE) {
+    // all 4 P rows' loads in flight at once (most memory parallelism per
+    // wave, at 4 P x 8 registers of deltas)
+    uint32_t d0[P][4], d1[P][4];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const uint32_t b = width_of(p);
+      unpack_row(row_of(p, b), b, i, d0[p], d1[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) pass(p, d0[p], d1[p]);
+  } else {
+    // each pass's row loaded while the previous one is decoded: two passes
+    // in flight, few registers, more waves resident (the patched kernels,
+    // whose passes also wait on LDS, gain more from waves than from
+    // loads in flight)
+    uint32_t bcur = width_of(0), bnext = 0;
+    RowWords cur = row_of(0, bcur), next;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      if (p + 1 < P) {
+        bnext = width_of(p + 1);
+        next = row_of(p + 1, bnext);
+      }
+      uint32_t d0[4], d1[4];
+      unpack_row(cur, bcur, i, d0, d1);
+      pass(p, d0, d1);
+      if (p + 1 < P) {
+        cur = next;
+        bcur = bnext;
+      }
+    }
   }
 }
 
-// Dispatch once per wave on the list's differential form, so each variant
-// of the unrolled passes is straight-line code.
-template <int P>
+// Dispatch once per wave on the list's differential form and on patching,
+// so each variant of the unrolled passes is straight-line code.  PK: the
+// kernel is instantiated for work that may hold patched lists; it decodes
+// every list with pipelined rows (see decode_wave_form), the plain kernels
+// load all rows at once.
+template <int P, bool PATCHED, bool PIPE>
+__device__ __forceinline__ void decode_wave_as(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
+                                               uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
+  switch (uniform(L.mode)) {
+    case S4_DELTA_D1: decode_wave_form<P, S4_DELTA_D1, PATCHED, PIPE>(L, first, full_end, kbase, out, tb); break;
+    case S4_DELTA_D2: decode_wave_form<P, S4_DELTA_D2, PATCHED, PIPE>(L, first, full_end, kbase, out, tb); break;
+    case S4_DELTA_DM: decode_wave_form<P, S4_DELTA_DM, PATCHED, PIPE>(L, first, full_end, kbase, out, tb); break;
+    default: decode_wave_form<P, S4_DELTA_D4, PATCHED, PIPE>(L, first, full_end, kbase, out, tb); break;
+  }
+}
+template <int P, bool PK>
 __device__ __forceinline__ void decode_wave(const DList &L, uint32_t first, uint32_t full_end, uint32_t kbase,
                                             uint32_t *__restrict__ out, uint32_t *__restrict__ tb) {
-  if (is_patched(L)) {
-    switch (uniform(L.mode)) {
-      case S4_DELTA_D1: decode_wave_form<P, S4_DELTA_D1, true>(L, first, full_end, kbase, out, tb); break;
-      case S4_DELTA_D2: decode_wave_form<P, S4_DELTA_D2, true>(L, first, full_end, kbase, out, tb); break;
-      case S4_DELTA_DM: decode_wave_form<P, S4_DELTA_DM, true>(L, first, full_end, kbase, out, tb); break;
-      default: decode_wave_form<P, S4_DELTA_D4, true>(L, first, full_end, kbase, out, tb); break;
-    }
-    return;
-  }
-  switch (uniform(L.mode)) {
-    case S4_DELTA_D1: decode_wave_form<P, S4_DELTA_D1, false>(L, first, full_end, kbase, out, tb); break;
-    case S4_DELTA_D2: decode_wave_form<P, S4_DELTA_D2, false>(L, first, full_end, kbase, out, tb); break;
-    case S4_DELTA_DM: decode_wave_form<P, S4_DELTA_DM, false>(L, first, full_end, kbase, out, tb); break;
-    default: decode_wave_form<P, S4_DELTA_D4, false>(L, first, full_end, kbase, out, tb); break;
-  }
+  if (PK && is_patched(L))
+    decode_wave_as<P, true, true>(L, first, full_end, kbase, out, tb);
+  else
+    decode_wave_as<P, false, PK>(L, first, full_end, kbase, out, tb);
 }
 
 __device__ __forceinline__ void copy_tail(const DList &L, uint32_t *__restrict__ dst) {
@@ -289,9 +319,13 @@ __device__ __forceinline__ void copy_tail(const DList &L, uint32_t *__restrict__
 // for an argument fetch; the tail pointer and nb (needed by the tail wave
 // and by patched lists only) follow.  form = differential form |
 // kDecodePatched if patched | kDecodeTail | t << 16.
+// PK: instantiated for patched lists (see decode_wave).  The plain kernels
+// of 4 or more passes are held to 5 waves per SIMD: with more, measured on
+// the bulk workload, they streamed slower (all 4 P rows' loads in flight
+// per wave is worth more than further waves).
 constexpr uint32_t kDecodePatched = 1u << 8, kDecodeTail = 1u << 9;
-template <int P>
-__global__ __launch_bounds__(256) void k_decode(const uint8_t *widths, const uint32_t *offs, const uint4 *seeds,
+template <int P, bool PK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, (P >= 4 && !PK) ? 5 : 8))) void k_decode(const uint8_t *widths, const uint32_t *offs, const uint4 *seeds,
                                                 const uint32_t *payload, uint32_t *__restrict__ out, uint32_t first,
                                                 uint32_t full_end, uint32_t block_waves, uint32_t form,
                                                 const uint32_t *tail, uint32_t nb) {
@@ -314,15 +348,15 @@ __global__ __launch_bounds__(256) void k_decode(const uint8_t *widths, const uin
     if (wave == block_waves && (form & kDecodeTail)) copy_tail(L, out + uint64_t(full_end - first) * kBlock);
     return;
   }
-  decode_wave<P>(L, first, full_end, first + wave * 4u * P, out, stage[w]);
+  decode_wave<P, PK>(L, first, full_end, first + wave * 4u * P, out, stage[w]);
 }
 
 // Multi-list decode in one launch: wave w decodes for list wave_list[w];
 // wave_prefix[l] is the first wave of list l.  Within a list the waves are
 // laid out as in k_decode (blocks, then one tail wave when the list has a
-// tail).
-template <int P>
-__global__ __launch_bounds__(256) void k_decode_multi(const DList *__restrict__ lists,
+// tail).  PK: instantiated for plans that hold patched lists.
+template <int P, bool PK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, (P >= 4 && !PK) ? 5 : 8))) void k_decode_multi(const DList *__restrict__ lists,
                                                       uint32_t *const *__restrict__ outs,
                                                       const uint32_t *__restrict__ wave_prefix,
                                                       const uint32_t *__restrict__ wave_list, uint32_t waves) {
@@ -339,7 +373,7 @@ __global__ __launch_bounds__(256) void k_decode_multi(const DList *__restrict__ 
     copy_tail(L, out + uint64_t(L.nb) * kBlock);
     return;
   }
-  decode_wave<P>(L, 0, L.nb, local * 4u * P, out, stage[w]);
+  decode_wave<P, PK>(L, 0, L.nb, local * 4u * P, out, stage[w]);
 }
 
 // Busy-wait on the constant-rate device clock for `ticks` ticks.
@@ -698,15 +732,23 @@ static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len
   return run_chain(r, r_raw, r_len, args, ps, d_out, d_count, stream);
 }
 
+template <int P, bool PK>
+static void launch_decode_k(const DList &L, uint32_t first, uint32_t full_end, uint32_t block_waves, uint32_t waves,
+                            uint32_t form, uint32_t *d_out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL((k_decode<P, PK>), dim3((waves + 3) / 4), dim3(256), 0, stream, ev0, ev1, 0, L.widths,
+                          L.offs, L.seeds, L.payload, d_out, first, full_end, block_waves, form, L.tail, L.nb);
+  else
+    hipLaunchKernelGGL((k_decode<P, PK>), dim3((waves + 3) / 4), dim3(256), 0, stream, L.widths, L.offs, L.seeds,
+                       L.payload, d_out, first, full_end, block_waves, form, L.tail, L.nb);
+}
 template <int P>
 static void launch_decode(const DList &L, uint32_t first, uint32_t full_end, uint32_t block_waves, uint32_t waves,
                           uint32_t form, uint32_t *d_out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
-  if (ev0)
-    hipExtLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, ev0, ev1, 0, L.widths, L.offs,
-                          L.seeds, L.payload, d_out, first, full_end, block_waves, form, L.tail, L.nb);
+  if (is_patched(L))
+    launch_decode_k<P, true>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1);
   else
-    hipLaunchKernelGGL(k_decode<P>, dim3((waves + 3) / 4), dim3(256), 0, stream, L.widths, L.offs, L.seeds,
-                       L.payload, d_out, first, full_end, block_waves, form, L.tail, L.nb);
+    launch_decode_k<P, false>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1);
 }
 
 int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream) {
@@ -747,9 +789,20 @@ struct s4_decode_plan {
   const uint32_t *wave_list = nullptr;
   uint32_t count = 0, passes = 4, waves = 0;
   uint64_t ints = 0;
+  bool patched = false;  // some list is patched: the kernels instantiated for them
 };
 
 using namespace s4;
+
+template <int P>
+static void launch_plan(const s4_decode_plan *p, hipStream_t st) {
+  if (p->patched)
+    hipLaunchKernelGGL((k_decode_multi<P, true>), dim3((p->waves + 3) / 4), dim3(256), 0, st, p->lists, p->outs,
+                       p->prefix, p->wave_list, p->waves);
+  else
+    hipLaunchKernelGGL((k_decode_multi<P, false>), dim3((p->waves + 3) / 4), dim3(256), 0, st, p->lists, p->outs,
+                       p->prefix, p->wave_list, p->waves);
+}
 
 static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -940,6 +993,7 @@ int s4_decode_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, 
     const uint32_t bw = (l->nb + 4 * p->passes - 1) / (4 * p->passes);
     prefix[i + 1] = prefix[i] + bw + (l->t ? 1u : 0u);
     p->ints += l->n;
+    p->patched |= is_patched(l->d);
   }
   p->waves = prefix[count];
   const size_t desc_b = align_up(sizeof(DList) * std::max<uint32_t>(1, count), 256);
@@ -979,22 +1033,10 @@ int s4_decode_plan_run(const s4_decode_plan *p, void *stream) {
   if (!p) return fail(S4_EINVAL, "null plan");
   if (!p->waves) return S4_OK;
   switch (p->passes) {
-    case 8:
-      hipLaunchKernelGGL(k_decode_multi<8>, dim3((p->waves + 3) / 4), dim3(256), 0, as_stream(stream), p->lists,
-                         p->outs, p->prefix, p->wave_list, p->waves);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_decode_multi<2>, dim3((p->waves + 3) / 4), dim3(256), 0, as_stream(stream), p->lists,
-                         p->outs, p->prefix, p->wave_list, p->waves);
-      break;
-    case 1:
-      hipLaunchKernelGGL(k_decode_multi<1>, dim3((p->waves + 3) / 4), dim3(256), 0, as_stream(stream), p->lists,
-                         p->outs, p->prefix, p->wave_list, p->waves);
-      break;
-    default:
-      hipLaunchKernelGGL(k_decode_multi<4>, dim3((p->waves + 3) / 4), dim3(256), 0, as_stream(stream), p->lists,
-                         p->outs, p->prefix, p->wave_list, p->waves);
-      break;
+    case 8: launch_plan<8>(p, as_stream(stream)); break;
+    case 2: launch_plan<2>(p, as_stream(stream)); break;
+    case 1: launch_plan<1>(p, as_stream(stream)); break;
+    default: launch_plan<4>(p, as_stream(stream)); break;
   }
   S4_HIP(hipGetLastError());
   return S4_OK;

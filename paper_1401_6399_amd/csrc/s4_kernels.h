@@ -128,16 +128,23 @@ __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t s)
 // Row layout (16 lanes per block): lane i of the row extracts the D4 deltas
 // of positions q = 2i and 2i + 1 for all four lanes j, i.e. block integers
 // 8i .. 8i + 7.  Word rows m = floor(q b / 32) .. m + 2 are read as 16-byte
-// vectors (word 4m + j of lane j sits in component j).
-__device__ __forceinline__ void extract_row(const uint32_t *__restrict__ blk, uint32_t b, uint32_t i,
-                                            uint32_t d0[4], uint32_t d1[4]) {
+// vectors (word 4m + j of lane j sits in component j).  load_row issues
+// the lane's three row loads and unpack_row extracts from them, so a caller
+// can put other work between the two; extract_row does both.
+struct RowWords {
+  uint4 r0, r1, r2;
+};
+__device__ __forceinline__ RowWords load_row(const uint32_t *__restrict__ blk, uint32_t b, uint32_t i) {
+  const gconst<uint4> p = gbl(reinterpret_cast<const uint4 *>(blk)) + ((2u * i * b) >> 5);
+  return RowWords{p[0], p[1], p[2]};
+}
+__device__ __forceinline__ void unpack_row(const RowWords &w, uint32_t b, uint32_t i, uint32_t d0[4], uint32_t d1[4]) {
   const uint32_t bit0 = 2u * i * b;
   const uint32_t m0 = bit0 >> 5, s0 = bit0 & 31u;
   const uint32_t bit1 = bit0 + b;
   const uint32_t s1 = bit1 & 31u;
   const bool step = (bit1 >> 5) != m0;
-  const gconst<uint4> p = gbl(reinterpret_cast<const uint4 *>(blk)) + m0;
-  const uint4 r0 = p[0], r1 = p[1], r2 = p[2];
+  const uint4 r0 = w.r0, r1 = w.r1, r2 = w.r2;
   const uint32_t mask = width_mask(b);
   d0[0] = funnel(r1.x, r0.x, s0) & mask;
   d0[1] = funnel(r1.y, r0.y, s0) & mask;
@@ -149,6 +156,10 @@ __device__ __forceinline__ void extract_row(const uint32_t *__restrict__ blk, ui
   d1[1] = funnel(hi.y, lo.y, s1) & mask;
   d1[2] = funnel(hi.z, lo.z, s1) & mask;
   d1[3] = funnel(hi.w, lo.w, s1) & mask;
+}
+__device__ __forceinline__ void extract_row(const uint32_t *__restrict__ blk, uint32_t b, uint32_t i,
+                                            uint32_t d0[4], uint32_t d1[4]) {
+  unpack_row(load_row(blk, b, i), b, i, d0, d1);
 }
 
 // Inverse differential coding (Sec. 5) of the row layout: lane i holds the
