@@ -236,7 +236,31 @@ def batched(s4, workloads, torch, nq, plain_sample):
         del b
     out["hybrid"] = hybrid(s4, workloads, torch, index, buf, soffs, nq, {k: out[k] for k in ("pairwise", "multiterm")})
     out["partitioned"] = partitioned(s4, workloads, torch, nq, {k: out[k] for k in ("pairwise", "multiterm")})
+    out["fastpfor_index"] = fastpfor_index(s4, workloads, torch, nq, {k: out[k] for k in ("pairwise", "multiterm")})
     return out
+
+
+def fastpfor_index(s4, workloads, torch, nq, plain):
+    """The same index encoded as S4-FastPFOR-D1 (Sec. 4.4, patched blocks,
+    the densest form) and the same queries, autotuned, replayed as a
+    graph: storage against query time."""
+    flat, offs = workloads.pairwise_index()
+    buf, soffs = s4.encode_many(flat, offs, delta=s4.DELTA_D1, patched=True)
+    ix = s4.Index(buf, soffs)
+    del flat
+    row = {"bits_per_int": round(8 * ix.payload_bytes / ix.total_ints, 3)}
+    for name, qfn in (("pairwise", workloads.pairwise_queries), ("multiterm", workloads.multiterm_queries)):
+        terms, qoffs = qfn(ix.lengths, nq)
+        b = s4.Batch(ix, terms, qoffs)
+        best, _ = b.autotune(reps=2)
+        stream = torch.cuda.Stream()
+        ms, _ = time_graph(torch, lambda: b.run(use_graph=False), stream, steps=5, warmup=2)
+        row[f"{name}_qps"] = round(b.nq / (ms / 1e3), 1)
+        row[f"{name}_ms"] = round(ms, 3)
+        row[f"{name}_time_vs_s4bp128_d4"] = round(ms / plain[name]["batched_ms"], 3)
+        del b
+    log(f"S4-FastPFOR-D1 index: {row}")
+    return row
 
 
 def partitioned(s4, workloads, torch, nq, plain):
