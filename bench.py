@@ -111,6 +111,25 @@ def time_graph(torch, fn, stream, steps, warmup):
     return e0.elapsed_time(e1) / steps, g
 
 
+def time_graph_gated(torch, s4, g, stream, steps):
+    """Replays of graph g timed on the device after a spin kernel has held
+    the stream long enough for the host to queue all of them; also the
+    host's wall time per replay launch, taken while the device is held."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        s4.spin(max(20_000_000, 3_000_000 * steps))
+        e0.record()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        t1 = time.perf_counter()
+        e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, (t1 - t0) * 1e3 / steps
+
+
 def per_launch_ms(torch, s4, lists, outs, stream, reps=3):
     """Duration of every decode launch, from HIP events on the launch stream
     that the launch itself records at the kernel's start and end
@@ -483,10 +502,17 @@ def main():
     stream = torch.cuda.Stream()
     # headline: one launch per list, forked over streams, replayed as a graph
     torch.cuda.synchronize()
-    ms, _ = time_graph(torch, lambda: s4.decode_lists(lists, outs, nstreams=args.nstreams), stream,
+    ms, g = time_graph(torch, lambda: s4.decode_lists(lists, outs, nstreams=args.nstreams), stream,
                        args.steps, args.warmup)
     value = total / (ms / 1e3) / 1e9
     log(f"per-list launches: {ms:.3f} ms/step, {value:.1f} Gint/s")
+    # diagnostic only (never `value`): the same replays with the stream held
+    # until the host has queued them all, i.e. the device's time per step
+    # when launching the 256-kernel graph does not limit it
+    # (at most 30 replays queued at once, so the hardware queues never fill)
+    gated_ms, host_ms = time_graph_gated(torch, s4, g, stream, min(args.steps, 30))
+    log(f"per-list, device time with launches queued ahead: {gated_ms:.3f} ms/step; "
+        f"host time to launch one replay: {host_ms:.3f} ms")
 
     # roofline of the decode kernel: events around each launch
     dur = per_launch_ms(torch, s4, lists, outs, stream)
@@ -553,6 +579,11 @@ def main():
             "bytes_per_launch": round(float(abytes.mean()), 1),
             "frac_lists_ge_2p22": round(achieved_big / HBM_PEAK_GBS, 4),
         },
+        "per_list_device": {"ms_per_step": round(gated_ms, 4), "gint_s": round(total / (gated_ms / 1e3) / 1e9, 2),
+                            "host_ms_per_launch_of_step": round(host_ms, 4),
+                            "note": "same graph replays with the stream held until the host has queued them: the "
+                                    "device's time per step; `value` is end to end and is bounded by whichever "
+                                    "of the two is slower"},
         "single_launch": {"value": round(single, 2), "unit": "Gint/s", "ms_per_step": round(ms1, 4),
                           "frac": round(abytes.sum() / (ms1 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "whole_job_hbm_frac": round(abytes.sum() / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
