@@ -160,3 +160,37 @@ def test_bulk_workload_patched_single_launch(gpu, mode):
     host = out.cpu().numpy().view(np.uint32)
     for i, l in enumerate(lists):
         assert np.array_equal(host[pos[i]: pos[i] + l.n], flat[int(offs[i]): int(offs[i + 1])]), i
+
+
+@pytest.mark.parametrize("passes", [1, 2, 4])
+def test_mixed_plan_patched_and_plain(gpu, passes):
+    """A single-launch plan holding patched and plain lists in every form
+    runs the kernel instantiated for patched lists, which decodes its plain
+    lists with pipelined rows too; every value compared, at 1, 2 and 4
+    passes per wave, with edge lengths (tail only, one block, ragged)."""
+    import torch
+    lens = [1, 127, 128, 129, 1000, 4096 + 5, 128 * 37, 70001, (1 << 18) + 3]
+    xs, lists = [], []
+    for i, n in enumerate(lens * 2):
+        x = with_outliers(300 + i, n) if i % 2 == 0 else workloads.sorted_list(i % 2, 400 + i, 1 << 26, n)
+        xs.append(x)
+        lists.append(gpu.DeviceList.upload(gpu.encode(x, FORMS[i % 4], patched=(i % 3 != 1))))
+    patched = [(l.flags >> 3) & 1 for l in lists]
+    assert any(patched) and not all(patched)
+    pos, p = [], 0
+    for x in xs:
+        pos.append(p)
+        p += (x.size + 63) // 64 * 64 + 64
+    out = torch.full((p,), -1, dtype=torch.int32, device="cuda")
+    outs = [out[q: q + x.size + 4] for q, x in zip(pos, xs)]
+    t = gpu.get_tuning()
+    try:
+        gpu.set_tuning(**{**t.as_dict(), "decode_passes": passes})
+        plan = gpu.DecodePlan(lists, outs)
+        plan.run()
+        torch.cuda.synchronize()
+    finally:
+        gpu.set_tuning(**t.as_dict())
+    host = out.cpu().numpy().view(np.uint32)
+    for i, x in enumerate(xs):
+        assert np.array_equal(host[pos[i]: pos[i] + x.size], x), (i, lens[i % len(lens)])
