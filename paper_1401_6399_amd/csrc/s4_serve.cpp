@@ -457,11 +457,22 @@ void dispatcher(s4_server *s) {
             j.outstanding = 1;
             ++s->st.sliced_queries;
           } else {
-            sl.q = q;
-            if (!fits(sl.c1, q.k, sl.bound())) {
+            // a whole query: its slice is built in place in the context
+            // (one copy of the query, not two)
+            if (!fits(sl.c1, q.k, q.bound)) {
               if (c.slices.empty()) ++s->st.waits_for_memory;
               break;
             }
+            c.slices.emplace_back();
+            Slice &ns = c.slices.back();
+            ns.q = q;
+            ns.c1 = sl.c1;
+            items += ns.c1;
+            terms += q.k;
+            bound += ns.bound();
+            s->waiting.pop_front();
+            ++started;
+            continue;
           }
           s->waiting.pop_front();
           ++started;
