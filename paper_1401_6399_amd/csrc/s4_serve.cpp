@@ -5,7 +5,8 @@
 // server is created (nothing is allocated on the device while serving).
 // Each turn of its loop it
 //   1. retires contexts whose iteration has finished on the device (an event
-//      query, never a wait), handing results to the completed queue and
+//      query, never a wait), handing the iteration's finished queries to the
+//      completed queue as one batch (their results copied once) and
 //      releasing their memory reservation;
 //   2. fills a free context: first one slice of every query already running
 //      in slices (unless every other context already runs such slices, so
@@ -64,16 +65,28 @@ struct Query {
   Clock::time_point submitted;
 };
 
-struct Done {
+// The whole queries one iteration finished, handed over together: the
+// dispatcher copies the iteration's results once (one allocation per
+// iteration, not one per query).
+struct DoneBatch {
+  std::vector<uint64_t> ids, latency_ns;  // per query
+  std::vector<uint64_t> offs;             // [n + 1] CSR offsets into results
+  std::vector<uint32_t> results;
+  Clock::time_point at;  // completion stamp of all of them
+  size_t next = 0;       // queries already handed out by s4_server_poll
+  size_t size() const { return ids.size(); }
+  uint64_t count(size_t i) const { return offs[i + 1] - offs[i]; }
+};
+
+// A query run in slices, finished: its slices' results in chunk order,
+// joined by the consumer, so the dispatcher never copies a whole large
+// result while other queries wait for admission.
+struct DoneJob {
   uint64_t id, count, latency_ns;
-  std::vector<uint32_t> result;
-  // a query run in slices: its slices' results in chunk order, joined by
-  // the consumer (result is then empty), so the dispatcher never copies a
-  // whole large result while other queries wait for admission
   std::vector<std::vector<uint32_t>> parts;
+  Clock::time_point at;
   // append the result, in order, at dst
   void copy_to(uint32_t *dst) const {
-    dst = std::copy(result.begin(), result.end(), dst);
     for (const auto &p : parts) dst = std::copy(p.begin(), p.end(), dst);
   }
 };
@@ -140,8 +153,8 @@ struct s4_server {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Query> waiting;
-  std::deque<Done> completed;
-  std::deque<Clock::time_point> completed_at;
+  std::deque<DoneBatch> completed;     // whole queries, per iteration
+  std::deque<DoneJob> completed_jobs;  // queries run in slices
   std::atomic<bool> stop{false};
   std::thread worker;
   int device = 0;
@@ -311,50 +324,66 @@ bool offsets_valid(const Context &c) {
   return true;
 }
 
-// Move a finished context's results to the completed queue: whole queries
-// at once, slices into their job (a finished job's slices handed over in
-// chunk order, to be joined by the consumer).
+// Move a finished context's results to the completed queues: the whole
+// queries of the iteration as one batch (their results copied once, in
+// slice order), slices into their job (a finished job's slices handed over
+// in chunk order, to be joined by the consumer).
 void retire_context(s4_server *s, Context &c, const uint32_t *res) {
   const auto now = Clock::now();
-  std::vector<Done> out;
-  out.reserve(c.slices.size());
-  auto done_of = [&](const Query &q, std::vector<uint32_t> &&r, std::vector<std::vector<uint32_t>> &&parts) {
-    Done d;
-    d.id = q.id;
-    d.count = r.size();
-    for (const auto &p : parts) d.count += p.size();
-    d.latency_ns = ns_between(q.submitted, now);
-    d.result = std::move(r);
-    d.parts = std::move(parts);
-    out.push_back(std::move(d));
-  };
-  for (size_t i = 0; i < c.slices.size(); ++i) {
+  const size_t n = c.slices.size();
+  DoneBatch bt;
+  bt.at = now;
+  bt.ids.reserve(n);
+  bt.latency_ns.reserve(n);
+  bt.offs.reserve(n + 1);
+  bt.offs.push_back(0);
+  std::vector<DoneJob> jobs_done;
+  bool any_job = false;
+  for (size_t i = 0; i < n; ++i) {
     Slice &sl = c.slices[i];
-    const uint64_t o0 = c.h_offs[i], cnt = c.h_offs[i + 1] - o0;
     if (!sl.job) {
-      done_of(sl.q, std::vector<uint32_t>(res + o0, res + o0 + cnt), {});
+      bt.ids.push_back(sl.q.id);
+      bt.latency_ns.push_back(ns_between(sl.q.submitted, now));
+      bt.offs.push_back(bt.offs.back() + (c.h_offs[i + 1] - c.h_offs[i]));
       continue;
     }
+    any_job = true;
+    const uint64_t o0 = c.h_offs[i], cnt = c.h_offs[i + 1] - o0;
     Job &j = *sl.job;
     j.parts.emplace_back(sl.c0, std::vector<uint32_t>(res + o0, res + o0 + cnt));
     if (--j.outstanding == 0 && j.next == j.q.items) {
       std::sort(j.parts.begin(), j.parts.end(),
                 [](const auto &a, const auto &b) { return a.first < b.first; });
-      std::vector<std::vector<uint32_t>> parts;
-      parts.reserve(j.parts.size());
-      for (auto &p : j.parts) parts.push_back(std::move(p.second));
-      done_of(j.q, {}, std::move(parts));
+      DoneJob d;
+      d.id = j.q.id;
+      d.count = 0;
+      d.latency_ns = ns_between(j.q.submitted, now);
+      d.at = now;
+      d.parts.reserve(j.parts.size());
+      for (auto &p : j.parts) {
+        d.count += p.second.size();
+        d.parts.push_back(std::move(p.second));
+      }
+      jobs_done.push_back(std::move(d));
       const Job *jp = &j;
       s->jobs.remove_if([jp](const Job &x) { return &x == jp; });
     }
   }
-  std::lock_guard<std::mutex> lock(s->mu);
-  for (auto &d : out) {
-    s->completed.push_back(std::move(d));
-    s->completed_at.push_back(now);
+  // the whole queries' results: one contiguous range when the iteration
+  // held no job slices, else each query's range in turn
+  if (!any_job) {
+    bt.results.assign(res, res + c.h_offs[n]);
+  } else {
+    bt.results.reserve(bt.offs.back());
+    for (size_t i = 0; i < n; ++i)
+      if (!c.slices[i].job) bt.results.insert(bt.results.end(), res + c.h_offs[i], res + c.h_offs[i + 1]);
   }
-  s->st.completed += out.size();
-  s->active -= out.size();
+  const uint64_t finished = bt.size() + jobs_done.size();
+  std::lock_guard<std::mutex> lock(s->mu);
+  if (bt.size()) s->completed.push_back(std::move(bt));
+  for (auto &d : jobs_done) s->completed_jobs.push_back(std::move(d));
+  s->st.completed += finished;
+  s->active -= finished;
   s->pool_in_use -= c.reserved_stage;
   c.slices.clear();
   c.reserved_stage = 0;
@@ -634,8 +663,26 @@ int s4_server_poll(s4_server *s, uint64_t *ids, uint64_t *counts, uint64_t *late
   uint32_t n = 0;
   uint64_t used = 0;
   if (max_done) res_offsets[0] = 0;
-  while (n < max_done && !s->completed.empty()) {
-    Done &d = s->completed.front();
+  bool room = true;
+  while (room && n < max_done && !s->completed.empty()) {
+    DoneBatch &b = s->completed.front();
+    for (; n < max_done && b.next < b.size(); ++b.next, ++n) {
+      const uint64_t cnt = b.count(b.next);
+      if (used + cnt > results_cap || (cnt && !results)) {
+        room = false;
+        break;
+      }
+      std::copy(b.results.begin() + b.offs[b.next], b.results.begin() + b.offs[b.next + 1], results + used);
+      ids[n] = b.ids[b.next];
+      counts[n] = cnt;
+      latency_ns[n] = b.latency_ns[b.next];
+      used += cnt;
+      res_offsets[n + 1] = used;
+    }
+    if (b.next == b.size()) s->completed.pop_front();
+  }
+  while (room && n < max_done && !s->completed_jobs.empty()) {
+    DoneJob &d = s->completed_jobs.front();
     if (used + d.count > results_cap || (d.count && !results)) break;
     d.copy_to(results + used);
     ids[n] = d.id;
@@ -643,8 +690,7 @@ int s4_server_poll(s4_server *s, uint64_t *ids, uint64_t *counts, uint64_t *late
     latency_ns[n] = d.latency_ns;
     used += d.count;
     res_offsets[n + 1] = used;
-    s->completed.pop_front();
-    s->completed_at.pop_front();
+    s->completed_jobs.pop_front();
     ++n;
   }
   *done = n;
@@ -665,14 +711,18 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
   if (!s || !h_q_offsets || !h_arrival_ns || !latency_ns || !counts || (nq && !h_terms))
     return fail(S4_EINVAL, "null argument");
   if (results && !res_offsets) return fail(S4_EINVAL, "results need res_offsets");
-  std::vector<std::vector<uint32_t>> res(results ? nq : 0);
-  std::unordered_map<uint64_t, std::vector<std::vector<uint32_t>>> res_parts;  // queries run in slices
+  // results stay in the batches they arrived in until the end: query q's
+  // are entry where[q].second of kept[where[q].first], or, for a query run
+  // in slices, its parts
+  std::vector<DoneBatch> kept;
+  std::vector<std::pair<uint32_t, uint32_t>> where(results ? nq : 0, {UINT32_MAX, 0u});
+  std::unordered_map<uint64_t, std::vector<std::vector<uint32_t>>> res_parts;
   uint64_t ndone = 0, next = 0;
   std::unordered_map<uint64_t, uint64_t> pending;
   pending.reserve(size_t(std::min<uint64_t>(nq, 64ull * s->cfg.max_slots)));
   std::vector<Query> due;
-  std::deque<Done> got;
-  std::deque<Clock::time_point> got_at;
+  std::deque<DoneBatch> got;
+  std::deque<DoneJob> got_jobs;
   const auto t0 = Clock::now();
   auto now_ns = [&]() { return ns_between(t0, Clock::now()); };
   uint64_t last_done_ns = 0, last_drain_ns = 0;
@@ -714,27 +764,35 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
       next += take;
       if (take) s->cv.notify_one();
       got.swap(s->completed);
-      got_at.swap(s->completed_at);
+      got_jobs.swap(s->completed_jobs);
     }
     // completions, outside the lock
+    auto finish = [&](uint64_t id, uint64_t count, Clock::time_point at) -> uint64_t {
+      auto it = pending.find(id);
+      if (it == pending.end()) return UINT64_MAX;
+      const uint64_t q = it->second;
+      const uint64_t fin = ns_between(t0, at);
+      latency_ns[q] = fin > h_arrival_ns[q] ? fin - h_arrival_ns[q] : 0;
+      last_done_ns = std::max(last_done_ns, fin);
+      counts[q] = count;
+      ++ndone;
+      pending.erase(it);
+      return q;
+    };
     while (!got.empty()) {
-      Done &d = got.front();
-      auto it = pending.find(d.id);
-      if (it != pending.end()) {
-        const uint64_t q = it->second;
-        const uint64_t fin = ns_between(t0, got_at.front());
-        latency_ns[q] = fin > h_arrival_ns[q] ? fin - h_arrival_ns[q] : 0;
-        last_done_ns = std::max(last_done_ns, fin);
-        counts[q] = d.count;
-        if (results) {
-          res[q] = std::move(d.result);
-          if (!d.parts.empty()) res_parts[q] = std::move(d.parts);
-        }
-        ++ndone;
-        pending.erase(it);
+      DoneBatch &b = got.front();
+      for (size_t i = b.next; i < b.size(); ++i) {
+        const uint64_t q = finish(b.ids[i], b.count(i), b.at);
+        if (q != UINT64_MAX && results) where[q] = {uint32_t(kept.size()), uint32_t(i)};
       }
+      if (results) kept.push_back(std::move(b));
       got.pop_front();
-      got_at.pop_front();
+    }
+    while (!got_jobs.empty()) {
+      DoneJob &d = got_jobs.front();
+      const uint64_t q = finish(d.id, d.count, d.at);
+      if (q != UINT64_MAX && results) res_parts[q] = std::move(d.parts);
+      got_jobs.pop_front();
     }
     if (double(now_ns()) * 1e-9 > timeout_s) return fail(S4_ERANGE, "replay timed out");
     if (next < nq && h_arrival_ns[next] > now_ns() + 50000)
@@ -748,11 +806,15 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
     res_offsets[0] = 0;
     for (uint64_t q = 0; q < nq; ++q) {
       if (used + counts[q] > results_cap) return fail(S4_ERANGE, "results_cap too small");
-      std::copy(res[q].begin(), res[q].end(), results + used);
-      uint64_t at = used + res[q].size();
       auto it = res_parts.find(q);
-      if (it != res_parts.end())
-        for (const auto &p : it->second) at = uint64_t(std::copy(p.begin(), p.end(), results + at) - results);
+      if (it != res_parts.end()) {
+        uint32_t *at = results + used;
+        for (const auto &p : it->second) at = std::copy(p.begin(), p.end(), at);
+      } else if (where[q].first != UINT32_MAX) {
+        const DoneBatch &b = kept[where[q].first];
+        const size_t i = where[q].second;
+        std::copy(b.results.begin() + b.offs[i], b.results.begin() + b.offs[i + 1], results + used);
+      }
       used += counts[q];
       res_offsets[q + 1] = used;
     }
