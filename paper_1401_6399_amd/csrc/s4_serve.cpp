@@ -718,8 +718,12 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
   std::vector<std::pair<uint32_t, uint32_t>> where(results ? nq : 0, {UINT32_MAX, 0u});
   std::unordered_map<uint64_t, std::vector<std::vector<uint32_t>>> res_parts;
   uint64_t ndone = 0, next = 0;
-  std::unordered_map<uint64_t, uint64_t> pending;
-  pending.reserve(size_t(std::min<uint64_t>(nq, 64ull * s->cfg.max_slots)));
+  // query of each id this replay assigned: ids are handed out in order under
+  // the lock, so q_of[id - id0] (UINT64_MAX for ids of other submitters, or
+  // once finished) replaces a hash map on the per-query path
+  uint64_t id0 = UINT64_MAX;
+  std::vector<uint64_t> q_of;
+  q_of.reserve(nq);
   std::vector<Query> due;
   std::deque<DoneBatch> got;
   std::deque<DoneJob> got_jobs;
@@ -753,11 +757,14 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
       const uint64_t room = 64ull * s->cfg.max_slots - std::min<uint64_t>(s->waiting.size(), 64ull * s->cfg.max_slots);
       const uint64_t take = std::min<uint64_t>(room, due.size());
       const auto now = Clock::now();
+      if (take && id0 == UINT64_MAX) id0 = s->next_id;
       for (uint64_t i = 0; i < take; ++i) {
         Query &q = due[i];
         q.id = s->next_id++;
         q.submitted = now;
-        pending.emplace(q.id, next + i);
+        const uint64_t slot = q.id - id0;
+        if (slot >= q_of.size()) q_of.resize(slot + 1, UINT64_MAX);
+        q_of[slot] = next + i;
         s->waiting.push_back(q);
       }
       s->st.submitted += take;
@@ -768,15 +775,14 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
     }
     // completions, outside the lock
     auto finish = [&](uint64_t id, uint64_t count, Clock::time_point at) -> uint64_t {
-      auto it = pending.find(id);
-      if (it == pending.end()) return UINT64_MAX;
-      const uint64_t q = it->second;
+      if (id0 == UINT64_MAX || id < id0 || id - id0 >= q_of.size() || q_of[id - id0] == UINT64_MAX) return UINT64_MAX;
+      const uint64_t q = q_of[id - id0];
+      q_of[id - id0] = UINT64_MAX;
       const uint64_t fin = ns_between(t0, at);
       latency_ns[q] = fin > h_arrival_ns[q] ? fin - h_arrival_ns[q] : 0;
       last_done_ns = std::max(last_done_ns, fin);
       counts[q] = count;
       ++ndone;
-      pending.erase(it);
       return q;
     };
     while (!got.empty()) {
