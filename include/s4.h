@@ -437,7 +437,10 @@ int s4_server_destroy(s4_server *srv);
  * results is not null, result q is copied to results + res_offsets[q]
  * (res_offsets has nq + 1 entries) if everything fits results_cap.  Returns
  * S4_ERANGE after timeout_s seconds without every result; *elapsed_s
- * receives the wall time from the first arrival to the last result. */
+ * receives the wall time from the first arrival to the last result.  The
+ * replay takes every completion the server hands over while it runs:
+ * queries submitted by other threads meanwhile finish unseen by
+ * s4_server_poll. */
 int s4_server_replay(s4_server *srv, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
                      const uint64_t *h_arrival_ns, uint64_t *latency_ns, uint64_t *counts, uint32_t *results,
                      uint64_t results_cap, uint64_t *res_offsets, double timeout_s, double *elapsed_s);
