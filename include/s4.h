@@ -349,10 +349,16 @@ int s4_batch_run(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offsets, u
  * ticks[nq].  Synchronises `stream`. */
 int s4_batch_query_ticks(const s4_batch *batch, uint64_t *ticks, void *stream);
 
-/* Algorithmic traffic of the last run: bytes = packed payload, width byte,
- * block offset and seed of every block decoded, skip-index entries staged,
- * raw values read, plus 4 bytes per result; blocks = blocks decoded.
- * Synchronises `stream`. */
+/* Count algorithmic traffic in later runs of this batch (on != 0) or not
+ * (the default: counting costs the kernels 7-16% of their time, so timed
+ * runs leave it off).  A captured graph of the batch is dropped and
+ * re-captured on its next run. */
+int s4_batch_set_counting(s4_batch *batch, int on);
+
+/* Algorithmic traffic of the last run, if it counted (else zeros): bytes =
+ * packed payload, width byte, block offset and seed of every block decoded,
+ * skip-index entries staged, raw values read, plus 4 bytes per result;
+ * blocks = blocks decoded.  Synchronises `stream`. */
 int s4_batch_traffic(const s4_batch *batch, uint64_t *bytes, uint64_t *blocks, void *stream);
 
 /* Autotune gallop_blocks / waves_per_group / groups_per_cu / items_per_grab

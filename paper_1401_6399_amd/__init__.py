@@ -103,6 +103,7 @@ SIGNATURES = {
     "s4_batch_results_bound": (_u64, [_vp]),
     "s4_batch_run": (_i, [_vp, _vp, _vp, _vp, _u64, _i, _vp]),
     "s4_batch_query_ticks": (_i, [_vp, _u64p, _vp]),
+    "s4_batch_set_counting": (_i, [_vp, _i]),
     "s4_batch_traffic": (_i, [_vp, _u64p, _u64p, _vp]),
     "s4_batch_autotune": (_i, [_vp, _vp, _vp, _vp, _u64, _i, _vp, ctypes.POINTER(Tuning),
                                ctypes.POINTER(ctypes.c_double)]),
@@ -525,8 +526,14 @@ class Batch:
                "s4_batch_query_ticks")
         return t[: self.nq]
 
+    def set_counting(self, on):
+        """Count algorithmic traffic in later runs (off by default: it slows
+        the kernels)."""
+        _check(require_library().s4_batch_set_counting(self.h, 1 if on else 0), "s4_batch_set_counting")
+
     def traffic(self, stream=None):
-        """(algorithmic bytes, blocks decoded) of the last run."""
+        """(algorithmic bytes, blocks decoded) of the last run, zeros if it
+        did not count (see set_counting)."""
         b, k = ctypes.c_uint64(0), ctypes.c_uint64(0)
         _check(require_library().s4_batch_traffic(self.h, ctypes.byref(b), ctypes.byref(k), _stream(stream)),
                "s4_batch_traffic")

@@ -46,6 +46,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
   const uint32_t lane = lane_id();
   const uint64_t t0 = *b.start;
   Traffic tr;
+  tr.on = b.count != 0;
   // completion stamps: one atomic per run of consecutive chunks of a query
   uint32_t run_q = kInvalid;
   uint64_t run_t = 0;
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
       drain(p, b.part_base[p], b.part_base[p + 1] - b.part_base[p]);
     }
   }
-  if (lane == 0) {
+  if (tr.on && lane == 0) {
     atomicAdd(reinterpret_cast<unsigned long long *>(b.stats), static_cast<unsigned long long>(tr.bytes));
     atomicAdd(reinterpret_cast<unsigned long long *>(b.stats + 1), static_cast<unsigned long long>(tr.blocks));
   }
@@ -829,6 +830,16 @@ int s4_batch_run(s4_batch *b, uint64_t *d_counts, uint64_t *d_res_offsets, uint3
     b->g_tuning = t;
   }
   S4_HIP(hipGraphLaunch(b->exec, st));
+  return S4_OK;
+}
+
+int s4_batch_set_counting(s4_batch *b, int on) {
+  if (!b) return fail(S4_EINVAL, "null batch");
+  const uint32_t c = on ? 1u : 0u;
+  if (b->dev.count != c) {
+    b->dev.count = c;
+    drop_graph(b);  // the kernels' arguments changed
+  }
   return S4_OK;
 }
 

@@ -407,10 +407,19 @@ struct RSide {
 
 // Algorithmic bytes read by a wave (uniform): packed payload + width byte +
 // block offset + seed of every decoded block, staged skip-index entries,
-// raw values; and the number of blocks decoded.
+// raw values; and the number of blocks decoded.  Counted only when `on`:
+// the count (a width load and cross-lane reads per candidate group) costs
+// the chunk kernels, bound by instruction issue, 7-16% of their time.
 struct Traffic {
   uint64_t bytes = 0;
   uint64_t blocks = 0;
+  bool on = false;
+  __device__ __forceinline__ void add(uint64_t b, uint64_t k = 0) {
+    if (on) {
+      bytes += b;
+      blocks += k;
+    }
+  }
 };
 
 // Chunk `item` of a bitmap list (its values of rank 128 item .. 128 item +
@@ -426,12 +435,12 @@ __device__ __forceinline__ uint32_t load_bitmap_chunk(const DList &L, uint32_t i
   if (want) {
     const uint32_t first = uniform(gbl(L.bmax)[item]);
     const uint32_t w0 = first >> 5;
-    tr.bytes += 4u;
+    tr.add(4u);
     for (uint32_t w = w0; got < want && w < L.aux; w += 64) {
       const uint32_t wi = w + lane;
       uint32_t word = wi < L.aux ? gbl(L.payload)[wi] : 0u;
       if (wi == w0) word &= ~((1u << (first & 31u)) - 1u);  // bits of earlier chunks
-      tr.bytes += 4u * min(64u, L.aux - w);
+      tr.add(4u * min(64u, L.aux - w));
       const uint32_t pc = uint32_t(__popc(word));
       const uint32_t incl = scan_wave64(pc);
       uint32_t pos = got + incl - pc;
@@ -462,8 +471,7 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     return load_bitmap_chunk(r.L, item, s, tr);
   } else if (item < r.L.nb) {
     cnt = kBlock;
-    tr.bytes += 16u * uniform(gbl(r.L.widths)[item]) + 1u + 4u + 16u;
-    tr.blocks += 1;
+    if (tr.on) tr.add(16u * uniform(gbl(r.L.widths)[item]) + 1u + 4u + 16u, 1);  // width load only when counting
     if (r.L.mode == S4_DELTA_D4 && !((FEAT & kFeatPatched) && is_patched(r.L))) {
       decode_block_wave(r.L, item, s.r);
     } else {
@@ -482,7 +490,7 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
     if (lane < cnt) s.r[lane] = gbl(r.L.tail)[lane];
     if (lane + 64 < cnt) s.r[lane + 64] = gbl(r.L.tail)[lane + 64];
   }
-  if (r.raw || item >= r.L.nb) tr.bytes += 4u * cnt;
+  if (r.raw || item >= r.L.nb) tr.add(4u * cnt);
   wave_sync();
   return cnt;
 }
@@ -532,7 +540,7 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
     if (span <= gallop_blocks) {
       // merge regime: stage the spanned bmax entries in LDS, search there
       for (uint32_t e = lane; e < span; e += 64) s.bm[e] = (lo + e < nbf) ? gbl(f.bmax)[lo + e] : kInvalid;
-      tr.bytes += 4u * span;
+      tr.add(4u * span);
       wave_sync();
       c0 = lo + lower_bound_u32(s.bm, 0, span - 1, a0);
       c1 = lo + lower_bound_u32(s.bm, 0, span - 1, a1);
@@ -564,11 +572,13 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
       const uint32_t cs = g + row;
       const uint32_t blk = cs < U ? s.cand[cs] : kInvalid;
       // traffic of the four rows' blocks, summed from each row's first lane
-      uint32_t tb = 0;
-      if (ri == 0) tb = blk < nbf ? 16u * gbl(f.widths)[blk] + 21u : (blk == nbf ? 4u * f.t : 0u);
-      tr.bytes += uint32_t(__builtin_amdgcn_readlane(int(tb), 0)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 16)) +
-                  uint32_t(__builtin_amdgcn_readlane(int(tb), 32)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 48));
-      tr.blocks += min(4u, U - g);
+      if (tr.on) {
+        uint32_t tb = 0;
+        if (ri == 0) tb = blk < nbf ? 16u * gbl(f.widths)[blk] + 21u : (blk == nbf ? 4u * f.t : 0u);
+        tr.bytes += uint32_t(__builtin_amdgcn_readlane(int(tb), 0)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 16)) +
+                    uint32_t(__builtin_amdgcn_readlane(int(tb), 32)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 48));
+        tr.blocks += min(4u, U - g);
+      }
       uint32_t x0[4], x1[4];
       decode_row<PATCHED>(f, blk, blk < nbf, ri, x0, x1, s.f[row]);
       if (blk < nbf) {
@@ -608,7 +618,7 @@ __device__ __forceinline__ uint32_t probe_chunk(uint32_t cnt, const DList &f, It
   bool f0 = false, f1 = false;
   if (v0 && (a0 >> 5) < f.aux) f0 = (gbl(f.payload)[a0 >> 5] >> (a0 & 31u)) & 1u;
   if (v1 && (a1 >> 5) < f.aux) f1 = (gbl(f.payload)[a1 >> 5] >> (a1 & 31u)) & 1u;
-  tr.bytes += 4u * cnt;
+  tr.add(4u * cnt);
   return compact_chunk(f0, f1, a0, a1, s);
 }
 
@@ -639,7 +649,7 @@ __device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, c
     else
       cnt = intersect_chunk<(FEAT & kFeatPatched) != 0>(cnt, fj, s, gallop_blocks, tr);
   }
-  tr.bytes += 4u * cnt;  // the chunk's results
+  tr.add(4u * cnt);  // the chunk's results
   return cnt;
 }
 

@@ -107,13 +107,23 @@ def test_batch_invariant_under_tuning(gpu, small_index):
 
 
 def test_query_ticks(gpu, small_index):
+    import torch
     ix, flat, offs = small_index
     terms, qoffs = workloads.queries(11, ix.lengths, 300, 2, 4)
     b = gpu.Batch(ix, terms, qoffs)
     b.run()
     t = b.query_ticks()
     assert t.size == 300 and (t > 0).all()
+    assert b.traffic() == (0, 0)  # counting is off by default
+    counts, results = b.counts.clone(), b.results.clone()
+    b.set_counting(True)
+    b.run()
     nbytes, blocks = b.traffic()
+    torch.cuda.synchronize()
+    assert torch.equal(b.counts, counts) and torch.equal(b.results, results)
+    b.set_counting(False)
+    b.run()
+    assert b.traffic() == (0, 0)
     chunks = sum((int(ix.lengths[min(terms[int(qoffs[q]): int(qoffs[q + 1])], key=lambda x: ix.lengths[x])]) + 127)
                  // 128 for q in range(300))
     assert blocks >= chunks * 0.5 and nbytes > 16 * blocks
