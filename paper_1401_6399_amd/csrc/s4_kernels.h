@@ -347,6 +347,20 @@ __device__ __forceinline__ uint32_t lower_bound_u32(Ptr v, uint32_t lo, uint32_t
   return lo;
 }
 
+// Whether key is among the first n (<= 128) values of a decoded block row
+// in LDS, sorted, with the entries from n up to 128 holding 0xFFFFFFFF: a
+// lower bound by seven fixed halvings (unrolled: a step is one LDS read, a
+// compare and a select, with no loop control), then one compare.  Entries
+// at n and beyond never satisfy p < n, so a key of 0xFFFFFFFF is found only
+// where the row really holds it.
+__device__ __forceinline__ bool block_has(const uint32_t *v, uint32_t n, uint32_t key) {
+  uint32_t p = 0;
+#pragma unroll
+  for (uint32_t step = kBlock / 2; step; step >>= 1)
+    if (v[p + step - 1] < key) p += step;
+  return p < n && v[p] == key;
+}
+
 // Two lower bounds at once over v[0 .. n): r0 = first index with
 // v[r0] >= key0, r1 = first with v[r1] >= key1 (n if none).  Lanes 0..31
 // work on key0 and lanes 32..63 on key1; every round each half probes 32
@@ -585,22 +599,13 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
         *reinterpret_cast<uint4 *>(&s.f[row][8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
         *reinterpret_cast<uint4 *>(&s.f[row][8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
       } else if (blk == nbf) {
+        // the raw tail, padded to a full row for block_has
         for (uint32_t e = 0; e < 8; ++e)
-          if (8 * ri + e < f.t) s.f[row][8 * ri + e] = gbl(f.tail)[8 * ri + e];
+          s.f[row][8 * ri + e] = 8 * ri + e < f.t ? gbl(f.tail)[8 * ri + e] : kInvalid;
       }
       wave_sync();
-      if (slot0 - g < 4u) {
-        const uint32_t n = (c0 == nbf) ? f.t : kBlock;
-        const uint32_t *v = s.f[slot0 - g];
-        const uint32_t p = lower_bound_u32(v, 0, n, a0);
-        f0 = p < n && v[p] == a0;
-      }
-      if (slot1 - g < 4u) {
-        const uint32_t n = (c1 == nbf) ? f.t : kBlock;
-        const uint32_t *v = s.f[slot1 - g];
-        const uint32_t p = lower_bound_u32(v, 0, n, a1);
-        f1 = p < n && v[p] == a1;
-      }
+      if (slot0 - g < 4u) f0 = block_has(s.f[slot0 - g], c0 == nbf ? f.t : kBlock, a0);
+      if (slot1 - g < 4u) f1 = block_has(s.f[slot1 - g], c1 == nbf ? f.t : kBlock, a1);
       wave_sync();
     }
   }

@@ -57,6 +57,11 @@ def test_edge_pairs(gpu):
         (base[::2], base[1::2]),                              # interleaved, disjoint
         (base[:2000], base[3000:]),                           # disjoint ranges
         (np.array([0, 2**32 - 1], np.uint32), np.array([0, 5, 2**32 - 1], np.uint32)),
+        # full blocks, then a raw tail ending at the largest value: the key
+        # 2^32 - 1 found there, and 2^32 - 2 (below the list's maximum) not
+        (np.array([base[7], 2**32 - 1], np.uint32), np.append(base[:300], np.uint32(2**32 - 1))),
+        (np.array([base[7], 2**32 - 2], np.uint32), np.append(base[:300], np.uint32(2**32 - 1))),
+        (np.append(base[250:300], np.uint32(2**32 - 1)), np.append(base[:300:2], np.uint32(2**32 - 1))),
         (base + np.uint32(1 << 30), base),
         (np.arange(0, 3000, 3, dtype=np.uint32), np.arange(0, 3000, 2, dtype=np.uint32)),
         (rng.choice(base, 300, replace=False), base),
