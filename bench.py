@@ -170,9 +170,60 @@ def cpu_baseline(flat, offs, passes):
             for r in ex.map(lambda i: oracle.decode(encs[i]).size, order):
                 done += r
     dt, cpu = time.perf_counter() - t0, time.process_time() - c0
+    # one thread, one pass over the same lists
+    t1 = time.perf_counter()
+    one = sum(oracle.decode(encs[i]).size for i in order)
+    dt1 = time.perf_counter() - t1
     return {"value": round(done / dt / 1e9, 4), "unit": "Gint/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle decode of all {n} bulk lists ({int(offs[-1])} ints), {passes} passes, "
-                      f"{threads} threads, {dt:.1f} s wall, {cpu:.1f} s CPU"}
+                      f"{threads} threads, {dt:.1f} s wall, {cpu:.1f} s CPU",
+            "single_thread_value": round(one / dt1 / 1e9, 4),
+            "single_thread_sample": f"one pass over the same lists on one thread, {dt1:.1f} s",
+            "host": host_info()}
+
+
+def host_info():
+    """CPU model and thread counts of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_threads": aff}
+
+
+def device_info(torch):
+    """The GPU's properties as the runtime reports them."""
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "l2_bytes": getattr(p, "L2_cache_size", None), "hbm_bytes": p.total_memory}
+
+
+def copy_ceiling(torch, stream, reps=10):
+    """Bandwidth of a plain device-to-device copy of 1 GiB (read + write
+    bytes per second): what a kernel that only moves data reaches here."""
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    gbs = 2 * 4 * n / (ms / 1e3) / 1e9
+    return {"gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes": 2 * 4 * n,
+            "ms": round(ms, 4)}
 
 
 def delta_forms(s4, torch, flat, offs, outs, stream, steps, warmup, patched=False):
@@ -598,7 +649,13 @@ def main():
                           "frac": round(abytes.sum() / (ms1 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "whole_job_hbm_frac": round(abytes.sum() / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "paper_context": "0.7 cycles/int, 5.4 Gint/s: Xeon E5-1620 3.6 GHz, 1 thread, cache-resident",
+        "device": device_info(torch),
     }
+    if not args.decode_only:
+        cc = copy_ceiling(torch, stream)
+        cc["decode_single_launch_vs_copy"] = round(abytes.sum() / (ms1 / 1e3) / 1e9 / cc["gbs"], 4)
+        result["copy_ceiling"] = cc
+        log(f"copy ceiling: {cc}")
     if not args.decode_only:
         result["delta_forms"] = delta_forms(s4, torch, flat, offs, outs, stream, 20, 3)
         log(f"delta forms: {result['delta_forms']}")
