@@ -129,6 +129,31 @@ def test_query_ticks(gpu, small_index):
     assert blocks >= chunks * 0.5 and nbytes > 16 * blocks
 
 
+def test_counting_through_graph(gpu, small_index):
+    # switching counting re-captures the batch's graph: a replay of the old
+    # graph would keep the old setting
+    import torch
+    ix, flat, offs = small_index
+    terms, qoffs = workloads.queries(12, ix.lengths, 400, 2, 5)
+    b = gpu.Batch(ix, terms, qoffs)
+    b.run(use_graph=True)
+    b.run(use_graph=True)
+    assert b.traffic() == (0, 0)
+    counts, results = b.counts.clone(), b.results.clone()
+    b.set_counting(True)
+    seen = []
+    for _ in range(2):
+        b.run(use_graph=True)
+        seen.append(b.traffic())
+    assert seen[0] == seen[1] and seen[0][0] > 0 and seen[0][1] > 0
+    b.set_counting(False)
+    b.run(use_graph=True)
+    assert b.traffic() == (0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(b.counts, counts) and torch.equal(b.results, results)
+    check_batch(gpu, b, terms, qoffs, flat, offs, sample=range(0, 400, 7))
+
+
 def test_batch_rejects_bad_queries(gpu, small_index):
     ix, _, _ = small_index
     with pytest.raises(gpu.S4Error):
