@@ -399,7 +399,7 @@ def hybrid(s4, workloads, torch, index, buf, soffs, nq, plain):
 
 def counted_traffic(b):
     """Algorithmic traffic of one extra, untimed run with counting on (the
-    timed runs leave it off: it costs the chunk kernels 7-16%)."""
+    timed runs leave it off: it slows the chunk kernels by 4-15%)."""
     b.set_counting(True)
     b.run(use_graph=False)
     out = b.traffic()

@@ -329,10 +329,15 @@ int s4_index_hybrid_info(const s4_index *index, uint64_t *universe, uint32_t *bi
  * h_terms[h_q_offsets[q] .. h_q_offsets[q+1]) (k >= 1 distinct list ids).
  * The plan orders each query's terms by length (SvS), reserves intermediate
  * memory from the output-to-input bound, and uploads its tables once.
- * s4_batch_run executes every query: one persistent decode-fused launch per
- * chain level (all queries advance together), with small scan/compaction
- * kernels between levels; with use_graph != 0 the whole sequence is
- * captured once into a hipGraph and replayed on later runs.
+ * s4_batch_run executes every query: one persistent decode-fused launch in
+ * which each 128-value chunk of a query's shortest list is carried through
+ * the query's other lists in SvS order (no intermediate list is written),
+ * then scan and compaction kernels that place each query's results in
+ * order; with use_graph != 0 the whole sequence is captured once into a
+ * hipGraph and replayed on later runs.  Runs of one batch share its work
+ * counters, so they must not overlap: issue them on one stream (or order
+ * them); s4_batch_set_counting and s4_batch_free likewise only while no
+ * run of the batch is in flight.
  * Outputs (device): d_counts[nq] (u64), d_res_offsets[nq + 1] (u64, CSR),
  * d_results[results_cap] (u32, query q's docIDs at
  * d_results[d_res_offsets[q] ..]).  results_cap >= s4_batch_results_bound.
@@ -350,8 +355,8 @@ int s4_batch_run(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offsets, u
 int s4_batch_query_ticks(const s4_batch *batch, uint64_t *ticks, void *stream);
 
 /* Count algorithmic traffic in later runs of this batch (on != 0) or not
- * (the default: counting costs the kernels 7-16% of their time, so timed
- * runs leave it off).  A captured graph of the batch is dropped and
+ * (the default: counting slows the chunk kernels by 4-15%, so timed runs
+ * leave it off).  A captured graph of the batch is dropped and
  * re-captured on its next run. */
 int s4_batch_set_counting(s4_batch *batch, int on);
 

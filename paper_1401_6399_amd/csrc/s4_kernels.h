@@ -422,8 +422,8 @@ struct RSide {
 // Algorithmic bytes read by a wave (uniform): packed payload + width byte +
 // block offset + seed of every decoded block, staged skip-index entries,
 // raw values; and the number of blocks decoded.  Counted only when `on`:
-// the count (a width load and cross-lane reads per candidate group) costs
-// the chunk kernels, bound by instruction issue, 7-16% of their time.
+// the count (a width load and cross-lane reads per candidate group) slows
+// the chunk kernels, bound by instruction issue, by 4-15%.
 struct Traffic {
   uint64_t bytes = 0;
   uint64_t blocks = 0;
