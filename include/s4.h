@@ -153,8 +153,9 @@ int s4_list_info(const s4_list *list, uint64_t *n, uint32_t *nb, uint32_t *flags
 int s4_list_skip_index(const s4_list *list, uint32_t *bmax, uint32_t *seeds, void *stream);
 
 /* Decode the whole list into device buffer d_out[cap] (cap >= n) on
- * `stream`: unpack + D4 prefix sum fused in one kernel (Alg. 1), tail
- * copied.  S4_ERANGE if cap < n. */
+ * `stream`: unpack and the stream's prefix sum (its differential form,
+ * Sec. 5; a patched stream's exceptions added in between, Sec. 4.4) fused
+ * in one kernel (Alg. 1), tail copied.  S4_ERANGE if cap < n. */
 int s4_decode_dev(const s4_list *list, uint32_t *d_out, uint64_t cap, void *stream);
 
 /* s4_decode_dev with timing: the kernel is launched so that the caller's
