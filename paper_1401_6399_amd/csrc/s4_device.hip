@@ -226,10 +226,13 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
   auto row_of = [&](int p, uint32_t b) {
     return load_row(L.payload + uint32_t(__shfl(int(ol), int(min(4u * p + row, last)))), b, i);
   };
+  // a row's exception record for pass p (patched lists), read a pass
+  // ahead with the row's payload; clamped like the rows
+  auto rec_of = [&](int p) { return gbl(exc_records(L))[kbase + min(4u * p + row, last)]; };
   // one pass: patch, scan (carry across passes in c), transpose, store
-  auto pass = [&](int p, uint32_t d0[4], uint32_t d1[4]) {
+  auto pass = [&](int p, uint32_t d0[4], uint32_t d1[4], const uint4 x) {
     const uint32_t k0 = kbase + 4u * p;
-    if (PATCHED) patch_row(L, k0 + row, k0 + row < full_end, i, tb + row * kBlock, d0, d1);
+    if (PATCHED) patch_row_rec(L, x, k0 + row < full_end, i, tb + row * kBlock, d0, d1);
     uint32_t x0[4], x1[4];
     prefix_form<false, MODE>(d0, d1, c, x0, x1);
 #pragma unroll
@@ -255,7 +258,7 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
       unpack_row(row_of(p, b), b, i, d0[p], d1[p]);
     }
 #pragma unroll
-    for (int p = 0; p < P; ++p) pass(p, d0[p], d1[p]);
+    for (int p = 0; p < P; ++p) pass(p, d0[p], d1[p], make_uint4(0, 0, 0, 0));
   } else {
     // each pass's row loaded while the previous one is decoded: two passes
     // in flight, few registers, more waves resident (the patched kernels,
@@ -263,18 +266,21 @@ __device__ __forceinline__ void decode_wave_form(const DList &L, uint32_t first,
     // loads in flight)
     uint32_t bcur = width_of(0), bnext = 0;
     RowWords cur = row_of(0, bcur), next;
+    uint4 xcur = PATCHED ? rec_of(0) : make_uint4(0, 0, 0, 0), xnext = xcur;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
       if (p + 1 < P) {
         bnext = width_of(p + 1);
         next = row_of(p + 1, bnext);
+        if (PATCHED) xnext = rec_of(p + 1);
       }
       uint32_t d0[4], d1[4];
       unpack_row(cur, bcur, i, d0, d1);
-      pass(p, d0, d1);
+      pass(p, d0, d1, xcur);
       if (p + 1 < P) {
         cur = next;
         bcur = bnext;
+        xcur = xnext;
       }
     }
   }

@@ -240,14 +240,14 @@ __device__ __forceinline__ void prefix_deltas(uint32_t mode, const uint32_t d0[4
   }
 }
 
-// Patching (S4-FastPFOR, Sec. 4.4) of block k of a patched list, on the
-// block's 128 deltas staged in LDS v[0..127] in block order: the row's 16
+// Patching (S4-FastPFOR, Sec. 4.4) of the block of a patched list whose
+// exception record is x, on the block's 128 deltas staged in LDS
+// v[0..127] in block order: the row's 16
 // lanes take its exceptions e = i, i + 16, ...; each adds its high part,
 // d = b - b' bits read from the page's array for d at the block's running
 // index, above the b' low bits unpacked at its position.  Exceptions of a
 // block sit at distinct positions, so the adds never collide.
-__device__ __forceinline__ void patch_block(const DList &L, uint32_t k, uint32_t i, uint32_t *v) {
-  const uint4 x = gbl(exc_records(L))[k];
+__device__ __forceinline__ void patch_block_rec(const DList &L, const uint4 x, uint32_t i, uint32_t *v) {
   const uint32_t c = x.x & 0xFFu, d = (x.x >> 8) & 0x3Fu, bp = (x.x >> 16) & 0x3Fu;
   const uint32_t *xd = exc_data(L);
   const gconst<uint8_t> pos = gbl(reinterpret_cast<const uint8_t *>(xd)) + x.y;
@@ -262,17 +262,19 @@ __device__ __forceinline__ void patch_block(const DList &L, uint32_t k, uint32_t
 }
 
 // Stage a row's deltas (positions 8i .. 8i + 7) in its LDS slice v, patch
-// them, and load them back.  Whole-wave call (it synchronises the wave);
-// only rows with `active` touch their slice.
-__device__ __forceinline__ void patch_row(const DList &L, uint32_t k, bool active, uint32_t i, uint32_t *v,
-                                          uint32_t d0[4], uint32_t d1[4]) {
+// them with the exceptions of the block whose record rec() gives, and load
+// them back.  Whole-wave call (it synchronises the wave); only rows with
+// `active` touch their slice or call rec().
+template <class Rec>
+__device__ __forceinline__ void patch_row_with(const DList &L, Rec rec, bool active, uint32_t i, uint32_t *v,
+                                               uint32_t d0[4], uint32_t d1[4]) {
   u32x4 *t = reinterpret_cast<u32x4 *>(v + 8u * i);
   if (active) {
     t[0] = u32x4{d0[0], d0[1], d0[2], d0[3]};
     t[1] = u32x4{d1[0], d1[1], d1[2], d1[3]};
   }
   wave_sync();
-  if (active) patch_block(L, k, i, v);
+  if (active) patch_block_rec(L, rec(), i, v);
   wave_sync();
   if (active) {
     const u32x4 a = t[0], b = t[1];
@@ -280,6 +282,19 @@ __device__ __forceinline__ void patch_row(const DList &L, uint32_t k, bool activ
     d1[0] = b.x; d1[1] = b.y; d1[2] = b.z; d1[3] = b.w;
   }
   wave_sync();
+}
+
+// For block k of L, its record read once the deltas are staged.
+__device__ __forceinline__ void patch_row(const DList &L, uint32_t k, bool active, uint32_t i, uint32_t *v,
+                                          uint32_t d0[4], uint32_t d1[4]) {
+  patch_row_with(L, [&] { return uint4(gbl(exc_records(L))[k]); }, active, i, v, d0, d1);
+}
+
+// For a row whose block's record x was loaded ahead (a pass ahead in the
+// decode kernels), which leaves the patch one memory round trip, not two.
+__device__ __forceinline__ void patch_row_rec(const DList &L, const uint4 x, bool active, uint32_t i, uint32_t *v,
+                                              uint32_t d0[4], uint32_t d1[4]) {
+  patch_row_with(L, [&] { return x; }, active, i, v, d0, d1);
 }
 
 // Feature set of a chunk-pipeline instantiation: the kinds of list it can
