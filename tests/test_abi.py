@@ -202,3 +202,14 @@ def test_decode_lists_stream_count_checked_before_any_device_work():
     assert lib.s4_decode_lists_dev(None, None, None, 0, 8, None) == 0
     for bad in (0, 2, 3, 4, 5, 6, 7, 9):
         assert lib.s4_decode_lists_dev(None, None, None, 0, bad, None) == s4.EINVAL, bad
+
+
+def test_batch_calls_refuse_a_null_batch():
+    """The batch entry points that take a handle check it before any device
+    work."""
+    import ctypes
+    lib = s4.require_library()
+    assert lib.s4_batch_set_counting(None, 1) == s4.EINVAL
+    assert lib.s4_batch_set_counting(None, 0) == s4.EINVAL
+    b, k = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    assert lib.s4_batch_traffic(None, ctypes.byref(b), ctypes.byref(k), None) == s4.EINVAL
