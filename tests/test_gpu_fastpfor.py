@@ -56,6 +56,26 @@ def test_decode_patched(gpu, mode, n):
         assert np.array_equal(got, oracle.decode(enc))
 
 
+@pytest.mark.parametrize("mode", [oracle.D4, oracle.D1])
+def test_decode_patched_large(gpu, mode):
+    """A patched list long enough (2^15 full blocks and a ragged tail) for
+    the per-list launch to take 4 passes per wave, where each pass's
+    exception records are read a pass ahead."""
+    n = (1 << 22) + 77
+    rng = np.random.default_rng(900 + mode)
+    gaps = rng.geometric(0.3, size=n).astype(np.uint64)
+    k = n // 1000
+    gaps[rng.integers(0, n, size=k)] += np.uint64(1) << rng.integers(4, 19, size=k).astype(np.uint64)
+    sparse_outliers = np.cumsum(gaps)
+    assert sparse_outliers[-1] < 1 << 32
+    for x in (sparse_outliers.astype(np.uint32),
+              workloads.sorted_list(workloads.CLUSTERED, 901 + mode, 1 << 26, n)):
+        enc = gpu.encode(x, mode, patched=True)
+        got = gpu.DeviceList.upload(enc).decode().cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, x)
+        assert np.array_equal(got, oracle.decode(enc))
+
+
 @pytest.mark.parametrize("mode", FORMS)
 def test_patched_skip_index_and_blocks(gpu, mode):
     import torch
