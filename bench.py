@@ -4,8 +4,11 @@
 Headline workload (bulk decode): 256 lists, lengths floor(2^u), u ~ U[12, 24],
 universe [0, 2^26), even lists uniform and odd lists clustered, encoded as
 S4-BP128-D4 and resident in HBM; one step decodes every list with one
-kernel launch per list (launches spread over forked streams, the whole step
-replayed as one hipGraph).  value = decoded integers per second (Gint/s).
+kernel launch per list, each a dispatch packet the library writes into one of
+its four HSA queues (s4_aql_plan; steps separated by barrier packets).
+value = decoded integers per second (Gint/s), end to end.  The same
+launches through HIP (forked streams, the step replayed as one hipGraph) are
+reported beside it.
 
 Also reported:
   roofline      the decode kernel's algorithmic bytes (width bytes + packed
@@ -52,6 +55,9 @@ def parse():
     ap.add_argument("--decode-only", action="store_true", help="skip the batched and CPU legs (for profiling)")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched leg and print its JSON (for profiling)")
+    ap.add_argument("--no-aql", action="store_true",
+                    help="time the per-list step through HIP only (for counter passes: the library's own queues "
+                         "run launches concurrently, so counters cannot be read per dispatch there)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB three times with a plain copy kernel (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -397,6 +403,29 @@ def hybrid(s4, workloads, torch, index, buf, soffs, nq, plain):
     return res
 
 
+def run_steps(plan, steps):
+    """Host wall time (ms) of `steps` per-list decodes on the library's
+    queues, in runs of at most 64 steps."""
+    t = 0.0
+    while steps > 0:
+        k = min(steps, 64)
+        t += plan.run(k)
+        steps -= k
+    return t
+
+
+def check_decoded(out, lists, flat, offs):
+    """Every list's decoded values equal its input (outputs laid out as
+    build_bulk lays them out)."""
+    import numpy as np
+    host = out.cpu().numpy().view(np.uint32)
+    p = 0
+    for i, l in enumerate(lists):
+        if not np.array_equal(host[p: p + l.n], flat[int(offs[i]): int(offs[i + 1])]):
+            raise SystemExit(f"decoded list {i} differs from its input")
+        p += (l.n + 63) // 64 * 64 + 64
+
+
 def counted_traffic(b):
     """Algorithmic traffic of one extra, untimed run with counting on (the
     timed runs leave it off: it slows the chunk kernels by 4-15%)."""
@@ -563,10 +592,10 @@ def main():
     stream = torch.cuda.Stream()
     # headline: one launch per list, forked over streams, replayed as a graph
     torch.cuda.synchronize()
-    ms, g = time_graph(torch, lambda: s4.decode_lists(lists, outs, nstreams=args.nstreams), stream,
-                       args.steps, args.warmup)
-    value = total / (ms / 1e3) / 1e9
-    log(f"per-list launches: {ms:.3f} ms/step, {value:.1f} Gint/s")
+    graph_ms, g = time_graph(torch, lambda: s4.decode_lists(lists, outs, nstreams=args.nstreams), stream,
+                             args.steps, args.warmup)
+    log(f"per-list launches through HIP (graph): {graph_ms:.3f} ms/step, "
+        f"{total / (graph_ms / 1e3) / 1e9:.1f} Gint/s")
     # diagnostic only (never `value`): the same replays with the stream held
     # until the host has queued them all, i.e. the device's time per step
     # when launching the 256-kernel graph does not limit it
@@ -574,6 +603,22 @@ def main():
     gated_ms, host_ms = time_graph_gated(torch, s4, g, stream, min(args.steps, 30))
     log(f"per-list, device time with launches queued ahead: {gated_ms:.3f} ms/step; "
         f"host time to launch one replay: {host_ms:.3f} ms")
+
+    # headline: the same launches written by the library into its own queues
+    if args.no_aql:
+        ms = graph_ms
+        launch = f"one k_decode launch per list over {args.nstreams} forked streams, hipGraph replay"
+    else:
+        plan_q = s4.AqlDecodePlan(lists, outs)
+        run_steps(plan_q, args.warmup)
+        out.fill_(-1)
+        ms = run_steps(plan_q, args.steps) / args.steps
+        check_decoded(out, lists, flat, offs)
+        del plan_q
+        launch = ("one k_decode dispatch per list, written by the library into four HSA queues "
+                  "(s4_aql_plan); steps separated by barrier packets")
+    value = total / (ms / 1e3) / 1e9
+    log(f"per-list launches ({launch}): {ms:.3f} ms/step, {value:.1f} Gint/s (outputs checked)")
 
     # roofline of the decode kernel: events around each launch
     dur = per_launch_ms(torch, s4, lists, outs, stream)
@@ -589,13 +634,8 @@ def main():
     single = total / (ms1 / 1e3) / 1e9
     log(f"single launch: {ms1:.3f} ms/step, {single:.1f} Gint/s, {abytes.sum() / (ms1 / 1e3) / 1e9:.0f} GB/s")
 
-    # correctness of what was timed
-    host = out.cpu().numpy().view(np.uint32)
-    p = 0
-    for i, l in enumerate(lists):
-        if not np.array_equal(host[p: p + l.n], flat[int(offs[i]): int(offs[i + 1])]):
-            raise SystemExit(f"decoded list {i} differs from its input")
-        p += (l.n + 63) // 64 * 64 + 64
+    # correctness of the last decode timed (the single launch)
+    check_decoded(out, lists, flat, offs)
 
     # counter-measured HBM bytes per launch, valid only for the kernel
     # source the counters were taken on
@@ -626,7 +666,7 @@ def main():
             "lists": len(lists),
             "total_ints": total,
             "bits_per_int": round(bits, 3),
-            "launch": f"one k_decode launch per list over {args.nstreams} forked streams, hipGraph replay",
+            "launch": launch,
         },
         "roofline": {
             "bound": "hbm",
@@ -640,11 +680,12 @@ def main():
             "bytes_per_launch": round(float(abytes.mean()), 1),
             "frac_lists_ge_2p22": round(achieved_big / HBM_PEAK_GBS, 4),
         },
-        "per_list_device": {"ms_per_step": round(gated_ms, 4), "gint_s": round(total / (gated_ms / 1e3) / 1e9, 2),
-                            "host_ms_per_launch_of_step": round(host_ms, 4),
-                            "note": "same graph replays with the stream held until the host has queued them: the "
-                                    "device's time per step; `value` is end to end and is bounded by whichever "
-                                    "of the two is slower"},
+        "per_list_hip_graph": {"ms_per_step": round(graph_ms, 4), "gint_s": round(total / (graph_ms / 1e3) / 1e9, 2),
+                               "device_ms_per_step": round(gated_ms, 4),
+                               "host_ms_per_launch_of_step": round(host_ms, 4),
+                               "note": f"the same launches through HIP over {args.nstreams} forked streams, replayed "
+                                       "as a hipGraph: end to end, and with the stream held until the host has "
+                                       "queued every replay (the device's time per step)"},
         "single_launch": {"value": round(single, 2), "unit": "Gint/s", "ms_per_step": round(ms1, 4),
                           "frac": round(abytes.sum() / (ms1 / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "whole_job_hbm_frac": round(abytes.sum() / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),

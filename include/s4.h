@@ -183,6 +183,29 @@ int s4_decode_blocks_dev(const s4_list *list, uint32_t first, uint32_t count, ui
 int s4_decode_lists_dev(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
                         uint32_t count, uint32_t nstreams, void *stream);
 
+/* The per-list decode of s4_decode_lists_dev (the same kernel, one launch
+ * per list, Alg. 1 fused with the prefix) dispatched by the library itself:
+ * each launch is a dispatch packet written into one of four HSA queues the
+ * library owns (lists spread over them by size), with no barrier or fence
+ * between the lists of a step (they are independent); barrier packets end
+ * each step on every queue and make the next step wait for all of them, so
+ * steps never overlap, and a launch costs the host one packet instead of a
+ * runtime launch call.  A plan holds the
+ * packets' argument blocks (coherent pinned host memory, built once); the
+ * lists and outputs (16-byte aligned, capacity caps[i] >= n) must outlive
+ * it.  Plain lists only: a patched list is S4_EINVAL.  The queue is not
+ * ordered with HIP streams: s4_aql_plan_run needs the lists and outputs
+ * idle (no HIP work on them in flight) and returns once `steps` (1..64) decodes of
+ * every list are complete, with the host wall time from its first packet
+ * to completion in *elapsed_ns (may be null); S4_EDEVICE if the queue
+ * reports an error or the work does not complete within 20 s.  The
+ * dispatcher serves the device it is first used on. */
+typedef struct s4_aql_plan s4_aql_plan;
+int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
+                       uint32_t count, s4_aql_plan **out);
+int s4_aql_plan_run(s4_aql_plan *plan, uint32_t steps, uint64_t *elapsed_ns);
+int s4_aql_plan_free(s4_aql_plan *plan);
+
 /* A reusable multi-list decode: one kernel launch decodes every list of
  * the plan (workgroups are laid out over the concatenated blocks of all
  * lists).  The plan holds a device table of the lists and output

@@ -79,6 +79,9 @@ SIGNATURES = {
                                    ctypes.POINTER(_vp)]),
     "s4_decode_plan_run": (_i, [_vp, _vp]),
     "s4_decode_plan_free": (_i, [_vp]),
+    "s4_aql_plan_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u64p, _u32, ctypes.POINTER(_vp)]),
+    "s4_aql_plan_run": (_i, [_vp, _u32, _u64p]),
+    "s4_aql_plan_free": (_i, [_vp]),
     "s4_spin_dev": (_i, [_u64, _vp]),
     "s4_intersect_scratch_bytes": (_sz, [_u64, _u64]),
     "s4_intersect": (_i, [_vp, _vp, _vp, _u64, _vp, _vp, _sz, _vp]),
@@ -339,6 +342,37 @@ class DecodePlan:
         try:
             if self.h:
                 require_library().s4_decode_plan_free(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+class AqlDecodePlan:
+    """Per-list decode, one dispatch per list, on the library's own queue
+    (s4_aql_plan).  Not ordered with torch's streams: the device is
+    synchronised before each call, and run() returns when done."""
+
+    def __init__(self, lists, outs):
+        import torch
+        hs, ptrs, caps = _out_arrays(lists, outs)
+        self._keep = (lists, outs)
+        self.h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(require_library().s4_aql_plan_create(hs, ptrs, _ptr(caps, ctypes.c_uint64), len(lists),
+                                                    ctypes.byref(self.h)), "s4_aql_plan_create")
+
+    def run(self, steps=1):
+        """Decode every list `steps` times; returns the host wall time in ms."""
+        import torch
+        torch.cuda.synchronize()
+        ns = ctypes.c_uint64(0)
+        _check(require_library().s4_aql_plan_run(self.h, int(steps), ctypes.byref(ns)), "s4_aql_plan_run")
+        return ns.value / 1e6
+
+    def __del__(self):
+        try:
+            if self.h:
+                require_library().s4_aql_plan_free(self.h)
                 self.h = ctypes.c_void_p()
         except Exception:
             pass

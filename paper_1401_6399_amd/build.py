@@ -10,7 +10,10 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libs4.so")
 
-SOURCES = ["s4_format.cpp", "s4_device.hip", "s4_batch.hip", "s4_hybrid.hip", "s4_serve.cpp"]
+SOURCES = ["s4_format.cpp", "s4_device.hip", "s4_batch.hip", "s4_hybrid.hip", "s4_serve.cpp", "s4_aql.cpp"]
+
+# the per-list dispatcher writes packets into an HSA queue of its own
+LINK_FLAGS = ["-L/opt/rocm/lib", "-lhsa-runtime64"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
@@ -34,7 +37,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp] + srcs
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp] + srcs + LINK_FLAGS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

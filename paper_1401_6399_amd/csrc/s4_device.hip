@@ -739,30 +739,24 @@ static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len
 }
 
 template <int P, bool PK>
-static void launch_decode_k(const DList &L, uint32_t first, uint32_t full_end, uint32_t block_waves, uint32_t waves,
-                            uint32_t form, uint32_t *d_out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+static void launch_decode_k(const DecodeLaunch &d, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+  const DecodeArgs &a = d.a;
   if (ev0)
-    hipExtLaunchKernelGGL((k_decode<P, PK>), dim3((waves + 3) / 4), dim3(256), 0, stream, ev0, ev1, 0, L.widths,
-                          L.offs, L.seeds, L.payload, d_out, first, full_end, block_waves, form, L.tail, L.nb);
+    hipExtLaunchKernelGGL((k_decode<P, PK>), dim3(d.workgroups), dim3(256), 0, stream, ev0, ev1, 0, a.widths, a.offs,
+                          a.seeds, a.payload, a.out, a.first, a.full_end, a.block_waves, a.form, a.tail, a.nb);
   else
-    hipLaunchKernelGGL((k_decode<P, PK>), dim3((waves + 3) / 4), dim3(256), 0, stream, L.widths, L.offs, L.seeds,
-                       L.payload, d_out, first, full_end, block_waves, form, L.tail, L.nb);
+    hipLaunchKernelGGL((k_decode<P, PK>), dim3(d.workgroups), dim3(256), 0, stream, a.widths, a.offs, a.seeds,
+                       a.payload, a.out, a.first, a.full_end, a.block_waves, a.form, a.tail, a.nb);
 }
 template <int P>
-static void launch_decode(const DList &L, uint32_t first, uint32_t full_end, uint32_t block_waves, uint32_t waves,
-                          uint32_t form, uint32_t *d_out, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
-  if (is_patched(L))
-    launch_decode_k<P, true>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1);
+static void launch_decode(const DecodeLaunch &d, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1) {
+  if (d.patched)
+    launch_decode_k<P, true>(d, stream, ev0, ev1);
   else
-    launch_decode_k<P, false>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1);
+    launch_decode_k<P, false>(d, stream, ev0, ev1);
 }
 
-int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream) {
-  return decode_range_timed(L, first, count, d_out, stream, nullptr, nullptr);
-}
-
-int decode_range_timed(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream,
-                       hipEvent_t ev0, hipEvent_t ev1) {
+bool plan_decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, DecodeLaunch *d) {
   const uint32_t end = first + count;
   const uint32_t full = end > L.nb ? (L.nb > first ? L.nb - first : 0) : count;
   // blocks per wave (4 P): the largest P that still gives ~8 waves per CU
@@ -772,14 +766,38 @@ int decode_range_timed(const DList &L, uint32_t first, uint32_t count, uint32_t 
   const uint32_t block_waves = (full + 4 * P - 1) / (4 * P);
   const bool tail = end > L.nb && L.t > 0;
   const uint32_t waves = block_waves + (tail ? 1 : 0);
-  if (waves == 0) return S4_OK;
-  const uint32_t full_end = first + full;
-  const uint32_t form = L.mode | (is_patched(L) ? kDecodePatched : 0u) | (tail ? kDecodeTail : 0u) | (L.t << 16);
+  if (waves == 0) return false;
+  d->P = P;
+  d->patched = is_patched(L);
+  d->workgroups = (waves + 3) / 4;
+  d->a = DecodeArgs{L.widths, L.offs, L.seeds, L.payload, d_out, first, first + full, block_waves,
+                    L.mode | (d->patched ? kDecodePatched : 0u) | (tail ? kDecodeTail : 0u) | (L.t << 16),
+                    L.tail, L.nb};
+  return true;
+}
+
+const void *decode_kernel_host_address(uint32_t P, bool patched) {
   switch (P) {
-    case 8: launch_decode<8>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1); break;
-    case 4: launch_decode<4>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1); break;
-    case 2: launch_decode<2>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1); break;
-    default: launch_decode<1>(L, first, full_end, block_waves, waves, form, d_out, stream, ev0, ev1); break;
+    case 8: return patched ? reinterpret_cast<const void *>(&k_decode<8, true>) : reinterpret_cast<const void *>(&k_decode<8, false>);
+    case 4: return patched ? reinterpret_cast<const void *>(&k_decode<4, true>) : reinterpret_cast<const void *>(&k_decode<4, false>);
+    case 2: return patched ? reinterpret_cast<const void *>(&k_decode<2, true>) : reinterpret_cast<const void *>(&k_decode<2, false>);
+    default: return patched ? reinterpret_cast<const void *>(&k_decode<1, true>) : reinterpret_cast<const void *>(&k_decode<1, false>);
+  }
+}
+
+int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream) {
+  return decode_range_timed(L, first, count, d_out, stream, nullptr, nullptr);
+}
+
+int decode_range_timed(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream,
+                       hipEvent_t ev0, hipEvent_t ev1) {
+  DecodeLaunch d;
+  if (!plan_decode_range(L, first, count, d_out, &d)) return S4_OK;
+  switch (d.P) {
+    case 8: launch_decode<8>(d, stream, ev0, ev1); break;
+    case 4: launch_decode<4>(d, stream, ev0, ev1); break;
+    case 2: launch_decode<2>(d, stream, ev0, ev1); break;
+    default: launch_decode<1>(d, stream, ev0, ev1); break;
   }
   S4_HIP(hipGetLastError());
   return S4_OK;

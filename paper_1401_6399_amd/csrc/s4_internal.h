@@ -123,6 +123,36 @@ inline bool hyb_is_bitmap(uint64_t n, uint64_t universe, uint32_t gap) {
 int build_bitmaps(Upload &u, uint64_t universe, hipStream_t stream, void **mem, std::vector<DList> *descs,
                   uint64_t *bitmap_bytes, uint64_t *select_bytes);
 // Decode blocks [first, first + count) of L into d_out (index nb = tail).
+// k_decode's arguments, in the kernel's order and layout (its kernel
+// argument segment: 68 bytes, no hidden arguments).
+struct DecodeArgs {
+  const uint8_t *widths;
+  const uint32_t *offs;
+  const uint4 *seeds;
+  const uint32_t *payload;
+  uint32_t *out;
+  uint32_t first, full_end, block_waves, form;
+  const uint32_t *tail;
+  uint32_t nb;
+};
+static_assert(offsetof(DecodeArgs, out) == 32 && offsetof(DecodeArgs, first) == 40 &&
+                  offsetof(DecodeArgs, tail) == 56 && offsetof(DecodeArgs, nb) == 64,
+              "k_decode argument layout");
+constexpr uint32_t kDecodeArgBytes = 68;
+// One k_decode launch: blocks per wave 4 P, kernel for patched lists or not,
+// workgroups of 256 lanes, arguments.
+struct DecodeLaunch {
+  uint32_t P = 1;
+  bool patched = false;
+  uint32_t workgroups = 0;
+  DecodeArgs a{};
+};
+// The launch that decodes blocks [first, first + count) of L into d_out (block
+// nb the tail); false when there is nothing to decode.
+bool plan_decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, DecodeLaunch *out);
+// Host address of the k_decode instantiation a launch names (for lookups of
+// the loaded kernel).
+const void *decode_kernel_host_address(uint32_t P, bool patched);
 int decode_range(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream);
 // The same, the kernel launched so that ev0 / ev1 record its start and end.
 int decode_range_timed(const DList &L, uint32_t first, uint32_t count, uint32_t *d_out, hipStream_t stream,
