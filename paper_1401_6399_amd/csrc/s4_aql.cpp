@@ -31,7 +31,7 @@ constexpr uint32_t kArgStride = 128;          // bytes per dispatch's argument b
 constexpr double kWaitLimitSeconds = 20.0;    // a step never takes this long
 constexpr uint32_t kQueueSlots = 4096;
 constexpr uint32_t kQueues = 4;               // one queue processes about one dispatch per 4 us
-static_assert(kQueues <= 5, "a step's opening barrier packet waits on every queue (5 signals at most)");
+static_assert(kQueues >= 1 && kQueues <= 16, "queues per device");
 constexpr uint32_t kMaxSteps = 64;            // signals kept per queue
 
 struct KernelInfo {
@@ -286,7 +286,7 @@ int s4_aql_plan_run(s4_aql_plan *plan, uint32_t steps, uint64_t *elapsed_ns) {
   std::lock_guard<std::mutex> lock(g_mu);
   if (!g_state.ready) return fail(S4_EINVAL, "dispatcher not set up");
   for (uint32_t q = 0; q < kQueues; ++q)
-    if (plan->per_queue[q].size() + 2 >= g_state.queues[q]->size)
+    if (plan->per_queue[q].size() + 2 + kQueues / 5 >= g_state.queues[q]->size)
       return fail(S4_EINVAL, "a step needs more packets than a queue holds");
   for (uint32_t s = 0; s < steps; ++s)
     for (uint32_t q = 0; q < kQueues; ++q) hsa_signal_store_relaxed(g_state.step_done[s][q], 1);
@@ -298,14 +298,16 @@ int s4_aql_plan_run(s4_aql_plan *plan, uint32_t steps, uint64_t *elapsed_ns) {
       const uint64_t mask = qu->size - 1;
       uint64_t i;
       int rc;
-      if (s > 0) {
-        // wait for every queue's previous step
+      // wait for every queue's previous step (a barrier packet waits on
+      // at most five signals: as many packets as the queues need)
+      for (uint32_t j0 = 0; s > 0 && j0 < kQueues; j0 += 5) {
         rc = next_slot(qu, t0, &i);
         if (rc) return rc;
         auto *bp = reinterpret_cast<hsa_barrier_and_packet_t *>(ring + (i & mask) * 64);
         bp->reserved0 = 0;
         bp->reserved1 = 0;
-        for (uint32_t j = 0; j < 5; ++j) bp->dep_signal[j].handle = j < kQueues ? g_state.step_done[s - 1][j].handle : 0;
+        for (uint32_t j = 0; j < 5; ++j)
+          bp->dep_signal[j].handle = j0 + j < kQueues ? g_state.step_done[s - 1][j0 + j].handle : 0;
         bp->reserved2 = 0;
         bp->completion_signal.handle = 0;
         __atomic_store_n(reinterpret_cast<uint32_t *>(bp),
