@@ -1,9 +1,10 @@
 // Per-list decode dispatched on queues of the library's own: one kernel
 // dispatch packet per list (the k_decode launch s4_decode_lists_dev would
 // make), written straight into HSA user queues.  The lists are spread over
-// kQueues queues by bytes (largest first); a queue's packets carry no
-// barrier and no fence, since the lists of a step are independent; each
-// queue ends a step with a barrier packet that signals, and starts the next
+// kQueues queues by bytes (largest first), each queue alternating its large
+// and small lists; a queue's packets carry no barrier and no fence, since
+// the lists of a step are independent; each queue ends a step with a
+// barrier packet that signals, and starts the next
 // one with a barrier packet waiting for every queue's signal, so steps do
 // not overlap.  The kernels are the ones HIP loaded for this library, found
 // through the AMD loader extension; their argument blocks are built once
@@ -275,6 +276,18 @@ int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, con
       if (load[q] < load[best]) best = q;
     load[best] += uint64_t(d.a.full_end - d.a.first) * 512u + 4096u;
     p->per_queue[best].push_back({k.object, k.group, d.workgroups * 256u, a});
+  }
+  // within a queue, alternate its largest and smallest remaining lists, so
+  // small dispatches are issued while large kernels run
+  for (auto &v : p->per_queue) {
+    std::vector<s4_aql_plan::Dispatch> mixed;
+    mixed.reserve(v.size());
+    size_t lo = 0, hi = v.size();
+    while (lo < hi) {
+      mixed.push_back(v[lo++]);
+      if (lo < hi) mixed.push_back(v[--hi]);
+    }
+    v.swap(mixed);
   }
   for (uint32_t i = 0; i < count; ++i) p->ints += lists[i]->n;
   *out = p;
