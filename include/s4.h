@@ -190,20 +190,46 @@ int s4_decode_lists_dev(const s4_list *const *lists, uint32_t *const *d_outs, co
  * between the lists of a step (they are independent); barrier packets end
  * each step on every queue and make the next step wait for all of them, so
  * steps never overlap, and a launch costs the host one packet instead of a
- * runtime launch call.  A plan holds the
- * packets' argument blocks (coherent pinned host memory, built once); the
- * lists and outputs (16-byte aligned, capacity caps[i] >= n) must outlive
- * it.  Plain lists only: a patched list is S4_EINVAL.  The queue is not
- * ordered with HIP streams: s4_aql_plan_run needs the lists and outputs
- * idle (no HIP work on them in flight) and returns once `steps` (1..64) decodes of
- * every list are complete, with the host wall time from its first packet
- * to completion in *elapsed_ns (may be null); S4_EDEVICE if the queue
- * reports an error or the work does not complete within 20 s.  The
- * dispatcher serves the device it is first used on. */
+ * runtime launch call.  Every run opens with a barrier packet whose
+ * system-scope acquire invalidates the device caches, so lists and
+ * outputs written through HIP before the run are seen.  A plan holds the
+ * packets and their argument blocks (coherent pinned host memory), built
+ * once; the lists and outputs (16-byte aligned, capacity caps[i] >= n)
+ * must outlive it.  Plain lists only: a patched list is S4_EINVAL.  The
+ * dispatcher serves the device it is first used on.
+ *
+ * s4_aql_plan_run is host-synchronous and not ordered with HIP streams: it
+ * needs the lists and outputs idle (no HIP work on them in flight) and
+ * returns once `steps` (1..64) decodes of every list are complete, with the
+ * host wall time from its first packet to completion in *elapsed_ns (may
+ * be null).  It is the form the throughput of the per-list decode is timed
+ * with: the host thread writes the packets of every step ahead of the
+ * device and nothing else stands between them.
+ * s4_aql_plan_enqueue is the stream-ordered form: it returns at once; the
+ * run starts after the work already enqueued on `stream` and the stream's
+ * later work waits for its completion (a host function of the stream
+ * submits the packets and waits for the last step; the caller's thread
+ * never blocks).  A failure of such a run is reported by the next
+ * s4_aql_plan_status (S4_OK while none has failed); the plan must not be
+ * freed while a run is enqueued (S4_EINVAL).
+ * s4_aql_plan_profile runs `steps` steps like s4_aql_plan_run with
+ * dispatch profiling enabled on the queues and a completion signal on every
+ * dispatch, and writes each dispatch's start and end on the device
+ * (nanoseconds after the earliest start of the run) to start_ns / end_ns
+ * [s * count + i] for list i of step s (0 for a list with nothing to
+ * decode); for measurement, not for timed runs.
+ * Every run returns S4_EDEVICE if a queue reports an error or the work does
+ * not complete within 20 s; the dispatcher then refuses every later run
+ * (packets may still be queued) and keeps the argument blocks of every
+ * plan for the rest of the process. */
 typedef struct s4_aql_plan s4_aql_plan;
 int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
                        uint32_t count, s4_aql_plan **out);
 int s4_aql_plan_run(s4_aql_plan *plan, uint32_t steps, uint64_t *elapsed_ns);
+int s4_aql_plan_enqueue(s4_aql_plan *plan, uint32_t steps, void *stream);
+int s4_aql_plan_status(s4_aql_plan *plan);
+int s4_aql_plan_profile(s4_aql_plan *plan, uint32_t steps, uint64_t *start_ns, uint64_t *end_ns,
+                        uint64_t *elapsed_ns);
 int s4_aql_plan_free(s4_aql_plan *plan);
 
 /* A reusable multi-list decode: one kernel launch decodes every list of

@@ -81,6 +81,9 @@ SIGNATURES = {
     "s4_decode_plan_free": (_i, [_vp]),
     "s4_aql_plan_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u64p, _u32, ctypes.POINTER(_vp)]),
     "s4_aql_plan_run": (_i, [_vp, _u32, _u64p]),
+    "s4_aql_plan_enqueue": (_i, [_vp, _u32, _vp]),
+    "s4_aql_plan_status": (_i, [_vp]),
+    "s4_aql_plan_profile": (_i, [_vp, _u32, _u64p, _u64p, _u64p]),
     "s4_aql_plan_free": (_i, [_vp]),
     "s4_spin_dev": (_i, [_u64, _vp]),
     "s4_intersect_scratch_bytes": (_sz, [_u64, _u64]),
@@ -348,14 +351,16 @@ class DecodePlan:
 
 
 class AqlDecodePlan:
-    """Per-list decode, one dispatch per list, on the library's own queue
-    (s4_aql_plan).  Not ordered with torch's streams: the device is
-    synchronised before each call, and run() returns when done."""
+    """Per-list decode, one dispatch per list, on the library's own queues
+    (s4_aql_plan).  run() is host-synchronous and not ordered with torch's
+    streams (the device is synchronised before it); enqueue() orders a run
+    after the work of a stream and returns at once."""
 
     def __init__(self, lists, outs):
         import torch
         hs, ptrs, caps = _out_arrays(lists, outs)
         self._keep = (lists, outs)
+        self.count = len(lists)
         self.h = ctypes.c_void_p()
         torch.cuda.synchronize()
         _check(require_library().s4_aql_plan_create(hs, ptrs, _ptr(caps, ctypes.c_uint64), len(lists),
@@ -368,6 +373,30 @@ class AqlDecodePlan:
         ns = ctypes.c_uint64(0)
         _check(require_library().s4_aql_plan_run(self.h, int(steps), ctypes.byref(ns)), "s4_aql_plan_run")
         return ns.value / 1e6
+
+    def enqueue(self, steps=1, stream=None):
+        """Decode every list `steps` times after the work already on `stream`
+        (torch's current stream by default); later work on the stream waits
+        for it."""
+        _check(require_library().s4_aql_plan_enqueue(self.h, int(steps), _stream(stream)), "s4_aql_plan_enqueue")
+
+    def status(self):
+        """Raise if an enqueued run has failed."""
+        _check(require_library().s4_aql_plan_status(self.h), "s4_aql_plan_status")
+
+    def profile(self, steps=1):
+        """One profiled run: per-list device start and end (ns after the
+        run's first dispatch started), arrays [steps, count], and the host
+        wall time in ms."""
+        import torch
+        torch.cuda.synchronize()
+        st = np.zeros(steps * self.count, np.uint64)
+        en = np.zeros(steps * self.count, np.uint64)
+        ns = ctypes.c_uint64(0)
+        _check(require_library().s4_aql_plan_profile(self.h, int(steps), _ptr(st, ctypes.c_uint64),
+                                                     _ptr(en, ctypes.c_uint64), ctypes.byref(ns)),
+               "s4_aql_plan_profile")
+        return st.reshape(steps, self.count), en.reshape(steps, self.count), ns.value / 1e6
 
     def __del__(self):
         try:

@@ -7,11 +7,19 @@
 // barrier packet that signals, and starts the next
 // one with a barrier packet waiting for every queue's signal, so steps do
 // not overlap.  The kernels are the ones HIP loaded for this library, found
-// through the AMD loader extension; their argument blocks are built once
-// per plan in coherent pinned host memory.
+// through the AMD loader extension; their argument blocks and packet images
+// are built once per plan (arguments in coherent pinned host memory), and a
+// step copies the images into the rings.  Every run opens with a barrier
+// packet whose system-scope acquire invalidates the caches before the first
+// kernel reads arguments or lists written through other queues.  A run can
+// be timed per dispatch (profiling enabled on the queues, one completion
+// signal per dispatch), or enqueued behind the work of a HIP stream (a host
+// function of that stream submits it and returns when it is complete).
 #include <hsa/hsa.h>
 #include <hsa/hsa_ext_amd.h>
 #include <hsa/hsa_ven_amd_loader.h>
+
+#include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
@@ -42,8 +50,13 @@ struct KernelInfo {
 
 struct AqlState {
   bool ready = false;
+  // a run stopped with packet slots reserved or packets in flight: the
+  // queues may be stalled and argument blocks still referenced, so no
+  // further run is accepted and no plan's argument blocks are freed
+  bool broken = false;
   int device = -1;
   hsa_agent_t agent{};
+  uint64_t ts_hz = 0;  // HSA system timestamp frequency (dispatch profiling)
   hsa_queue_t *queues[kQueues] = {};
   hsa_signal_t step_done[kMaxSteps][kQueues] = {};  // queue q finished step s
   KernelInfo kernels[4];  // k_decode<P, false>, P = 1, 2, 4, 8
@@ -155,6 +168,9 @@ int ensure_queue() {
     for (auto &sig : row)
       if (hsa_signal_create(1, 0, nullptr, &sig) != HSA_STATUS_SUCCESS)
         return fail(S4_EDEVICE, "hsa_signal_create failed");
+  if (hsa_system_get_info(HSA_SYSTEM_INFO_TIMESTAMP_FREQUENCY, &g_state.ts_hz) != HSA_STATUS_SUCCESS ||
+      g_state.ts_hz == 0)
+    return fail(S4_EDEVICE, "HSA timestamp frequency query failed");
   g_state.agent = as.match;
   g_state.device = dev;
   g_state.ready = true;
@@ -198,15 +214,46 @@ using Clock = std::chrono::steady_clock;
 
 double seconds_since(Clock::time_point t0) { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
-// Reserve the next packet slot, waiting (bounded) until the queue has room.
+// The dispatcher cannot be used again: a packet slot was reserved and never
+// filled (the queue stalls there), or packets may still be in flight.
+int poison(const std::string &msg) {
+  g_state.broken = true;
+  return fail(S4_EDEVICE, msg + "; the per-list dispatcher is disabled for the rest of the process");
+}
+
+// Reserve the next packet slot once the queue has room for it (bounded
+// wait).  The write index is advanced only after the room is seen, so a
+// failed wait leaves no reserved slot behind.  One host thread writes the
+// queues (the dispatcher's mutex), so the slot stays this thread's.
 int next_slot(hsa_queue_t *q, Clock::time_point t0, uint64_t *index) {
-  const uint64_t i = hsa_queue_add_write_index_scacq_screl(q, 1);
+  const uint64_t i = hsa_queue_load_write_index_relaxed(q);
   while (i - hsa_queue_load_read_index_scacquire(q) >= q->size) {
-    if (g_queue_error.load()) return fail(S4_EDEVICE, "the decode queue reported an error");
-    if (seconds_since(t0) > kWaitLimitSeconds) return fail(S4_EDEVICE, "the decode queue did not drain");
+    if (g_queue_error.load()) return poison("the decode queue reported an error");
+    if (seconds_since(t0) > kWaitLimitSeconds) return poison("the decode queue did not drain");
   }
+  hsa_queue_store_write_index_relaxed(q, i + 1);
   *index = i;
   return S4_OK;
+}
+
+// Publish a packet: everything but its first word is in place; the first
+// word (header and setup) is stored last with release order.
+void publish_packet(void *slot, uint32_t word0) {
+  __atomic_store_n(reinterpret_cast<uint32_t *>(slot), word0, __ATOMIC_RELEASE);
+}
+
+// A barrier-AND packet in slot i of q: waits for deps[0 .. ndeps) (at most
+// five), then signals `done` (may be null).
+void barrier_packet(hsa_queue_t *q, uint64_t i, const hsa_signal_t *deps, uint32_t ndeps, hsa_signal_t done,
+                    hsa_fence_scope_t acquire, hsa_fence_scope_t release) {
+  auto *bp = reinterpret_cast<hsa_barrier_and_packet_t *>(static_cast<uint8_t *>(q->base_address) +
+                                                           (i & (q->size - 1)) * 64);
+  bp->reserved0 = 0;
+  bp->reserved1 = 0;
+  for (uint32_t j = 0; j < 5; ++j) bp->dep_signal[j].handle = j < ndeps ? deps[j].handle : 0;
+  bp->reserved2 = 0;
+  bp->completion_signal = done;
+  publish_packet(bp, packet_header(HSA_PACKET_TYPE_BARRIER_AND, true, acquire, release));
 }
 
 }  // namespace
@@ -214,13 +261,134 @@ int next_slot(hsa_queue_t *q, Clock::time_point t0, uint64_t *index) {
 struct s4_aql_plan {
   void *args = nullptr;  // coherent pinned host memory, kArgStride bytes per dispatch
   struct Dispatch {
-    uint64_t object;
-    uint32_t group, grid;
-    const void *args;
+    hsa_kernel_dispatch_packet_t pkt;  // the packet, completion signal empty; its first word is published last
+    uint32_t word0;                    // header and setup
+    uint32_t list;                     // index of the list in the plan's input order
   };
   std::vector<Dispatch> per_queue[kQueues];
+  uint32_t count = 0, dispatches = 0;
   uint64_t ints = 0;
+  bool lost = false;  // a run of this plan failed: its argument blocks may still be referenced
+  std::atomic<uint32_t> pending{0};  // runs enqueued on a stream and not yet done
+  std::atomic<int> async_rc{0};      // first failure of an enqueued run
+  std::string async_msg;             // its message (under g_mu)
 };
+
+namespace {
+
+// Write `steps` steps of the plan into the queues and ring their doorbells.
+// Each queue: an opening barrier (step 0: no dependency, system-scope
+// acquire; later steps: every queue's previous step), its dispatches, and a
+// closing barrier that signals step_done[s][q].  sig: null, or one
+// completion signal per dispatch per step (dispatch j of queue q in step s
+// at sig[s * dispatches + offset of q + j]).  Caller holds g_mu.
+int submit_steps(s4_aql_plan *plan, uint32_t steps, const hsa_signal_t *sig, Clock::time_point t0) {
+  for (uint32_t s = 0; s < steps; ++s)
+    for (uint32_t q = 0; q < kQueues; ++q) hsa_signal_store_relaxed(g_state.step_done[s][q], 1);
+  for (uint32_t s = 0; s < steps; ++s) {
+    uint32_t base = s * plan->dispatches;
+    for (uint32_t q = 0; q < kQueues; ++q) {
+      hsa_queue_t *qu = g_state.queues[q];
+      auto *ring = static_cast<uint8_t *>(qu->base_address);
+      const uint64_t mask = qu->size - 1;
+      uint64_t i;
+      int rc;
+      if (s == 0) {
+        rc = next_slot(qu, t0, &i);
+        if (rc) return rc;
+        barrier_packet(qu, i, nullptr, 0, hsa_signal_t{0}, HSA_FENCE_SCOPE_SYSTEM, HSA_FENCE_SCOPE_NONE);
+      }
+      // wait for every queue's previous step (a barrier packet waits on at
+      // most five signals: as many packets as the queues need)
+      for (uint32_t j0 = 0; s > 0 && j0 < kQueues; j0 += 5) {
+        rc = next_slot(qu, t0, &i);
+        if (rc) return rc;
+        barrier_packet(qu, i, &g_state.step_done[s - 1][j0], std::min<uint32_t>(5, kQueues - j0), hsa_signal_t{0},
+                       HSA_FENCE_SCOPE_AGENT, HSA_FENCE_SCOPE_NONE);
+      }
+      const auto &v = plan->per_queue[q];
+      for (size_t j = 0; j < v.size(); ++j) {
+        rc = next_slot(qu, t0, &i);
+        if (rc) return rc;
+        uint8_t *slot = ring + (i & mask) * 64;
+        // independent lists: no barrier, no fences (the step's barriers carry them)
+        std::memcpy(slot + 4, reinterpret_cast<const uint8_t *>(&v[j].pkt) + 4, 60);
+        if (sig) reinterpret_cast<hsa_kernel_dispatch_packet_t *>(slot)->completion_signal = sig[base + j];
+        publish_packet(slot, v[j].word0);
+      }
+      base += uint32_t(v.size());
+      // this queue's part of the step is done once its kernels are
+      rc = next_slot(qu, t0, &i);
+      if (rc) return rc;
+      barrier_packet(qu, i, nullptr, 0, g_state.step_done[s][q], HSA_FENCE_SCOPE_NONE,
+                     s + 1 == steps ? HSA_FENCE_SCOPE_SYSTEM : HSA_FENCE_SCOPE_AGENT);
+      hsa_signal_store_screlease(qu->doorbell_signal, hsa_signal_value_t(i));
+    }
+  }
+  return S4_OK;
+}
+
+// Wait (bounded) until the last step is done on every queue.
+int wait_steps(uint32_t steps, Clock::time_point t0) {
+  for (uint32_t q = 0; q < kQueues; ++q)
+    while (hsa_signal_wait_scacquire(g_state.step_done[steps - 1][q], HSA_SIGNAL_CONDITION_LT, 1, 1000000,
+                                     HSA_WAIT_STATE_ACTIVE) >= 1) {
+      if (g_queue_error.load()) return poison("a decode queue reported an error");
+      if (seconds_since(t0) > kWaitLimitSeconds) return poison("decode did not complete in time");
+    }
+  return S4_OK;
+}
+
+int check_runnable(const s4_aql_plan *plan, uint32_t steps) {
+  if (!plan || steps == 0 || steps > kMaxSteps) return fail(S4_EINVAL, "null plan or steps outside 1..64");
+  if (!g_state.ready) return fail(S4_EINVAL, "dispatcher not set up");
+  if (g_state.broken) return fail(S4_EDEVICE, "the per-list dispatcher was disabled by an earlier failure");
+  for (uint32_t q = 0; q < kQueues; ++q)
+    if (plan->per_queue[q].size() + 3 + kQueues / 5 >= g_state.queues[q]->size)
+      return fail(S4_EINVAL, "a step needs more packets than a queue holds");
+  return S4_OK;
+}
+
+// One run of `steps` steps, returning when they are complete.  Caller holds g_mu.
+int run_locked(s4_aql_plan *plan, uint32_t steps, const hsa_signal_t *sig, uint64_t *elapsed_ns) {
+  int rc = check_runnable(plan, steps);
+  if (rc) return rc;
+  const Clock::time_point t0 = Clock::now();
+  rc = submit_steps(plan, steps, sig, t0);
+  if (!rc) rc = wait_steps(steps, t0);
+  if (rc) {
+    plan->lost = true;
+    return rc;
+  }
+  if (elapsed_ns)
+    *elapsed_ns = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count());
+  return S4_OK;
+}
+
+struct Pending {
+  s4_aql_plan *plan;
+  uint32_t steps;
+};
+
+// Host function of a caller's stream: runs the plan and returns when it is
+// complete, so the stream's later work is ordered after it.  No HIP call
+// is made here (only HSA).
+void run_from_stream(void *data) {
+  Pending *pd = static_cast<Pending *>(data);
+  s4_aql_plan *plan = pd->plan;
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    const int rc = run_locked(plan, pd->steps, nullptr, nullptr);
+    if (rc && plan->async_rc.load() == 0) {
+      plan->async_msg = s4_last_error();
+      plan->async_rc.store(rc);
+    }
+  }
+  delete pd;
+  plan->pending.fetch_sub(1);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -243,6 +411,7 @@ int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, con
   S4_HIP(hipGetDevice(&dev));
   if (dev != g_state.device) return fail(S4_EINVAL, "the dispatcher serves the device it was first used on");
   std::vector<DecodeLaunch> launches;
+  std::vector<uint32_t> list_of;
   launches.reserve(count);
   for (uint32_t i = 0; i < count; ++i) {
     DecodeLaunch d;
@@ -250,6 +419,7 @@ int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, con
     rc = ensure_kernel(d.P);
     if (rc) return rc;
     launches.push_back(d);
+    list_of.push_back(i);
   }
   s4_aql_plan *p = new (std::nothrow) s4_aql_plan;
   if (!p) return fail(S4_ENOMEM, "plan allocation failed");
@@ -275,7 +445,23 @@ int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, con
     for (uint32_t q = 1; q < kQueues; ++q)
       if (load[q] < load[best]) best = q;
     load[best] += uint64_t(d.a.full_end - d.a.first) * 512u + 4096u;
-    p->per_queue[best].push_back({k.object, k.group, d.workgroups * 256u, a});
+    s4_aql_plan::Dispatch dp;
+    std::memset(&dp, 0, sizeof dp);
+    dp.pkt.workgroup_size_x = 256;
+    dp.pkt.workgroup_size_y = 1;
+    dp.pkt.workgroup_size_z = 1;
+    dp.pkt.grid_size_x = d.workgroups * 256u;
+    dp.pkt.grid_size_y = 1;
+    dp.pkt.grid_size_z = 1;
+    dp.pkt.private_segment_size = 0;
+    dp.pkt.group_segment_size = k.group;
+    dp.pkt.kernel_object = k.object;
+    dp.pkt.kernarg_address = a;
+    dp.pkt.completion_signal.handle = 0;
+    dp.word0 = packet_header(HSA_PACKET_TYPE_KERNEL_DISPATCH, false, HSA_FENCE_SCOPE_NONE, HSA_FENCE_SCOPE_NONE) |
+               (uint32_t(1) << (16 + HSA_KERNEL_DISPATCH_PACKET_SETUP_DIMENSIONS));
+    dp.list = list_of[j];
+    p->per_queue[best].push_back(dp);
   }
   // within a queue, alternate its largest and smallest remaining lists, so
   // small dispatches are issued while large kernels run
@@ -289,98 +475,101 @@ int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, con
     }
     v.swap(mixed);
   }
+  p->count = count;
+  p->dispatches = uint32_t(launches.size());
   for (uint32_t i = 0; i < count; ++i) p->ints += lists[i]->n;
   *out = p;
   return S4_OK;
 }
 
 int s4_aql_plan_run(s4_aql_plan *plan, uint32_t steps, uint64_t *elapsed_ns) {
-  if (!plan || steps == 0 || steps > kMaxSteps) return fail(S4_EINVAL, "null plan or steps outside 1..64");
   std::lock_guard<std::mutex> lock(g_mu);
-  if (!g_state.ready) return fail(S4_EINVAL, "dispatcher not set up");
-  for (uint32_t q = 0; q < kQueues; ++q)
-    if (plan->per_queue[q].size() + 2 + kQueues / 5 >= g_state.queues[q]->size)
-      return fail(S4_EINVAL, "a step needs more packets than a queue holds");
-  for (uint32_t s = 0; s < steps; ++s)
-    for (uint32_t q = 0; q < kQueues; ++q) hsa_signal_store_relaxed(g_state.step_done[s][q], 1);
-  const Clock::time_point t0 = Clock::now();
-  for (uint32_t s = 0; s < steps; ++s) {
-    for (uint32_t q = 0; q < kQueues; ++q) {
-      hsa_queue_t *qu = g_state.queues[q];
-      auto *ring = static_cast<uint8_t *>(qu->base_address);
-      const uint64_t mask = qu->size - 1;
-      uint64_t i;
-      int rc;
-      // wait for every queue's previous step (a barrier packet waits on
-      // at most five signals: as many packets as the queues need)
-      for (uint32_t j0 = 0; s > 0 && j0 < kQueues; j0 += 5) {
-        rc = next_slot(qu, t0, &i);
-        if (rc) return rc;
-        auto *bp = reinterpret_cast<hsa_barrier_and_packet_t *>(ring + (i & mask) * 64);
-        bp->reserved0 = 0;
-        bp->reserved1 = 0;
-        for (uint32_t j = 0; j < 5; ++j)
-          bp->dep_signal[j].handle = j0 + j < kQueues ? g_state.step_done[s - 1][j0 + j].handle : 0;
-        bp->reserved2 = 0;
-        bp->completion_signal.handle = 0;
-        __atomic_store_n(reinterpret_cast<uint32_t *>(bp),
-                         uint32_t(packet_header(HSA_PACKET_TYPE_BARRIER_AND, true, HSA_FENCE_SCOPE_AGENT,
-                                                HSA_FENCE_SCOPE_NONE)),
-                         __ATOMIC_RELEASE);
-      }
-      for (const auto &d : plan->per_queue[q]) {
-        rc = next_slot(qu, t0, &i);
-        if (rc) return rc;
-        auto *pk = reinterpret_cast<hsa_kernel_dispatch_packet_t *>(ring + (i & mask) * 64);
-        pk->workgroup_size_x = 256;
-        pk->workgroup_size_y = 1;
-        pk->workgroup_size_z = 1;
-        pk->reserved0 = 0;
-        pk->grid_size_x = d.grid;
-        pk->grid_size_y = 1;
-        pk->grid_size_z = 1;
-        pk->private_segment_size = 0;
-        pk->group_segment_size = d.group;
-        pk->kernel_object = d.object;
-        pk->kernarg_address = const_cast<void *>(d.args);
-        pk->reserved2 = 0;
-        pk->completion_signal.handle = 0;
-        // independent lists: no barrier, no fences (the step's barriers carry them)
-        const uint32_t word =
-            packet_header(HSA_PACKET_TYPE_KERNEL_DISPATCH, false, HSA_FENCE_SCOPE_NONE, HSA_FENCE_SCOPE_NONE) |
-            (uint32_t(1) << (16 + HSA_KERNEL_DISPATCH_PACKET_SETUP_DIMENSIONS));
-        __atomic_store_n(reinterpret_cast<uint32_t *>(pk), word, __ATOMIC_RELEASE);
-      }
-      // this queue's part of the step is done once its kernels are
-      rc = next_slot(qu, t0, &i);
-      if (rc) return rc;
-      auto *ep = reinterpret_cast<hsa_barrier_and_packet_t *>(ring + (i & mask) * 64);
-      ep->reserved0 = 0;
-      ep->reserved1 = 0;
-      for (auto &dep : ep->dep_signal) dep.handle = 0;
-      ep->reserved2 = 0;
-      ep->completion_signal.handle = g_state.step_done[s][q].handle;
-      __atomic_store_n(reinterpret_cast<uint32_t *>(ep),
-                       uint32_t(packet_header(HSA_PACKET_TYPE_BARRIER_AND, true, HSA_FENCE_SCOPE_NONE,
-                                              s + 1 == steps ? HSA_FENCE_SCOPE_SYSTEM : HSA_FENCE_SCOPE_AGENT)),
-                       __ATOMIC_RELEASE);
-      hsa_signal_store_screlease(qu->doorbell_signal, hsa_signal_value_t(i));
-    }
+  return run_locked(plan, steps, nullptr, elapsed_ns);
+}
+
+int s4_aql_plan_profile(s4_aql_plan *plan, uint32_t steps, uint64_t *start_ns, uint64_t *end_ns,
+                        uint64_t *elapsed_ns) {
+  if (!plan || !start_ns || !end_ns) return fail(S4_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lock(g_mu);
+  int rc = check_runnable(plan, steps);
+  if (rc) return rc;
+  const size_t nsig = size_t(steps) * plan->dispatches;
+  std::vector<hsa_signal_t> sig(nsig);
+  size_t made = 0;
+  for (; made < nsig; ++made)
+    if (hsa_amd_signal_create(1, 0, nullptr, HSA_AMD_SIGNAL_AMD_GPU_ONLY, &sig[made]) != HSA_STATUS_SUCCESS) break;
+  auto destroy = [&]() {
+    for (size_t j = 0; j < made; ++j) (void)hsa_signal_destroy(sig[j]);
+  };
+  if (made < nsig) {
+    destroy();
+    return fail(S4_ENOMEM, "profiling: signal creation failed");
   }
-  for (uint32_t q = 0; q < kQueues; ++q)
-    while (hsa_signal_wait_scacquire(g_state.step_done[steps - 1][q], HSA_SIGNAL_CONDITION_LT, 1, 1000000,
-                                     HSA_WAIT_STATE_ACTIVE) >= 1) {
-      if (g_queue_error.load()) return fail(S4_EDEVICE, "a decode queue reported an error");
-      if (seconds_since(t0) > kWaitLimitSeconds) return fail(S4_EDEVICE, "decode did not complete in time");
+  uint32_t on = 0;
+  for (; on < kQueues; ++on)
+    if (hsa_amd_profiling_set_profiler_enabled(g_state.queues[on], 1) != HSA_STATUS_SUCCESS) break;
+  if (on == kQueues) rc = run_locked(plan, steps, sig.data(), elapsed_ns);
+  else rc = fail(S4_EDEVICE, "profiling could not be enabled on the dispatch queues");
+  for (uint32_t q = 0; q < on; ++q) (void)hsa_amd_profiling_set_profiler_enabled(g_state.queues[q], 0);
+  if (rc) return rc;  // the signals may still be referenced by packets: kept
+  std::fill(start_ns, start_ns + size_t(steps) * plan->count, 0);
+  std::fill(end_ns, end_ns + size_t(steps) * plan->count, 0);
+  std::vector<hsa_amd_profiling_dispatch_time_t> t(nsig);
+  uint64_t t0 = UINT64_MAX;
+  for (size_t j = 0; j < nsig; ++j) {
+    if (hsa_amd_profiling_get_dispatch_time(g_state.agent, sig[j], &t[j]) != HSA_STATUS_SUCCESS) {
+      destroy();
+      return fail(S4_EDEVICE, "profiling: dispatch time not available");
     }
-  if (elapsed_ns)
-    *elapsed_ns = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count());
+    t0 = std::min(t0, t[j].start);
+  }
+  destroy();
+  auto ns = [&](uint64_t tick) { return uint64_t(double(tick - t0) * 1e9 / double(g_state.ts_hz)); };
+  for (uint32_t s = 0; s < steps; ++s) {
+    size_t j = size_t(s) * plan->dispatches;
+    for (uint32_t q = 0; q < kQueues; ++q)
+      for (const auto &d : plan->per_queue[q]) {
+        start_ns[size_t(s) * plan->count + d.list] = ns(t[j].start);
+        end_ns[size_t(s) * plan->count + d.list] = ns(t[j].end);
+        ++j;
+      }
+  }
+  return S4_OK;
+}
+
+int s4_aql_plan_enqueue(s4_aql_plan *plan, uint32_t steps, void *stream) {
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    int rc = check_runnable(plan, steps);
+    if (rc) return rc;
+  }
+  Pending *pd = new (std::nothrow) Pending{plan, steps};
+  if (!pd) return fail(S4_ENOMEM, "enqueue: allocation failed");
+  plan->pending.fetch_add(1);
+  const hipError_t e = hipLaunchHostFunc(static_cast<hipStream_t>(stream), run_from_stream, pd);
+  if (e != hipSuccess) {
+    plan->pending.fetch_sub(1);
+    delete pd;
+    return hip_fail(e, "hipLaunchHostFunc");
+  }
+  return S4_OK;
+}
+
+int s4_aql_plan_status(s4_aql_plan *plan) {
+  if (!plan) return fail(S4_EINVAL, "null plan");
+  std::lock_guard<std::mutex> lock(g_mu);
+  const int rc = plan->async_rc.load();
+  if (rc) return fail(rc, "an enqueued run failed: " + plan->async_msg);
   return S4_OK;
 }
 
 int s4_aql_plan_free(s4_aql_plan *plan) {
   if (!plan) return S4_OK;
-  if (plan->args) (void)hipHostFree(plan->args);
+  if (plan->pending.load()) return fail(S4_EINVAL, "a run of the plan is still enqueued on a stream");
+  std::lock_guard<std::mutex> lock(g_mu);
+  // after a failed run, packets may still reference the argument blocks:
+  // they are kept for the rest of the process
+  if (plan->args && !plan->lost && !g_state.broken) (void)hipHostFree(plan->args);
   delete plan;
   return S4_OK;
 }

@@ -67,3 +67,76 @@ def test_aql_plan_rejects_patched_lists(gpu):
     with pytest.raises(gpu.S4Error) as e:
         gpu.AqlDecodePlan([lst], [out])
     assert e.value.code == gpu.EINVAL
+
+
+def test_aql_new_plan_after_free_sees_new_lists(gpu):
+    """A plan and its lists freed, other lists uploaded (often at the freed
+    addresses) and a new plan built: the new run must decode the new inputs,
+    not stale cached arguments or payload (every run opens with a
+    system-scope acquire)."""
+    import gc
+    for round_ in range(3):
+        specs = [((1 << 16) + 37 * round_, oracle.D4), (5000 + round_, oracle.D1), (129, oracle.D4),
+                 ((1 << 19) + 11 * round_, oracle.D4)]
+        log("round", round_, [n for n, _ in specs])
+        # different seeds each round: different values at possibly reused addresses
+        import torch
+        xs, lists = [], []
+        for i, (n, mode) in enumerate(specs):
+            kind = workloads.CLUSTERED if (i + round_) % 2 else workloads.UNIFORM
+            x = workloads.sorted_list(kind, 9000 + 17 * round_ + i, 1 << 26, n)
+            xs.append(x)
+            lists.append(gpu.DeviceList.upload(gpu.encode(x, mode)))
+        pos, p = [], 0
+        for x in xs:
+            pos.append(p)
+            p += (x.size + 63) // 64 * 64 + 64
+        out = torch.full((p,), -1, dtype=torch.int32, device="cuda")
+        outs = [out[q: q + x.size + 4] for q, x in zip(pos, xs)]
+        plan = gpu.AqlDecodePlan(lists, outs)
+        plan.run(2)
+        check(out, xs, pos)
+        del plan, lists, outs, out
+        gc.collect()
+
+
+def test_aql_enqueue_is_stream_ordered(gpu):
+    """enqueue(): the run starts after the stream's earlier work (a fill of
+    the outputs) and the stream's later work (a copy of the outputs) sees
+    its results; the caller never synchronises in between."""
+    import torch
+    specs = [((1 << 20) + 3, oracle.D4), (70001, oracle.D1), (128, oracle.D4), (0, oracle.D4)]
+    xs, lists, out, outs, pos = build(gpu, specs)
+    plan = gpu.AqlDecodePlan(lists, outs)
+    s = torch.cuda.Stream()
+    copy = torch.empty_like(out)
+    with torch.cuda.stream(s):
+        for rep in range(3):
+            out.fill_(-1)
+            gpu.spin(2_000_000)  # the fill stays in flight while the call returns
+            plan.enqueue(2)
+            copy.copy_(out)
+    s.synchronize()
+    plan.status()
+    check(copy, xs, pos)
+
+
+def test_aql_profile_reports_every_dispatch(gpu):
+    specs = [(0, oracle.D4), (1, oracle.D4), (5000, oracle.D4), ((1 << 21) + 5, oracle.D4),
+             ((1 << 22) + 77, oracle.D1), (127, oracle.D1)]
+    xs, lists, out, outs, pos = build(gpu, specs)
+    plan = gpu.AqlDecodePlan(lists, outs)
+    st, en, ms = plan.profile(2)
+    check(out, xs, pos)
+    assert st.shape == (2, len(specs))
+    for s in range(2):
+        for i, x in enumerate(xs):
+            if x.size == 0:
+                assert st[s, i] == 0 and en[s, i] == 0
+            else:
+                assert en[s, i] > st[s, i], (s, i)
+    # step 1 starts after step 0 has ended on every queue
+    live = [i for i, x in enumerate(xs) if x.size]
+    assert st[1, live].min() >= en[0, live].max()
+    # the device span fits in the host's wall time of the run
+    assert (en.max() - st[0, live].min()) / 1e6 <= ms * 1.05 + 0.05
