@@ -256,7 +256,16 @@ int s4_spin_dev(uint64_t ns, void *stream);
  * cap >= min(len a, len b) is always enough; a smaller cap is S4_ERANGE.
  * The count is written to device memory *d_count (u64).  Scratch is a
  * caller-owned device buffer of at least the size the *_scratch_bytes call
- * reports; its contents on entry do not matter.
+ * reports (16 bytes per 128 values of the shorter side, plus 256); its
+ * contents on entry do not matter, and calls that share it must not overlap
+ * (stream order is enough).
+ * Each call is one kernel launch (an empty shorter side: one launch that
+ * writes the zero count): every wavefront takes a 128-value chunk of the
+ * shorter side in the order the wavefronts start, intersects it, and finds
+ * where its survivors go by a look-back over its predecessors' counts in
+ * the scratch (each call's counts carry an epoch of their own, so stale
+ * ones are never read).  That wait is bounded: a call that cannot finish
+ * (never seen) writes *d_count = UINT64_MAX instead of hanging.
  */
 size_t s4_intersect_scratch_bytes(uint64_t len_a, uint64_t len_b);
 int s4_intersect(const s4_list *a, const s4_list *b, uint32_t *d_out, uint64_t cap,
@@ -268,7 +277,8 @@ int s4_intersect(const s4_list *a, const s4_list *b, uint32_t *d_out, uint64_t c
  * the blocks it needs.  The work is split by 128-value chunks of the
  * shortest list, each chunk carried through all the lists by one wavefront
  * (one launch in all), which gives the same set.  k = 0 or k > 33 is
- * S4_EINVAL; k = 1 decodes the list. */
+ * S4_EINVAL; k = 1 decodes the list (d_out 16-byte aligned; no scratch
+ * needed). */
 size_t s4_intersect_k_scratch_bytes(const s4_list *const *lists, uint32_t k);
 int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap,
                    uint64_t *d_count, void *d_scratch, size_t scratch_bytes, void *stream);
@@ -424,6 +434,43 @@ int s4_batch_autotune(s4_batch *batch, uint64_t *d_counts, uint64_t *d_res_offse
                       uint32_t *d_results, uint64_t results_cap, int reps, void *stream,
                       s4_tuning *best, double *best_ms);
 
+/* ------------------------------------------------------------- plain path
+ *
+ * The plain path a batch is compared with: every query on its own, one
+ * single-launch conjunction per query (the kernel of s4_intersect_k, Sec. 6
+ * SvS over chunks of the shortest list), launched back to back on `stream`
+ * from this call's thread, with no batching.  Queries are as for
+ * s4_batch_plan but need 2..33 terms; the index must be neither hybrid nor
+ * partitioned (S4_EINVAL).  The call checks every query, then launches,
+ * then synchronises `stream`.
+ *
+ * s4_plain_run: query q's results go to d_results + res_offsets[q]
+ * (res_offsets: host [nq + 1], written by the call: the prefix sum of each
+ * query's shortest length, the output-to-input bound), its count to
+ * d_counts[q] (device u64).  results_cap >= res_offsets[nq] and
+ * scratch_bytes >= s4_intersect_raw_scratch_bytes(longest shortest list),
+ * else S4_ERANGE before any launch.  lat_ns (host [nq], may be null): each
+ * query is then waited for before the next is launched, and lat_ns[q] is
+ * its host wall time from launch to completion (an isolated query's
+ * latency).  *elapsed_ns: host wall time from the first launch to the
+ * completion of the last query. */
+int s4_plain_run(const s4_index *index, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
+                 uint32_t *d_results, uint64_t results_cap, uint64_t *res_offsets, uint64_t *d_counts,
+                 void *d_scratch, size_t scratch_bytes, uint64_t *lat_ns, uint64_t *elapsed_ns, void *stream);
+/* s4_plain_replay: the same plain path under an open-loop arrival trace
+ * (as s4_server_replay): query q is launched h_arrival_ns[q] ns after the
+ * call starts, or as soon after as the launching thread gets to it;
+ * latency_ns[q] is the time from its scheduled arrival until a watcher
+ * thread sees its completion event.  Every query writes its results to
+ * d_results (results_cap >= the longest shortest list; each query
+ * overwrites the last, in stream order) and its count to d_counts[q].
+ * *elapsed_s: wall time from the first arrival to the last completion.
+ * S4_ERANGE after timeout_s seconds. */
+int s4_plain_replay(const s4_index *index, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
+                    const uint64_t *h_arrival_ns, uint64_t *latency_ns, uint32_t *d_results, uint64_t results_cap,
+                    uint64_t *d_counts, void *d_scratch, size_t scratch_bytes, double timeout_s, double *elapsed_s,
+                    void *stream);
+
 /* ----------------------------------------------------------------- server
  *
  * Continuous-batching query server over a device-resident index (each
@@ -496,7 +543,10 @@ int s4_server_destroy(s4_server *srv);
  * drained concurrently.  latency_ns[q] receives the time from the scheduled
  * arrival to the result on the host, counts[q] the result size; when
  * results is not null, result q is copied to results + res_offsets[q]
- * (res_offsets has nq + 1 entries) if everything fits results_cap.  Returns
+ * (res_offsets has nq + 1 entries) if everything fits results_cap; keep
+ * (host [nq], may be null) limits the copies to the queries with
+ * keep[q] != 0 (the others get empty ranges), so a long trace need not hold
+ * every result.  Returns
  * S4_ERANGE after timeout_s seconds without every result; *elapsed_s
  * receives the wall time from the first arrival to the last result.  The
  * replay takes every completion the server hands over while it runs:
@@ -504,7 +554,8 @@ int s4_server_destroy(s4_server *srv);
  * s4_server_poll. */
 int s4_server_replay(s4_server *srv, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
                      const uint64_t *h_arrival_ns, uint64_t *latency_ns, uint64_t *counts, uint32_t *results,
-                     uint64_t results_cap, uint64_t *res_offsets, double timeout_s, double *elapsed_s);
+                     uint64_t results_cap, uint64_t *res_offsets, const uint8_t *keep, double timeout_s,
+                     double *elapsed_s);
 
 #ifdef __cplusplus
 }

@@ -118,8 +118,11 @@ SIGNATURES = {
     "s4_server_poll": (_i, [_vp, _u64p, _u64p, _u64p, _u32p, _u64, _u64p, _u32, _u32p]),
     "s4_server_stats_get": (_i, [_vp, ctypes.POINTER(ServerStats)]),
     "s4_server_destroy": (_i, [_vp]),
-    "s4_server_replay": (_i, [_vp, _u32p, _u64p, _u64, _u64p, _u64p, _u64p, _u32p, _u64, _u64p,
+    "s4_server_replay": (_i, [_vp, _u32p, _u64p, _u64, _u64p, _u64p, _u64p, _u32p, _u64, _u64p, _u8p,
                               ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+    "s4_plain_run": (_i, [_vp, _u32p, _u64p, _u64, _vp, _u64, _u64p, _vp, _vp, _sz, _u64p, _u64p, _vp]),
+    "s4_plain_replay": (_i, [_vp, _u32p, _u64p, _u64, _u64p, _u64p, _vp, _u64, _vp, _vp, _sz, ctypes.c_double,
+                             ctypes.POINTER(ctypes.c_double), _vp]),
 }
 
 
@@ -630,6 +633,63 @@ class Batch:
             pass
 
 
+# ------------------------------------------------------------- plain path
+
+def plain_run(index: "Index", terms, q_offsets, isolate=False, stream=None):
+    """Every query as its own single-launch conjunction, back to back
+    (s4_plain_run).  Returns (counts tensor, results tensor, res_offsets
+    numpy, elapsed ms, per-query isolated latency in ns or None)."""
+    import torch
+    lib = require_library()
+    terms = np.ascontiguousarray(terms, dtype=np.uint32)
+    q_offsets = np.ascontiguousarray(q_offsets, dtype=np.uint64)
+    nq = q_offsets.size - 1
+    lens = index.lengths
+    # sizes only (terms are checked by the library)
+    tl = lens[np.minimum(terms, max(0, lens.size - 1))] if lens.size else np.zeros(terms.size, np.uint64)
+    mins = np.minimum.reduceat(tl, q_offsets[:-1].astype(np.int64)) if nq and tl.size else np.zeros(nq, np.uint64)
+    total = int(mins.sum()) if nq else 0
+    need = int(lib.s4_intersect_raw_scratch_bytes(int(mins.max()) if nq else 0))
+    results = torch.empty(max(1, total), dtype=torch.int32, device="cuda")
+    counts = torch.zeros(max(1, nq), dtype=torch.int64, device="cuda")
+    scratch = _scratch(need)
+    roffs = np.zeros(nq + 1, np.uint64)
+    lat = np.zeros(max(1, nq), np.uint64) if isolate else None
+    ns = ctypes.c_uint64(0)
+    _check(lib.s4_plain_run(index.h, _ptr(terms if terms.size else np.zeros(1, np.uint32), ctypes.c_uint32),
+                            _ptr(q_offsets, ctypes.c_uint64), nq, _dptr(results), results.numel(),
+                            _ptr(roffs, ctypes.c_uint64), _dptr(counts), _dptr(scratch), scratch.numel(),
+                            _ptr(lat, ctypes.c_uint64) if isolate else None, ctypes.byref(ns), _stream(stream)),
+           "s4_plain_run")
+    return counts[:nq], results, roffs, ns.value / 1e6, (lat[:nq] if isolate else None)
+
+
+def plain_replay(index: "Index", terms, q_offsets, arrival_ns, timeout_s=600.0, stream=None):
+    """The plain path under an open-loop arrival trace (s4_plain_replay):
+    {'latency_ns', 'counts', 'elapsed_s'}."""
+    import torch
+    lib = require_library()
+    terms = np.ascontiguousarray(terms, dtype=np.uint32)
+    q_offsets = np.ascontiguousarray(q_offsets, dtype=np.uint64)
+    arrival_ns = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+    nq = q_offsets.size - 1
+    lens = index.lengths
+    tl = lens[np.minimum(terms, max(0, lens.size - 1))] if lens.size else np.zeros(terms.size, np.uint64)
+    mins = np.minimum.reduceat(tl, q_offsets[:-1].astype(np.int64)) if nq and tl.size else np.zeros(1, np.uint64)
+    m = int(mins.max()) if nq else 0
+    results = torch.empty(max(1, m), dtype=torch.int32, device="cuda")
+    counts = torch.zeros(max(1, nq), dtype=torch.int64, device="cuda")
+    scratch = _scratch(int(lib.s4_intersect_raw_scratch_bytes(m)))
+    lat = np.zeros(max(1, nq), np.uint64)
+    el = ctypes.c_double(0)
+    _check(lib.s4_plain_replay(index.h, _ptr(terms if terms.size else np.zeros(1, np.uint32), ctypes.c_uint32),
+                               _ptr(q_offsets, ctypes.c_uint64), nq, _ptr(arrival_ns, ctypes.c_uint64),
+                               _ptr(lat, ctypes.c_uint64), _dptr(results), results.numel(), _dptr(counts),
+                               _dptr(scratch), scratch.numel(), timeout_s, ctypes.byref(el), _stream(stream)),
+           "s4_plain_replay")
+    return {"latency_ns": lat[:nq], "counts": counts[:nq].cpu().numpy().astype(np.uint64), "elapsed_s": el.value}
+
+
 # ----------------------------------------------------------------- server
 
 class Server:
@@ -669,8 +729,10 @@ class Server:
             out.append((int(ids[i]), res[int(roffs[i]): int(roffs[i + 1])].copy(), int(lat[i])))
         return out
 
-    def replay(self, terms, q_offsets, arrival_ns, with_results=False, results_cap=1 << 26, timeout_s=600.0):
-        """Open-loop replay of an arrival trace (s4_server_replay)."""
+    def replay(self, terms, q_offsets, arrival_ns, with_results=False, results_cap=1 << 26, timeout_s=600.0,
+               keep=None):
+        """Open-loop replay of an arrival trace (s4_server_replay); with
+        keep (bool per query) only those queries' results are returned."""
         terms = np.ascontiguousarray(terms, dtype=np.uint32)
         q_offsets = np.ascontiguousarray(q_offsets, dtype=np.uint64)
         arrival_ns = np.ascontiguousarray(arrival_ns, dtype=np.uint64)
@@ -680,11 +742,17 @@ class Server:
         res = np.zeros(results_cap if with_results else 1, np.uint32)
         roffs = np.zeros(nq + 1, np.uint64)
         el = ctypes.c_double(0)
+        kp = None
+        if keep is not None:
+            keep = np.ascontiguousarray(keep, dtype=np.uint8)
+            if keep.size != nq:
+                raise ValueError("keep needs one entry per query")
+            kp = _ptr(keep if keep.size else np.zeros(1, np.uint8), ctypes.c_uint8)
         _check(require_library().s4_server_replay(
             self.h, _ptr(terms if terms.size else np.zeros(1, np.uint32), ctypes.c_uint32),
             _ptr(q_offsets, ctypes.c_uint64), nq, _ptr(arrival_ns, ctypes.c_uint64), _ptr(lat, ctypes.c_uint64),
             _ptr(counts, ctypes.c_uint64), _ptr(res, ctypes.c_uint32) if with_results else None,
-            results_cap if with_results else 0, _ptr(roffs, ctypes.c_uint64), timeout_s, ctypes.byref(el)),
+            results_cap if with_results else 0, _ptr(roffs, ctypes.c_uint64), kp, timeout_s, ctypes.byref(el)),
             "s4_server_replay")
         out = {"latency_ns": lat[:nq], "counts": counts[:nq], "elapsed_s": el.value}
         if with_results:

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libs4.so")
 
-SOURCES = ["s4_format.cpp", "s4_device.hip", "s4_batch.hip", "s4_hybrid.hip", "s4_serve.cpp", "s4_aql.cpp"]
+SOURCES = ["s4_format.cpp", "s4_device.hip", "s4_batch.hip", "s4_hybrid.hip", "s4_serve.cpp", "s4_aql.cpp", "s4_plain.cpp"]
 
 # the per-list dispatcher writes packets into an HSA queue of its own
 LINK_FLAGS = ["-L/opt/rocm/lib", "-lhsa-runtime64"]

@@ -104,12 +104,6 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
   }
 }
 
-// Sum over the wave.
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-  for (int o = 32; o > 0; o >>= 1) v += uint32_t(__shfl_xor(int(v), o));
-  return v;
-}
-
 // Scan word of one chunk: high half (epoch << 2 | flag), low half a value;
 // flag 1: the chunk's count alone, flag 2: inclusive prefix through it.
 __device__ __forceinline__ void publish(uint64_t *w, uint32_t tag, uint32_t v) {

@@ -2,6 +2,7 @@
 // build, bulk decode (unpack + D4 prefix sum fused, Alg. 1), pairwise and
 // k-way (SvS) decode-fused intersection.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -394,32 +395,131 @@ struct ChainArgs {
   uint32_t nf;  // lists after the short side
 };
 
-// One wave per chunk of r: decode-fused SvS over the chunk.  r is either a
-// compressed list or raw values whose length lives on the device.  Writes
-// the chunk's survivors to stage[128 item ..] and their number to
-// counts[item]; chunks past the end of r get 0.
+// Scratch of one single-launch intersection run: a ticket word, then per
+// 128-value chunk of the short side a 64-bit scan tag and two counts.
+// Every run carries its own epoch, so nothing needs clearing between runs.
+struct RunScratch {
+  uint64_t *ticket;  // (low 32 bits of the run's epoch) << 32 | chunks taken
+  uint64_t *tag;     // [items] epoch << 2 | flag: 1 agg set, 2 incl set, 3 poisoned
+  uint32_t *agg;     // [items] survivors of the chunk
+  uint32_t *incl;    // [items] survivors of chunks 0 .. i
+  uint32_t items_cap;
+};
+
+// Bound on the look-back's waits (each ends with a short sleep): a guard
+// that turns a run that cannot finish into a reported failure, never a hang.
+constexpr uint32_t kRunSpins = 1u << 22;
+// *d_count of a run whose look-back gave up.
+constexpr uint64_t kRunFailed = ~0ull;
+
+// The wave's chunk (lane 0 asks): chunks are numbered in the order waves
+// start, so every chunk a wave waits for belongs to a wave already running.
+// The counter restarts at the first ticket of a new epoch.
+__device__ uint32_t run_ticket(uint64_t *ticket, uint32_t e32) {
+  for (;;) {
+    uint64_t v = __hip_atomic_load(ticket, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (uint32_t(v >> 32) == e32)
+      return uint32_t(__hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (__hip_atomic_compare_exchange_strong(ticket, &v, (uint64_t(e32) << 32) | 1u, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return 0;
+  }
+}
+
+// Decoupled look-back over the run's tags: publish this chunk's count, read
+// the tags of its 64 nearest predecessors at once, and sum counts back to
+// the nearest chunk whose inclusive prefix is known; then publish this
+// chunk's inclusive prefix.  A chunk that waited too long publishes
+// "poisoned" instead, and so does every chunk whose walk reaches one, so a
+// failure reaches the run's last chunk and every wave ends.
+__device__ uint32_t run_lookback(const RunScratch &s, uint32_t item, uint64_t epoch, uint32_t cnt, bool &ok) {
+  const uint32_t lane = lane_id();
+  const uint64_t tag_a = (epoch << 2) | 1u, tag_p = (epoch << 2) | 2u, tag_x = (epoch << 2) | 3u;
+  if (lane == 0) {
+    if (item == 0) {
+      __hip_atomic_store(s.incl, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(s.tag, tag_p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(s.agg + item, cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(s.tag + item, tag_a, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  ok = true;
+  if (item == 0) return 0;
+  uint32_t excl = 0, spins = 0;
+  bool poisoned = false;
+  int64_t base = int64_t(item) - 1;
+  for (;;) {
+    const int64_t j = base - int64_t(lane);
+    uint64_t t = tag_p;  // before the first chunk: inclusive prefix 0
+    if (j >= 0) t = __hip_atomic_load(s.tag + j, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t is_t = __ballot(t == tag_p || t == tag_x);
+    const uint64_t ready = __ballot(t == tag_p || t == tag_x || t == tag_a);
+    // lanes through the nearest terminal word (all 64 if none)
+    const uint64_t nearest = is_t & (~is_t + 1);
+    const uint64_t need = is_t ? (nearest << 1) - 1 : ~0ull;
+    if ((ready & need) == need) {
+      if (__ballot(t == tag_x) & nearest) {
+        poisoned = true;
+        break;
+      }
+      uint32_t v = 0;
+      if (((need >> lane) & 1) && j >= 0)
+        v = __hip_atomic_load(t == tag_a ? s.agg + j : s.incl + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      excl += wave_sum(v);
+      if (is_t) break;
+      base -= 64;
+    } else if (++spins > kRunSpins) {
+      poisoned = true;
+      break;
+    } else {
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  if (lane == 0) {
+    if (!poisoned) __hip_atomic_store(s.incl + item, excl + cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(s.tag + item, poisoned ? tag_x : tag_p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  ok = !poisoned;
+  return excl;
+}
+
+// One launch per conjunction: each wave takes a 128-value chunk of r and
+// carries it through the other lists (decode-fused SvS), finds its output
+// offset by look-back and writes its survivors to their final place; the
+// last chunk writes the total to *count (kRunFailed if the run gave up).
+// r is a compressed list or raw values whose length lives on the device;
+// chunks past the end of r count 0.
 template <int WAVES, uint32_t FEAT>
 __global__ __launch_bounds__(WAVES * 64) void k_chain(DList rl, const uint32_t *__restrict__ r_raw,
                                                       const uint64_t *__restrict__ r_len_dev, ChainArgs args,
-                                                      uint32_t items_cap, uint32_t *__restrict__ stage,
-                                                      uint32_t *__restrict__ counts, uint32_t gallop_blocks) {
+                                                      RunScratch rs, uint64_t epoch, uint32_t *__restrict__ out,
+                                                      uint64_t *__restrict__ count, uint32_t gallop_blocks) {
   __shared__ ItemLds lds[WAVES];
   const uint32_t w = threadIdx.x >> 6;
-  const uint32_t item = blockIdx.x * WAVES + w;
-  if (item >= items_cap) return;
+  const uint32_t lane = lane_id();
+  uint32_t ticket = 0;
+  if (lane == 0) ticket = run_ticket(rs.ticket, uint32_t(epoch));
+  const uint32_t item = uniform(uint32_t(__shfl(int(ticket), 0)));
+  if (item >= rs.items_cap) return;
   RSide r;
   r.L = rl;
   r.raw = r_raw;
-  r.len = r_raw ? *r_len_dev : rl.n;
+  // raw values: rl.n holds the host's bound on their count
+  r.len = r_raw ? min(*r_len_dev, rl.n) : rl.n;
   const uint64_t n_items = (r.len + kBlock - 1) / kBlock;
-  if (item >= n_items) {
-    if (lane_id() == 0) counts[item] = 0;
-    return;
-  }
   Traffic tr;
-  const uint32_t cnt = chain_chunk<FEAT>(r, item, args.f[0], [&](uint32_t j) -> const DList & { return args.f[j]; },
-                                         args.nf, lds[w], gallop_blocks, tr);
-  store_chunk(cnt, lds[w], stage + uint64_t(item) * kBlock, counts + item);
+  uint32_t cnt = 0;
+  if (item < n_items)
+    cnt = chain_chunk<FEAT>(r, item, args.f[0], [&](uint32_t j) -> const DList & { return args.f[j]; }, args.nf,
+                            lds[w], gallop_blocks, tr);
+  bool ok = true;
+  const uint32_t excl = run_lookback(rs, item, epoch, cnt, ok);
+  if (ok) {
+    if (lane < cnt) gbl_out(out)[uint64_t(excl) + lane] = lds[w].r[lane];
+    if (lane + 64 < cnt) gbl_out(out)[uint64_t(excl) + 64 + lane] = lds[w].r[lane + 64];
+  }
+  if (item + 1 == rs.items_cap && lane == 0) *gbl_out(count) = ok ? uint64_t(excl) + cnt : kRunFailed;
 }
 
 // Exclusive scan of counts[n] in tiles of 1024 (256 threads x 4): local
@@ -660,65 +760,72 @@ int build_arena(Upload &u, hipStream_t stream, void **arena_out, std::vector<DLi
 
 // ---------------------------------------------------------- pair pipeline
 
-// Scratch of one pairwise step whose short side has at most cap_r values.
-struct PairScratch {
-  uint32_t *stage, *counts, *excl, *tiles;
-  uint32_t items_cap, ntiles;
-};
-
-static size_t pair_scratch_layout(uint64_t cap_r, char *base, PairScratch *ps) {
+// Layout of a run's scratch when its short side has at most cap_r values
+// (bytes needed; fills *rs when base is given).
+static size_t run_scratch_layout(uint64_t cap_r, char *base, RunScratch *rs) {
   const uint64_t items = (cap_r + kBlock - 1) / kBlock;
-  const uint64_t ntiles = (items + 1023) / 1024;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = align_up(off + bytes, 256);
     return o;
   };
-  size_t st = take(4 * kBlock * items), co = take(4 * items), ex = take(4 * items), ti = take(4 * ntiles + 4);
-  if (ps) {
-    ps->stage = reinterpret_cast<uint32_t *>(base + st);
-    ps->counts = reinterpret_cast<uint32_t *>(base + co);
-    ps->excl = reinterpret_cast<uint32_t *>(base + ex);
-    ps->tiles = reinterpret_cast<uint32_t *>(base + ti);
-    ps->items_cap = uint32_t(items);
-    ps->ntiles = uint32_t(ntiles);
+  const size_t tk = take(8), tg = take(8 * items), ag = take(4 * items), in = take(4 * items);
+  if (rs) {
+    rs->ticket = reinterpret_cast<uint64_t *>(base + tk);
+    rs->tag = reinterpret_cast<uint64_t *>(base + tg);
+    rs->agg = reinterpret_cast<uint32_t *>(base + ag);
+    rs->incl = reinterpret_cast<uint32_t *>(base + in);
+    rs->items_cap = uint32_t(items);
   }
   return off;
+}
+
+// Epochs of runs, process-wide: a run's tags never match those an earlier
+// run left in the same scratch.  Epochs whose low 32 bits are zero are
+// skipped, so a zeroed ticket word never looks current.
+static std::atomic<uint64_t> g_run_epoch{0};
+static uint64_t next_run_epoch() {
+  uint64_t e;
+  do e = g_run_epoch.fetch_add(1, std::memory_order_relaxed) + 1;
+  while (uint32_t(e) == 0);
+  return e;
 }
 
 // Lists given as handles are never bitmaps; the patched instantiation is
 // used only when a patched list takes part.
 template <int WAVES>
 static void launch_chain_w(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const ChainArgs &args,
-                           const PairScratch &ps, hipStream_t stream) {
-  const uint32_t groups = std::max<uint32_t>(1, (ps.items_cap + WAVES - 1) / WAVES);
+                           const RunScratch &rs, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
+  const uint32_t groups = std::max<uint32_t>(1, (rs.items_cap + WAVES - 1) / WAVES);
   bool patched = !r_raw && is_patched(r);
   for (uint32_t j = 0; j < args.nf; ++j) patched |= is_patched(args.f[j]);
+  const uint64_t epoch = next_run_epoch();
+  const uint32_t gb = std::min(tuning().gallop_blocks, kMaxGallopBlocks);
   if (patched)
     hipLaunchKernelGGL((k_chain<WAVES, kFeatPatched>), dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len,
-                       args, ps.items_cap, ps.stage, ps.counts, std::min(tuning().gallop_blocks, kMaxGallopBlocks));
+                       args, rs, epoch, d_out, d_count, gb);
   else
-    hipLaunchKernelGGL((k_chain<WAVES, 0>), dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len, args,
-                       ps.items_cap, ps.stage, ps.counts, std::min(tuning().gallop_blocks, kMaxGallopBlocks));
+    hipLaunchKernelGGL((k_chain<WAVES, 0>), dim3(groups), dim3(WAVES * 64), 0, stream, r, r_raw, r_len, args, rs,
+                       epoch, d_out, d_count, gb);
 }
 
-// chunk kernel -> tile scan -> top scan -> ordered compaction; count to d_count.
+// One launch: chunk kernel with look-back compaction; count to d_count.
 static int run_chain(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const ChainArgs &args,
-                     const PairScratch &ps, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
-  if (ps.items_cap == 0) {
+                     const RunScratch &rs, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
+  if (rs.items_cap == 0) {
     hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, stream, d_count, uint64_t(0));
     S4_HIP(hipGetLastError());
     return S4_OK;
   }
   switch (tuning().waves_per_group) {
-    case 1: launch_chain_w<1>(r, r_raw, r_len, args, ps, stream); break;
-    case 2: launch_chain_w<2>(r, r_raw, r_len, args, ps, stream); break;
-    case 8: launch_chain_w<8>(r, r_raw, r_len, args, ps, stream); break;
-    default: launch_chain_w<4>(r, r_raw, r_len, args, ps, stream); break;
+    case 1: launch_chain_w<1>(r, r_raw, r_len, args, rs, d_out, d_count, stream); break;
+    case 2: launch_chain_w<2>(r, r_raw, r_len, args, rs, d_out, d_count, stream); break;
+    case 8: launch_chain_w<8>(r, r_raw, r_len, args, rs, d_out, d_count, stream); break;
+    default: launch_chain_w<4>(r, r_raw, r_len, args, rs, d_out, d_count, stream); break;
   }
   S4_HIP(hipGetLastError());
-  return scan_and_compact(ps.stage, ps.counts, ps.items_cap, ps.excl, ps.tiles, ps.ntiles, d_count, d_out, stream);
+  return S4_OK;
 }
 
 int scan_and_compact(const uint32_t *stage, const uint32_t *counts, uint32_t n, uint32_t *excl, uint32_t *tiles,
@@ -731,11 +838,11 @@ int scan_and_compact(const uint32_t *stage, const uint32_t *counts, uint32_t n, 
 }
 
 static int run_pair(const DList &r, const uint32_t *r_raw, const uint64_t *r_len, const DList &f,
-                    const PairScratch &ps, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
+                    const RunScratch &rs, uint32_t *d_out, uint64_t *d_count, hipStream_t stream) {
   ChainArgs args;
   args.f[0] = f;
   args.nf = 1;
-  return run_chain(r, r_raw, r_len, args, ps, d_out, d_count, stream);
+  return run_chain(r, r_raw, r_len, args, rs, d_out, d_count, stream);
 }
 
 template <int P, bool PK>
@@ -1087,7 +1194,7 @@ int s4_spin_dev(uint64_t ns, void *stream) {
 }
 
 size_t s4_intersect_scratch_bytes(uint64_t len_a, uint64_t len_b) {
-  return pair_scratch_layout(std::min(len_a, len_b), nullptr, nullptr);
+  return run_scratch_layout(std::min(len_a, len_b), nullptr, nullptr);
 }
 
 int s4_intersect(const s4_list *a, const s4_list *b, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
@@ -1097,17 +1204,17 @@ int s4_intersect(const s4_list *a, const s4_list *b, uint32_t *d_out, uint64_t c
   const s4_list *r = a->n <= b->n ? a : b;
   const s4_list *f = a->n <= b->n ? b : a;
   if (cap < r->n) return fail(S4_ERANGE, "cap < min(len a, len b)");
-  const size_t need = pair_scratch_layout(r->n, nullptr, nullptr);
+  const size_t need = run_scratch_layout(r->n, nullptr, nullptr);
   if (scratch_bytes < need || (!d_scratch && need)) return fail(S4_ERANGE, "scratch too small");
   if (r->n && !d_out) return fail(S4_EINVAL, "null d_out");
   int rc = ensure_device();
   if (rc) return rc;
-  PairScratch ps;
-  pair_scratch_layout(r->n, static_cast<char *>(d_scratch), &ps);
+  RunScratch ps;
+  run_scratch_layout(r->n, static_cast<char *>(d_scratch), &ps);
   return run_pair(r->d, nullptr, nullptr, f->d, ps, d_out, d_count, as_stream(stream));
 }
 
-size_t s4_intersect_raw_scratch_bytes(uint64_t cap_r) { return pair_scratch_layout(cap_r, nullptr, nullptr); }
+size_t s4_intersect_raw_scratch_bytes(uint64_t cap_r) { return run_scratch_layout(cap_r, nullptr, nullptr); }
 
 int s4_intersect_raw(const uint32_t *d_r, const uint64_t *d_len_r, uint64_t cap_r, const s4_list *f,
                      uint32_t *d_out, uint64_t cap, uint64_t *d_count, void *d_scratch, size_t scratch_bytes,
@@ -1116,13 +1223,14 @@ int s4_intersect_raw(const uint32_t *d_r, const uint64_t *d_len_r, uint64_t cap_
   if (!(f->flags & 1u)) return fail(S4_EUNSORTED, "intersection inputs must be strictly increasing");
   if (cap < std::min(cap_r, f->n)) return fail(S4_ERANGE, "cap too small");
   const uint64_t cr = cap_r;
-  const size_t need = pair_scratch_layout(cr, nullptr, nullptr);
+  const size_t need = run_scratch_layout(cr, nullptr, nullptr);
   if (scratch_bytes < need || (!d_scratch && need)) return fail(S4_ERANGE, "scratch too small");
   int rc = ensure_device();
   if (rc) return rc;
-  PairScratch ps;
-  pair_scratch_layout(cr, static_cast<char *>(d_scratch), &ps);
+  RunScratch ps;
+  run_scratch_layout(cr, static_cast<char *>(d_scratch), &ps);
   DList none{};
+  none.n = cr;  // the kernel reads at most cap_r raw values
   return run_pair(none, d_r, d_len_r, f->d, ps, d_out, d_count, as_stream(stream));
 }
 
@@ -1132,44 +1240,87 @@ size_t s4_intersect_k_scratch_bytes(const s4_list *const *lists, uint32_t k) {
   for (uint32_t i = 0; i < k; ++i)
     if (lists[i]) m = std::min(m, lists[i]->n);
   if (m == UINT64_MAX) return 0;
-  return pair_scratch_layout(m, nullptr, nullptr);
+  return run_scratch_layout(m, nullptr, nullptr);
 }
 
-int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
-                   void *d_scratch, size_t scratch_bytes, void *stream) {
+}  // extern "C"
+
+// Checks a conjunction's arguments and orders its lists shortest first into
+// ord[0 .. k) (stable, so equal lengths keep their given order: SvS).
+static int order_conjunction(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap,
+                             uint64_t *d_count, const s4_list **ord) {
   if (!lists || k == 0 || !d_count) return fail(S4_EINVAL, "s4_intersect_k: need k >= 1 lists and d_count");
   if (k > kMaxTerms + 1) return fail(S4_EINVAL, "s4_intersect_k: at most 33 lists");
-  std::vector<const s4_list *> ord(lists, lists + k);
-  for (auto *l : ord)
-    if (!l) return fail(S4_EINVAL, "null list");
-  // SvS: shortest first (stable, so equal lengths keep their given order)
-  std::stable_sort(ord.begin(), ord.end(), [](const s4_list *x, const s4_list *y) { return x->n < y->n; });
+  for (uint32_t i = 0; i < k; ++i) {
+    if (!lists[i]) return fail(S4_EINVAL, "null list");
+    uint32_t j = i;
+    for (; j > 0 && ord[j - 1]->n > lists[i]->n; --j) ord[j] = ord[j - 1];
+    ord[j] = lists[i];
+  }
   const uint64_t m = ord[0]->n;
   if (cap < m) return fail(S4_ERANGE, "cap < length of the shortest list");
   if (m && !d_out) return fail(S4_EINVAL, "null d_out");
-  hipStream_t st = as_stream(stream);
-  int rc = ensure_device();
-  if (rc) return rc;
   if (k == 1) {
     if (reinterpret_cast<uintptr_t>(d_out) & 15u) return fail(S4_EINVAL, "d_out must be 16-byte aligned");
-    if (m) {
-      rc = decode_range(ord[0]->d, 0, ord[0]->nb + (ord[0]->t ? 1 : 0), d_out, st);
+    return S4_OK;
+  }
+  for (uint32_t i = 0; i < k; ++i)
+    if (!(ord[i]->flags & 1u)) return fail(S4_EUNSORTED, "intersection inputs must be strictly increasing");
+  return S4_OK;
+}
+
+// The ordered conjunction on scratch rs: k = 1 decodes the list and sets
+// the count; otherwise one chain launch.
+static int run_conjunction(const s4_list *const *ord, uint32_t k, const RunScratch &rs, uint32_t *d_out,
+                           uint64_t *d_count, hipStream_t st) {
+  if (k == 1) {
+    if (ord[0]->n) {
+      const int rc = decode_range(ord[0]->d, 0, ord[0]->nb + (ord[0]->t ? 1 : 0), d_out, st);
       if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, d_count, m);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, st, d_count, ord[0]->n);
     S4_HIP(hipGetLastError());
     return S4_OK;
   }
-  for (auto *l : ord)
-    if (!(l->flags & 1u)) return fail(S4_EUNSORTED, "intersection inputs must be strictly increasing");
-  const size_t need = pair_scratch_layout(m, nullptr, nullptr);
-  if (scratch_bytes < need || !d_scratch) return fail(S4_ERANGE, "scratch too small");
-  PairScratch ps;
-  pair_scratch_layout(m, static_cast<char *>(d_scratch), &ps);
   ChainArgs args;
   args.nf = k - 1;
   for (uint32_t i = 1; i < k; ++i) args.f[i - 1] = ord[i]->d;
-  return run_chain(ord[0]->d, nullptr, nullptr, args, ps, d_out, d_count, st);
+  return run_chain(ord[0]->d, nullptr, nullptr, args, rs, d_out, d_count, st);
+}
+
+namespace s4 {
+
+size_t conjunction_scratch_bytes(uint64_t m) { return run_scratch_layout(m, nullptr, nullptr); }
+
+int enqueue_conjunction(const DList *ord, uint32_t k, void *scratch, uint32_t *d_out, uint64_t *d_count,
+                        hipStream_t st) {
+  if (k < 2 || k > kMaxTerms + 1) return fail(S4_EINVAL, "a conjunction takes 2 to 33 lists");
+  RunScratch rs{};
+  run_scratch_layout(ord[0].n, static_cast<char *>(scratch), &rs);
+  ChainArgs args;
+  args.nf = k - 1;
+  for (uint32_t i = 1; i < k; ++i) args.f[i - 1] = ord[i];
+  return run_chain(ord[0], nullptr, nullptr, args, rs, d_out, d_count, st);
+}
+
+}  // namespace s4
+
+extern "C" {
+
+int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
+                   void *d_scratch, size_t scratch_bytes, void *stream) {
+  const s4_list *ord[kMaxTerms + 1];
+  int rc = order_conjunction(lists, k, d_out, cap, d_count, ord);
+  if (rc) return rc;
+  rc = ensure_device();
+  if (rc) return rc;
+  RunScratch rs{};
+  if (k > 1) {
+    const size_t need = run_scratch_layout(ord[0]->n, nullptr, nullptr);
+    if (scratch_bytes < need || !d_scratch) return fail(S4_ERANGE, "scratch too small");
+    run_scratch_layout(ord[0]->n, static_cast<char *>(d_scratch), &rs);
+  }
+  return run_conjunction(ord, k, rs, d_out, d_count, as_stream(stream));
 }
 
 }  // extern "C"

@@ -162,6 +162,14 @@ int decode_range_timed(const DList &L, uint32_t first, uint32_t count, uint32_t 
 int scan_and_compact(const uint32_t *stage, const uint32_t *counts, uint32_t n, uint32_t *excl, uint32_t *tiles,
                      uint32_t ntiles, uint64_t *total, uint32_t *out, hipStream_t stream);
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+// One conjunction as a single launch on st: lists ord[0 .. k) (2 <= k <= 33,
+// shortest first, compressed, strictly increasing; none a bitmap), results
+// to d_out[ord[0].n], count to *d_count.  scratch holds
+// conjunction_scratch_bytes(ord[0].n) bytes; runs sharing it must not
+// overlap.
+size_t conjunction_scratch_bytes(uint64_t m);
+int enqueue_conjunction(const DList *ord, uint32_t k, void *scratch, uint32_t *d_out, uint64_t *d_count,
+                        hipStream_t st);
 
 // Device tables of a batch of conjunctive queries (planned on the host).
 struct BatchDev {

@@ -63,6 +63,12 @@ __device__ __forceinline__ uint32_t scan_wave64(uint32_t v) {
   return v;
 }
 
+// Sum over the wave.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += uint32_t(__shfl_xor(int(v), o));
+  return v;
+}
+
 // Global-memory views of device pointers.  Lists, tables and outputs live
 // in global memory, but pointers read from descriptor tables reach the
 // compiler as generic ones, whose loads and stores become flat accesses that

@@ -707,15 +707,16 @@ int s4_server_stats_get(const s4_server *s, s4_server_stats *st) {
 
 int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
                      const uint64_t *h_arrival_ns, uint64_t *latency_ns, uint64_t *counts, uint32_t *results,
-                     uint64_t results_cap, uint64_t *res_offsets, double timeout_s, double *elapsed_s) {
+                     uint64_t results_cap, uint64_t *res_offsets, const uint8_t *keep, double timeout_s,
+                     double *elapsed_s) {
   if (!s || !h_q_offsets || !h_arrival_ns || !latency_ns || !counts || (nq && !h_terms))
     return fail(S4_EINVAL, "null argument");
   if (results && !res_offsets) return fail(S4_EINVAL, "results need res_offsets");
   // results stay in the batches they arrived in until the end: query q's
   // are entry where[q].second of kept[where[q].first], or, for a query run
-  // in slices, its parts
+  // in slices or picked by keep, its parts (a copy, so batches are not held)
   std::vector<DoneBatch> kept;
-  std::vector<std::pair<uint32_t, uint32_t>> where(results ? nq : 0, {UINT32_MAX, 0u});
+  std::vector<std::pair<uint32_t, uint32_t>> where(results && !keep ? nq : 0, {UINT32_MAX, 0u});
   std::unordered_map<uint64_t, std::vector<std::vector<uint32_t>>> res_parts;
   uint64_t ndone = 0, next = 0;
   // query of each id this replay assigned: ids are handed out in order under
@@ -789,15 +790,19 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
       DoneBatch &b = got.front();
       for (size_t i = b.next; i < b.size(); ++i) {
         const uint64_t q = finish(b.ids[i], b.count(i), b.at);
-        if (q != UINT64_MAX && results) where[q] = {uint32_t(kept.size()), uint32_t(i)};
+        if (q == UINT64_MAX || !results) continue;
+        if (!keep)
+          where[q] = {uint32_t(kept.size()), uint32_t(i)};
+        else if (keep[q])
+          res_parts[q].emplace_back(b.results.begin() + b.offs[i], b.results.begin() + b.offs[i + 1]);
       }
-      if (results) kept.push_back(std::move(b));
+      if (results && !keep) kept.push_back(std::move(b));
       got.pop_front();
     }
     while (!got_jobs.empty()) {
       DoneJob &d = got_jobs.front();
       const uint64_t q = finish(d.id, d.count, d.at);
-      if (q != UINT64_MAX && results) res_parts[q] = std::move(d.parts);
+      if (q != UINT64_MAX && results && (!keep || keep[q])) res_parts[q] = std::move(d.parts);
       got_jobs.pop_front();
     }
     if (double(now_ns()) * 1e-9 > timeout_s) return fail(S4_ERANGE, "replay timed out");
@@ -811,6 +816,10 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
     uint64_t used = 0;
     res_offsets[0] = 0;
     for (uint64_t q = 0; q < nq; ++q) {
+      if (keep && !keep[q]) {
+        res_offsets[q + 1] = used;
+        continue;
+      }
       if (used + counts[q] > results_cap) return fail(S4_ERANGE, "results_cap too small");
       auto it = res_parts.find(q);
       if (it != res_parts.end()) {

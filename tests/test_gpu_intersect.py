@@ -155,3 +155,47 @@ def test_raw_side(gpu):
     out, cnt = gpu.intersect_raw(rt, ln, r.size + 300, dev(gpu, f))
     c = int(cnt.item())
     assert np.array_equal(out[:c].cpu().numpy().view(np.uint32), oracle.intersect(r, f))
+
+
+def test_single_launch_many_chunks(gpu):
+    """One launch, far more chunks than resident waves (2^22 values in the
+    shortest list: 32768 chunks): every chunk's offset comes from the
+    look-back; results equal the merge."""
+    n = 1 << 22
+    log("single launch: shortest 2^22")
+    a = workloads.sorted_list(workloads.CLUSTERED, 77, 1 << 26, n)
+    b = workloads.sorted_list(workloads.CLUSTERED, 78, 1 << 26, n + 12345)
+    la, lb = dev(gpu, a), dev(gpu, b)
+    out, cnt = gpu.intersect(la, lb)
+    c = int(cnt.item())
+    assert c != 2**64 - 1 and c < 2**63
+    assert np.array_equal(out[:c].cpu().numpy().view(np.uint32), oracle.intersect(a, b))
+    # self-intersection: every chunk survives whole
+    out, cnt = gpu.intersect(la, la)
+    assert int(cnt.item()) == n
+    assert np.array_equal(out[:n].cpu().numpy().view(np.uint32), a)
+
+
+def test_scratch_reused_across_calls(gpu):
+    """Calls of different sizes back to back on one scratch buffer, never
+    cleared: each call's scan words carry their own epoch, so counts left
+    by earlier calls are never read."""
+    import torch
+    rng = np.random.default_rng(9)
+    big = workloads.sorted_list(workloads.UNIFORM, 80, 1 << 24, 1 << 19)
+    lbig = dev(gpu, big)
+    scratch = torch.zeros(gpu.intersect_k_scratch_bytes([lbig, lbig]) + 4096, dtype=torch.uint8, device="cuda")
+    out = torch.empty(1 << 19, dtype=torch.int32, device="cuda")
+    cnts = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in range(12)]
+    cases = []
+    for i, m in enumerate([1 << 19, 1000, 129, 1 << 17, 1, 5000, 1 << 19, 128, 70000, 3, 1 << 18, 777]):
+        r = np.sort(rng.choice(big, size=min(m, big.size), replace=False)).astype(np.uint32) if i % 2 else \
+            workloads.sorted_list(workloads.UNIFORM, 90 + i, 1 << 24, m)
+        cases.append((r, dev(gpu, r)))
+    res = []
+    for (r, lr), c in zip(cases, cnts):
+        gpu.intersect_k([lr, lbig], out=out, count=c, scratch=scratch)
+        k = int(c.item())
+        res.append(out[:k].cpu().numpy().view(np.uint32).copy())
+    for (r, _), got in zip(cases, res):
+        assert np.array_equal(got, oracle.intersect(r, big))
