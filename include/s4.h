@@ -49,6 +49,10 @@ extern "C" {
 
 const char *s4_last_error(void);
 int s4_version(void); /* stream format version written by s4_encode (1) */
+/* Optional set-up of the current device: checks that it is a gfx950 part
+ * and looks up the device address of the library's static scratch
+ * (s4_intersect_k_noalloc); every call does this itself on first use. */
+int s4_init(void);
 
 /* ------------------------------------------------------------------ codec
  *
@@ -291,6 +295,24 @@ size_t s4_intersect_raw_scratch_bytes(uint64_t cap_r);
 int s4_intersect_raw(const uint32_t *d_r, const uint64_t *d_len_r, uint64_t cap_r,
                      const s4_list *f, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
                      void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * k-way conjunction of s4_intersect_k, with its scratch taken from a static
+ * device array of S4_NOALLOC_SCRATCH_BYTES per device that the library
+ * holds until the process ends.  The call allocates nothing; the caller
+ * passes lists, outputs and stream as for s4_intersect_k.  The shortest
+ * list may hold at most s4_intersect_k_noalloc_max_len() values
+ * (33,550,336 = 262,112 chunks of 128 in 4 MiB), else S4_ERANGE.  Every call on a device shares
+ * that device's array: calls that overlap on one GPU (other streams, or
+ * other threads without ordering) race and give wrong results; calls
+ * ordered on one stream are safe, and the array needs no clearing between
+ * them.  The array's device address is looked up once per device, by
+ * s4_init or by the first call there. */
+#define S4_NOALLOC_SCRATCH_BYTES (4u << 20)
+uint64_t s4_intersect_k_noalloc_max_len(void);
+int s4_intersect_k_noalloc(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap,
+                           uint64_t *d_count, void *stream);
 
 /* ---------------------------------------------------------------- tuning
  *

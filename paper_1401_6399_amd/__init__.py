@@ -62,6 +62,7 @@ class ServerStats(ctypes.Structure):
 SIGNATURES = {
     "s4_last_error": (ctypes.c_char_p, []),
     "s4_version": (_i, []),
+    "s4_init": (_i, []),
     "s4_encoded_bound": (_sz, [_u64]),
     "s4_encode": (_i, [_u32p, _u64, _u8p, _sz, ctypes.POINTER(_sz)]),
     "s4_encode_ex": (_i, [_u32p, _u64, _u32, _u8p, _sz, ctypes.POINTER(_sz)]),
@@ -91,6 +92,8 @@ SIGNATURES = {
     "s4_intersect_k_scratch_bytes": (_sz, [ctypes.POINTER(_vp), _u32]),
     "s4_intersect_k": (_i, [ctypes.POINTER(_vp), _u32, _vp, _u64, _vp, _vp, _sz, _vp]),
     "s4_intersect_raw_scratch_bytes": (_sz, [_u64]),
+    "s4_intersect_k_noalloc_max_len": (_u64, []),
+    "s4_intersect_k_noalloc": (_i, [ctypes.POINTER(_vp), _u32, _vp, _u64, _vp, _vp]),
     "s4_intersect_raw": (_i, [_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp, _sz, _vp]),
     "s4_get_tuning": (_i, [ctypes.POINTER(Tuning)]),
     "s4_set_tuning": (_i, [ctypes.POINTER(Tuning)]),
@@ -176,6 +179,12 @@ def _stream(stream=None):
 
 
 # ------------------------------------------------------------------ codec
+
+def init():
+    """Set up the current device (s4_init): checks it and looks up the
+    static scratch of intersect_k_noalloc."""
+    _check(require_library().s4_init(), "s4_init")
+
 
 def encoded_bound(n: int) -> int:
     return int(require_library().s4_encoded_bound(n))
@@ -465,6 +474,25 @@ def intersect_k(lists, out=None, count=None, scratch=None, stream=None):
     _check(lib.s4_intersect_k(_handles(lists), len(lists), _dptr(out), out.numel(), _dptr(count),
                               _dptr(scratch), scratch.numel(), _stream(stream)), "s4_intersect_k")
     return out, count
+
+
+def intersect_k_noalloc(lists, out=None, count=None, stream=None):
+    """intersect_k with the library's static device scratch (no allocation
+    in the library; out and count are allocated here when not given)."""
+    import torch
+    lib = require_library()
+    m = min(l.n for l in lists) if lists else 0
+    if out is None:
+        out = torch.empty(max(1, m), dtype=torch.int32, device="cuda")
+    if count is None:
+        count = _device_u64()
+    _check(lib.s4_intersect_k_noalloc(_handles(lists), len(lists), _dptr(out), out.numel(), _dptr(count),
+                                      _stream(stream)), "s4_intersect_k_noalloc")
+    return out, count
+
+
+def intersect_k_noalloc_max_len() -> int:
+    return int(require_library().s4_intersect_k_noalloc_max_len())
 
 
 def intersect_raw(r, r_len, cap_r, f: DeviceList, out=None, count=None, scratch=None, stream=None):

@@ -1305,7 +1305,46 @@ int enqueue_conjunction(const DList *ord, uint32_t k, void *scratch, uint32_t *d
 
 }  // namespace s4
 
+// Scratch of s4_intersect_k_noalloc: one array per device, for callers that
+// cannot allocate; its device address is looked up once per device.
+static __device__ __align__(256) uint8_t scratch[S4_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_static_mu;
+static std::map<int, char *> g_static_ptr;
+
+static int static_scratch(char **out) {
+  int dev = 0;
+  S4_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  auto it = g_static_ptr.find(dev);
+  if (it == g_static_ptr.end()) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || (reinterpret_cast<uintptr_t>(p) & 255u)) return fail(S4_EDEVICE, "static scratch address unusable");
+    it = g_static_ptr.emplace(dev, static_cast<char *>(p)).first;
+  }
+  *out = it->second;
+  return S4_OK;
+}
+
+// Longest shortest list the static scratch serves.
+static uint64_t noalloc_max_len() {
+  uint64_t lo = 0, hi = uint64_t(S4_NOALLOC_SCRATCH_BYTES) * 8;  // fits at lo, not at hi
+  while (hi - lo > 1) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (run_scratch_layout(mid, nullptr, nullptr) <= S4_NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 extern "C" {
+
+int s4_init(void) {
+  int rc = ensure_device();
+  if (rc) return rc;
+  char *p = nullptr;
+  return static_scratch(&p);
+}
 
 int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap, uint64_t *d_count,
                    void *d_scratch, size_t scratch_bytes, void *stream) {
@@ -1320,6 +1359,27 @@ int s4_intersect_k(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uin
     if (scratch_bytes < need || !d_scratch) return fail(S4_ERANGE, "scratch too small");
     run_scratch_layout(ord[0]->n, static_cast<char *>(d_scratch), &rs);
   }
+  return run_conjunction(ord, k, rs, d_out, d_count, as_stream(stream));
+}
+
+uint64_t s4_intersect_k_noalloc_max_len(void) { return noalloc_max_len(); }
+
+int s4_intersect_k_noalloc(const s4_list *const *lists, uint32_t k, uint32_t *d_out, uint64_t cap,
+                           uint64_t *d_count, void *stream) {
+  const s4_list *ord[kMaxTerms + 1];
+  int rc = order_conjunction(lists, k, d_out, cap, d_count, ord);
+  if (rc) return rc;
+  static const uint64_t max_len = noalloc_max_len();
+  if (ord[0]->n > max_len)
+    return fail(S4_ERANGE, "s4_intersect_k_noalloc: shortest list has " + std::to_string(ord[0]->n) +
+                               " values; the static scratch serves at most " + std::to_string(max_len));
+  rc = ensure_device();
+  if (rc) return rc;
+  char *base = nullptr;
+  rc = static_scratch(&base);
+  if (rc) return rc;
+  RunScratch rs{};
+  run_scratch_layout(ord[0]->n, base, &rs);
   return run_conjunction(ord, k, rs, d_out, d_count, as_stream(stream));
 }
 
