@@ -123,6 +123,15 @@ int s4_encode_many(const uint32_t *in, const uint64_t *in_offsets, uint64_t coun
  * table (S4_ECORRUPT on any inconsistency). */
 int s4_decoded_length(const uint8_t *enc, size_t bytes, uint64_t *n);
 
+/* Host decode of a whole stream (any form, plain or patched) into host
+ * out[cap]; *n_out receives n (also when cap < n: S4_ERANGE, nothing
+ * written).  The stream is validated first as by s4_decoded_length
+ * (patched pages included).  For tools and checks on the host: the
+ * decoding path of this library is the device one (s4_decode_dev and the
+ * calls after it); this is a plain scalar loop (Alg. 1's extraction per
+ * value, the exceptions of Sec. 4.4, the form's inverse of Sec. 5). */
+int s4_decode(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, uint64_t *n_out);
+
 /* ----------------------------------------------------------- device lists
  *
  * Every device call below handles all four differential forms; lists of
@@ -234,6 +243,10 @@ int s4_aql_plan_enqueue(s4_aql_plan *plan, uint32_t steps, void *stream);
 int s4_aql_plan_status(s4_aql_plan *plan);
 int s4_aql_plan_profile(s4_aql_plan *plan, uint32_t steps, uint64_t *start_ns, uint64_t *end_ns,
                         uint64_t *elapsed_ns);
+/* Where each list's dispatch goes: queue_of[i] (0..3) and its position
+ * in that queue's order within a step (host arrays [count]; UINT32_MAX for
+ * a list with nothing to decode). */
+int s4_aql_plan_layout(const s4_aql_plan *plan, uint32_t *queue_of, uint32_t *position);
 int s4_aql_plan_free(s4_aql_plan *plan);
 
 /* A reusable multi-list decode: one kernel launch decodes every list of

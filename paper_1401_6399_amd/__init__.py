@@ -68,6 +68,7 @@ SIGNATURES = {
     "s4_encode_ex": (_i, [_u32p, _u64, _u32, _u8p, _sz, ctypes.POINTER(_sz)]),
     "s4_encode_many": (_i, [_u32p, _u64p, _u64, _u32, _u8p, _u64p, _u64p, _i]),
     "s4_decoded_length": (_i, [_u8p, _sz, _u64p]),
+    "s4_decode": (_i, [_u8p, _sz, _u32p, _u64, _u64p]),
     "s4_list_upload": (_i, [_u8p, _sz, _vp, ctypes.POINTER(_vp)]),
     "s4_list_free": (_i, [_vp]),
     "s4_list_info": (_i, [_vp, _u64p, _u32p, _u32p, _u64p, _u64p]),
@@ -85,6 +86,7 @@ SIGNATURES = {
     "s4_aql_plan_enqueue": (_i, [_vp, _u32, _vp]),
     "s4_aql_plan_status": (_i, [_vp]),
     "s4_aql_plan_profile": (_i, [_vp, _u32, _u64p, _u64p, _u64p]),
+    "s4_aql_plan_layout": (_i, [_vp, _u32p, _u32p]),
     "s4_aql_plan_free": (_i, [_vp]),
     "s4_spin_dev": (_i, [_u64, _vp]),
     "s4_intersect_scratch_bytes": (_sz, [_u64, _u64]),
@@ -246,6 +248,19 @@ def encode_many(flat, offsets, nthreads: int = 0, delta: int = DELTA_D4, patched
     return packed[: int(offs[-1])], offs
 
 
+def decode_host(enc) -> np.ndarray:
+    """Host decode of a stream (s4_decode): a scalar loop in the library,
+    for tools and checks; the decoding path is the device one."""
+    lib = require_library()
+    enc = np.ascontiguousarray(enc, dtype=np.uint8)
+    n = decoded_length(enc)
+    out = np.zeros(max(1, n), np.uint32)
+    got = ctypes.c_uint64(0)
+    _check(lib.s4_decode(_ptr(enc, ctypes.c_uint8), enc.size, _ptr(out, ctypes.c_uint32), n, ctypes.byref(got)),
+           "s4_decode")
+    return out[:n]
+
+
 def decoded_length(enc) -> int:
     lib = require_library()
     enc = np.ascontiguousarray(enc, dtype=np.uint8)
@@ -395,6 +410,14 @@ class AqlDecodePlan:
     def status(self):
         """Raise if an enqueued run has failed."""
         _check(require_library().s4_aql_plan_status(self.h), "s4_aql_plan_status")
+
+    def layout(self):
+        """(queue of each list, its position in that queue's step order)."""
+        q = np.zeros(max(1, self.count), np.uint32)
+        p = np.zeros(max(1, self.count), np.uint32)
+        _check(require_library().s4_aql_plan_layout(self.h, _ptr(q, ctypes.c_uint32), _ptr(p, ctypes.c_uint32)),
+               "s4_aql_plan_layout")
+        return q[: self.count], p[: self.count]
 
     def profile(self, steps=1):
         """One profiled run: per-list device start and end (ns after the

@@ -405,6 +405,79 @@ int s4_encode_many(const uint32_t *in, const uint64_t *in_offsets, uint64_t coun
   return S4_OK;
 }
 
+int s4_decode(const uint8_t *enc, size_t bytes, uint32_t *out, uint64_t cap, uint64_t *n_out) {
+  if (!n_out) return fail(S4_EINVAL, "null n_out");
+  StreamView v;
+  int rc = parse_stream(enc, bytes, &v);
+  if (rc) return rc;
+  *n_out = v.n;
+  if (cap < v.n) return fail(S4_ERANGE, "s4_decode: cap < n");
+  if (v.n && !out) return fail(S4_EINVAL, "s4_decode: null out");
+  const uint32_t form = (v.flags >> 1) & 3u;
+  // 1. every block's deltas: value q of lane j is bits [q b, q b + b) of the
+  //    lane's LSB-first stream, whose m-th word is payload word 4 m + j
+  uint64_t wpos = 0;
+  for (uint64_t k = 0; k < v.nb; ++k) {
+    const uint32_t b = v.widths[k];
+    const uint8_t *w = v.payload + 4 * wpos;
+    uint32_t *d = out + k * kBlock;
+    const uint64_t mask = (uint64_t(1) << b) - 1u;
+    for (uint32_t j = 0; j < 4; ++j)
+      for (uint32_t q = 0; q < 32; ++q) {
+        if (b == 0) {
+          d[4 * q + j] = 0;
+          continue;
+        }
+        const uint32_t bit = q * b, m = bit >> 5, sh = bit & 31u;
+        uint64_t win = rd32(w + 4 * (4 * m + j));
+        if (sh + b > 32) win |= uint64_t(rd32(w + 4 * (4 * (m + 1) + j))) << 32;
+        d[4 * q + j] = uint32_t((win >> sh) & mask);
+      }
+    wpos += 4u * b;
+  }
+  // 2. patched streams: each exception's high bits (b - b' of them, from the
+  //    page's array for that difference, in order) go above its b' low bits
+  if (v.patched()) {
+    const uint8_t *p = v.pages;
+    for (uint64_t k0 = 0; k0 < v.nb; k0 += kPage) {
+      const uint64_t k1 = std::min<uint64_t>(v.nb, k0 + kPage);
+      const uint32_t meta_len = rd32(p);
+      const uint8_t *m = p + 4;
+      const uint8_t *q = m + round4(meta_len);
+      const uint32_t present = rd32(q);
+      q += 4;
+      const uint8_t *arr[33] = {nullptr};
+      uint64_t used[33] = {0};
+      for (uint32_t e = 1; e <= 32; ++e) {
+        if (!((present >> (e - 1)) & 1u)) continue;
+        const uint32_t count = rd32(q);
+        arr[e] = q + 4;
+        q += 4u + 4u * uint64_t(e) * ((count + 31u) / 32u);
+      }
+      uint64_t o = 0;
+      for (uint64_t k = k0; k < k1; ++k) {
+        const uint32_t b = m[o], c = m[o + 1], bp = v.widths[k];
+        o += 2;
+        for (uint32_t x = 0; x < c; ++x) {
+          const uint32_t pos = m[o + x], e = b - bp;
+          const uint64_t bit = used[e]++ * e, wi = bit >> 5, sh = bit & 31u;
+          uint64_t win = rd32(arr[e] + 4 * wi);
+          if (sh + e > 32) win |= uint64_t(rd32(arr[e] + 4 * (wi + 1))) << 32;
+          const uint64_t high = (win >> sh) & ((uint64_t(1) << e) - 1u);
+          out[k * kBlock + pos] |= uint32_t(high << bp);
+        }
+        o += c;
+      }
+      p = q;
+    }
+  }
+  // 3. the form's inverse in index order (x_i = delta_i + the value the form
+  //    subtracts, Sec. 5), then the raw tail
+  for (uint64_t i = 0; i < uint64_t(v.nb) * kBlock; ++i) out[i] += reference(out, i, form);
+  for (uint32_t i = 0; i < v.t; ++i) out[uint64_t(v.nb) * kBlock + i] = rd32(v.tail + 4 * i);
+  return S4_OK;
+}
+
 int s4_decoded_length(const uint8_t *enc, size_t bytes, uint64_t *n) {
   if (!n) return fail(S4_EINVAL, "null n");
   StreamView v;

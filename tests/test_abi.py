@@ -213,3 +213,37 @@ def test_batch_calls_refuse_a_null_batch():
     assert lib.s4_batch_set_counting(None, 0) == s4.EINVAL
     b, k = ctypes.c_uint64(0), ctypes.c_uint64(0)
     assert lib.s4_batch_traffic(None, ctypes.byref(b), ctypes.byref(k), None) == s4.EINVAL
+
+
+@pytest.mark.parametrize("delta", [0, 1, 2, 3])
+@pytest.mark.parametrize("patched", [False, True])
+@pytest.mark.parametrize("n", [0, 1, 127, 128, 129, 4097, 128 * 1100 + 77])
+def test_host_decode_matches_oracle(delta, patched, n):
+    """s4_decode (the library's host decoder) on streams of every form,
+    plain and patched (several pages), equals the oracle's decode and the
+    input; extreme values and duplicates too."""
+    for x in (workloads.sorted_list(workloads.CLUSTERED, 800 + n, 1 << 26, n), _with_outliers(n + 3 * delta, n)):
+        enc = oracle.encode(x, delta, patched=patched)
+        got = s4.decode_host(enc)
+        assert np.array_equal(got, oracle.decode(enc))
+        assert np.array_equal(got, x)
+    y = np.repeat(np.array([0, 5, 2**31, 2**32 - 1], np.uint32), 100)
+    enc = oracle.encode(y, delta, patched=patched)
+    assert np.array_equal(s4.decode_host(enc), y)
+
+
+def test_host_decode_errors():
+    x = workloads.sorted_list(workloads.UNIFORM, 5, 1 << 20, 1000)
+    enc = s4.encode(x)
+    lib = s4.require_library()
+    import ctypes
+    out = np.zeros(999, np.uint32)
+    n = ctypes.c_uint64(0)
+    rc = lib.s4_decode(enc.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), enc.size,
+                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 999, ctypes.byref(n))
+    assert rc == s4.ERANGE and n.value == 1000
+    bad = enc.copy()
+    bad[0] ^= 1
+    with pytest.raises(s4.S4Error) as e:
+        s4.decode_host(bad)
+    assert e.value.code == s4.ECORRUPT
