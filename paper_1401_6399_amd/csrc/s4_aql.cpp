@@ -497,7 +497,9 @@ int s4_aql_plan_profile(s4_aql_plan *plan, uint32_t steps, uint64_t *start_ns, u
   std::vector<hsa_signal_t> sig(nsig);
   size_t made = 0;
   for (; made < nsig; ++made)
-    if (hsa_amd_signal_create(1, 0, nullptr, HSA_AMD_SIGNAL_AMD_GPU_ONLY, &sig[made]) != HSA_STATUS_SUCCESS) break;
+    // ordinary signals: a tool that intercepts the queues may complete them
+    // from the host, which a GPU-only signal does not allow
+    if (hsa_signal_create(1, 0, nullptr, &sig[made]) != HSA_STATUS_SUCCESS) break;
   auto destroy = [&]() {
     for (size_t j = 0; j < made; ++j) (void)hsa_signal_destroy(sig[j]);
   };
@@ -560,6 +562,18 @@ int s4_aql_plan_status(s4_aql_plan *plan) {
   std::lock_guard<std::mutex> lock(g_mu);
   const int rc = plan->async_rc.load();
   if (rc) return fail(rc, "an enqueued run failed: " + plan->async_msg);
+  return S4_OK;
+}
+
+int s4_aql_plan_layout(const s4_aql_plan *plan, uint32_t *queue_of, uint32_t *position) {
+  if (!plan || !queue_of || !position) return fail(S4_EINVAL, "null argument");
+  std::fill(queue_of, queue_of + plan->count, UINT32_MAX);
+  std::fill(position, position + plan->count, UINT32_MAX);
+  for (uint32_t q = 0; q < kQueues; ++q)
+    for (size_t j = 0; j < plan->per_queue[q].size(); ++j) {
+      queue_of[plan->per_queue[q][j].list] = q;
+      position[plan->per_queue[q][j].list] = uint32_t(j);
+    }
   return S4_OK;
 }
 
