@@ -11,15 +11,22 @@ launches through HIP (forked streams, the step replayed as one hipGraph) are
 reported beside it.
 
 Also reported:
-  roofline      the decode kernel's algorithmic bytes (width bytes + packed
-                payload + raw tail read, 4 bytes per integer written) over its
-                average launch duration, measured with HIP events around each
-                launch on its own stream, against 8 TB/s HBM peak;
+  roofline      the step's algorithmic bytes (width bytes + packed payload +
+                raw tail read, 4 bytes per integer written) over its time in
+                the timed run, against 8 TB/s HBM peak; beside it a profiled
+                breakdown (device timestamp of every dispatch) and the same
+                kernel launched serially through HIP;
   single_launch the same lists decoded by one multi-list launch;
+  plain_config  the CPU-sized configuration (A = 2^20, B = 2^14): host
+                encode, GPU decode and intersect, and the oracle on one thread;
   batched       two-term and multi-term query batches (one persistent
-                decode-fused launch) against the plain one-launch-per-query
-                path, with p50 / p99 query latency;
-  cpu_baseline  the oracle's decode timed on the host cores.
+                decode-fused launch) against the plain path (one
+                single-launch conjunction per query, submitted from C++),
+                with the oracle's queries/s on a sample;
+  cpu_baseline  the oracle's decode timed on the host cores;
+  serving       the serving workload: sustained rate, three Poisson levels
+                with latency percentiles, the plain path and the oracle
+                beside each.
 
 Prints one JSON line.  --gpus N with N > 1 exits: the engine runs on one GPU
 (sharding by document-ID range across GPUs is a design, not code).
@@ -64,14 +71,29 @@ def parse():
                     help="turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs into profiles/decode_traffic.json")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving workload instead (index of 2^20 lists, Poisson arrivals at 3 levels)")
-    ap.add_argument("--serve-queries", type=int, default=1 << 20)
     ap.add_argument("--serve-lists", type=int, default=1 << 20)
     ap.add_argument("--serve-check", type=int, default=1 << 12,
                     help="queries per level checked against the oracle (0: none)")
     ap.add_argument("--calib-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="rocprofv3 CSVs of --calibrate-copy, for the counter scale factors")
     ap.add_argument("--batch-queries", type=int, default=1 << 18)
-    ap.add_argument("--plain-sample", type=int, default=4096)
+    ap.add_argument("--plain-sample", type=int, default=4096,
+                    help="queries whose isolated latency the plain path measures")
+    ap.add_argument("--cpu-queries", type=int, default=1 << 15,
+                    help="sample of the batched workloads the oracle's queries/s is timed on")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-level-s", type=float, default=30.0,
+                    help="length of each Poisson level of the serving leg (at least 2^16 queries)")
+    ap.add_argument("--serve-saturate", type=int, default=1 << 24,
+                    help="queries submitted at once to measure the serving burst rate")
+    ap.add_argument("--serve-saturate-s", type=float, default=10.0,
+                    help="length of the overloaded open-loop trace that measures the sustained rate Q*")
+    ap.add_argument("--serve-plain", type=int, default=1 << 14,
+                    help="queries of each level's trace replayed through the plain path")
+    ap.add_argument("--step-only", action="store_true",
+                    help="only the headline's per-list steps on the library's queues (for rocprofv3)")
+    ap.add_argument("--profile-steps", type=int, default=8,
+                    help="untimed steps run with per-dispatch device timestamps for the roofline")
     return ap.parse_args()
 
 
@@ -251,17 +273,44 @@ def delta_forms(s4, torch, flat, offs, outs, stream, steps, warmup, patched=Fals
     return res
 
 
-def batched(s4, workloads, torch, nq, plain_sample):
+def cpu_queries(encs, terms, qoffs, sample):
+    """The oracle's queries/s on a sample of a batch, all host threads:
+    each query decodes its lists from their (oracle-encoded) streams and
+    intersects them shortest first."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    threads = max(1, min(16, os.cpu_count() or 1))
+
+    def one(q):
+        ts = terms[int(qoffs[q]): int(qoffs[q + 1])]
+        return oracle.intersect_k(sorted((oracle.decode(encs[t]) for t in ts), key=len)).size
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as ex:
+        total = sum(ex.map(one, sample))
+    dt = time.perf_counter() - t0
+    return {"value": round(len(sample) / dt, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {len(sample)} queries: oracle decode of every term's list from its stream, "
+                      f"then intersect_k (two-pointer merge, shortest first); {threads} threads, {dt:.2f} s",
+            "results": int(total)}
+
+
+def batched(s4, workloads, torch, nq, plain_sample, cpu_sample):
     """Batched pairwise / multi-term queries vs the plain per-query path."""
     import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
     out = {}
     t0 = time.time()
     flat, offs = workloads.pairwise_index()
     buf, soffs = s4.encode_many(flat, offs)
     index = s4.Index(buf, soffs)
-    del flat
     log(f"index: {index.count} lists, {index.total_ints} ints, built in {time.time() - t0:.1f} s")
-    dev = torch.cuda.current_device()
+    # the oracle's own streams of every list (for its queries/s baseline)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(threads) as ex:
+        encs = list(ex.map(lambda i: oracle.encode(flat[int(offs[i]): int(offs[i + 1])]), range(index.count)))
+    del flat
     for name, qfn in (("pairwise", workloads.pairwise_queries), ("multiterm", workloads.multiterm_queries)):
         terms, qoffs = qfn(index.lengths, nq)
         b = s4.Batch(index, terms, qoffs)
@@ -270,46 +319,39 @@ def batched(s4, workloads, torch, nq, plain_sample):
         ms, _ = time_graph(torch, lambda: b.run(use_graph=False), stream, steps=5, warmup=2)
         ticks = b.query_ticks().astype(np.float64) / 100.0  # 100 MHz clock -> us
         abytes, ablocks = counted_traffic(b)
-        # plain path: one intersect_k call per query, on a sample
-        lists = [index.list(i) for i in range(index.count)] if name == "pairwise" else lists
-        sample = np.arange(min(plain_sample, b.nq))
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        lat = []
-        scratch = torch.empty(1 << 26, dtype=torch.uint8, device="cuda")
-        res = torch.empty(1 << 24, dtype=torch.int32, device="cuda")
-        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for q in sample:
-            ts = terms[int(qoffs[q]): int(qoffs[q + 1])]
-            s4.intersect_k([lists[t] for t in ts], out=res, count=cnt, scratch=scratch)
-        torch.cuda.synchronize()
-        plain_s = time.perf_counter() - t1
-        for q in sample[:256]:
-            ts = terms[int(qoffs[q]): int(qoffs[q + 1])]
-            e0.record()
-            s4.intersect_k([lists[t] for t in ts], out=res, count=cnt, scratch=scratch)
-            e1.record()
-            torch.cuda.synchronize()
-            lat.append(e0.elapsed_time(e1) * 1e3)
+        # plain path: every query its own single-launch conjunction, all of
+        # them back to back from C++, then a sample one at a time
+        pc, _, _, plain_ms, _ = s4.plain_run(index, terms, qoffs)
+        same = bool(torch.equal(pc, b.counts[: b.nq]))
+        ns_ = min(plain_sample, b.nq)
+        _, _, _, _, lat = s4.plain_run(index, terms[: int(qoffs[ns_])], qoffs[: ns_ + 1], isolate=True)
+        lat = lat.astype(np.float64) / 1e3
+        cpu = cpu_queries(encs, terms, qoffs, np.arange(min(cpu_sample, b.nq)))
         out[name] = {
             "queries": int(b.nq),
             "batched_qps": round(b.nq / (ms / 1e3), 1),
             "batched_ms": round(ms, 3),
-            "batch_p50_us": round(float(np.percentile(ticks, 50)), 1),
-            "batch_p99_us": round(float(np.percentile(ticks, 99)), 1),
-            "plain_qps": round(sample.size / plain_s, 1),
-            "plain_p50_us": round(float(np.percentile(lat, 50)), 1),
-            "plain_p99_us": round(float(np.percentile(lat, 99)), 1),
-            "speedup_vs_plain": round((b.nq / (ms / 1e3)) / (sample.size / plain_s), 2),
+            "batch_completion_p50_us": round(float(np.percentile(ticks, 50)), 1),
+            "batch_completion_p99_us": round(float(np.percentile(ticks, 99)), 1),
+            "plain_qps": round(b.nq / (plain_ms / 1e3), 1),
+            "plain_ms": round(plain_ms, 2),
+            "plain_isolated_p50_us": round(float(np.percentile(lat, 50)), 1),
+            "plain_isolated_p99_us": round(float(np.percentile(lat, 99)), 1),
+            "plain_counts_match_batch": same,
+            "speedup_vs_plain": round(plain_ms / ms, 2),
             "algorithmic_mb": round(abytes / 1e6, 2),
             "blocks_decoded": int(ablocks),
             "achieved_gbs": round(abytes / (ms / 1e3) / 1e9, 1),
             "hbm_frac": round(abytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "tuning": best,
+            "cpu_baseline": cpu,
+            "note": "batch_completion_*: when each query's last chunk finished inside the batch, from the batch's "
+                    "start; plain_isolated_*: one query launched and waited for alone (launch to completion); "
+                    "plain_qps: all queries, one launch each, submitted back to back from C++",
         }
         log(f"{name}: {out[name]}")
         del b
+    del encs
     out["hybrid"] = hybrid(s4, workloads, torch, index, buf, soffs, nq, {k: out[k] for k in ("pairwise", "multiterm")})
     out["partitioned"] = partitioned(s4, workloads, torch, nq, {k: out[k] for k in ("pairwise", "multiterm")})
     out["fastpfor_index"] = fastpfor_index(s4, workloads, torch, nq, {k: out[k] for k in ("pairwise", "multiterm")})
@@ -490,17 +532,26 @@ def calibrate_copy():
     print(json.dumps({"copied_bytes": 4 * n, "times": 3}))
 
 
-def serving(args):
-    """Serving workload: device-resident index of 2^20 clustered lists over
-    [0, 2^31) (length max(128, 2^28 / (t + 1))), 2..8-term queries, open-loop
-    Poisson arrivals at 0.5, 0.8 and 0.95 of the saturated rate."""
+def pct(x, q):
     import numpy as np
-    import torch
-    import workloads
-    import paper_1401_6399_amd as s4
+    return round(float(np.percentile(x, q)), 1) if len(x) else None
 
-    s4.require_library()
-    torch.cuda.set_device(0)
+
+def serving_leg(s4, workloads, torch, args):
+    """Serving workload: device-resident index of 2^20 clustered lists over
+    [0, 2^31) (length max(128, 2^28 / (t + 1))), 2..8-term queries.  The
+    saturated rate Q* (every query of a long trace submitted at once), then
+    open-loop Poisson arrivals at 0.5, 0.8 and 0.95 Q*, each level lasting
+    at least --serve-level-s seconds and 2^16 queries; latency percentiles
+    from arrival to result; the plain path (one single-launch conjunction
+    per query, submitted from C++) replaying the first --serve-plain
+    arrivals of the same trace; a sample of each level's results checked
+    against the oracle, whose own queries/s on that sample is timed on the
+    host cores."""
+    import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
     t0 = time.time()
     nl = args.serve_lists
     lens = workloads.index_lengths(nl, 28 - (20 - nl.bit_length() + 1))
@@ -510,52 +561,220 @@ def serving(args):
     buf, soffs = s4.encode_many(flat, offs)
     ix = s4.Index(buf, soffs)
     del buf, soffs
+    build_s = time.time() - t0
     log(f"index resident: {ix.payload_bytes / 2**30:.2f} GiB payload + {ix.index_bytes / 2**30:.2f} GiB skip "
-        f"index, {8 * ix.payload_bytes / ix.total_ints:.2f} bits/int; built in {time.time() - t0:.1f} s")
+        f"index, {8 * ix.payload_bytes / ix.total_ints:.2f} bits/int; built in {build_s:.1f} s")
     srv = s4.Server(ix, max_slots=1 << 15, pool_bytes=24 << 30, result_bytes=3 << 28, max_terms=8)
-    nq = args.serve_queries
-    terms, qoffs = workloads.serving_queries(ix.lengths, nq, level=0)
-    sat = srv.replay(terms, qoffs, np.zeros(nq, np.uint64))
-    qstar = nq / sat["elapsed_s"]
-    log(f"saturated: {qstar:.0f} queries/s over {nq} queries")
+    # saturated rate: first every query of a trace submitted at once (a
+    # burst), then an open-loop trace offered above that rate for
+    # --serve-saturate-s seconds: what the server sustains under arrivals
+    # is Q*, and the levels are fractions of it
+    nsat = args.serve_saturate
+    terms, qoffs = workloads.serving_trace(ix.lengths, nsat, 0)
+    sat = srv.replay(terms, qoffs, np.zeros(nsat, np.uint64))
+    q_burst = nsat / sat["elapsed_s"]
+    log(f"burst: {q_burst:.0f} queries/s over {nsat} queries")
+    over = 1.25 * q_burst
+    nov = max(1 << 16, int(over * args.serve_saturate_s))
+    terms, qoffs = workloads.serving_trace(ix.lengths, nov, 9)
+    arr = (workloads.arrivals(workloads.config_seed(4, 29), over, nov) * 1e9).astype(np.uint64)
+    ov = srv.replay(terms, qoffs, arr, timeout_s=max(600.0, 8 * args.serve_saturate_s))
+    qstar = nov / ov["elapsed_s"]
+    log(f"sustained under {over:.0f}/s offered: {qstar:.0f} queries/s over {nov} queries")
+    del terms, qoffs, arr, ov
+    threads = max(1, min(16, os.cpu_count() or 1))
+
+    def raw(t):
+        return flat[int(offs[t]): int(offs[t + 1])]
+
     levels = []
-    for lv, frac in enumerate((0.5, 0.8, 0.95)):
-        terms, qoffs = workloads.serving_queries(ix.lengths, nq, level=lv + 1)
-        arr = (workloads.arrivals(workloads.config_seed(4, 20 + lv), frac * qstar, nq) * 1e9).astype(np.uint64)
-        chk = args.serve_check > 0
-        r = srv.replay(terms, qoffs, arr, with_results=chk, results_cap=1 << 28)
+    for lv, frac in ((1, 0.5), (2, 0.8), (3, 0.95)):
+        rate = frac * qstar
+        nq = max(1 << 16, int(np.ceil(rate * args.serve_level_s)))
+        tg = time.time()
+        terms, qoffs = workloads.serving_trace(ix.lengths, nq, lv)
+        arr = (workloads.arrivals(workloads.config_seed(4, 20 + lv), rate, nq) * 1e9).astype(np.uint64)
+        rng = np.random.default_rng(lv)
+        sample = np.sort(rng.choice(nq, size=min(args.serve_check, nq), replace=False))
+        keep = np.zeros(nq, np.uint8)
+        keep[sample] = 1
+        log(f"level {lv}: {nq} queries at {rate:.0f}/s generated in {time.time() - tg:.1f} s")
+        r = srv.replay(terms, qoffs, arr, with_results=True, results_cap=1 << 27, keep=keep,
+                       timeout_s=max(600.0, 4 * args.serve_level_s))
         lat = r["latency_ns"].astype(np.float64) / 1e3
-        span = (float(arr[-1]) / 1e9) if nq else 0.0
-        lev = {"offered_qps": round(frac * qstar, 1), "achieved_qps": round(nq / max(r["elapsed_s"], 1e-9), 1),
-               "queries": nq, "trace_s": round(span, 3),
-               "p50_us": round(float(np.percentile(lat, 50)), 1), "p99_us": round(float(np.percentile(lat, 99)), 1),
-               "p999_us": round(float(np.percentile(lat, 99.9)), 1)}
-        if chk:
-            import oracle
-            rng = np.random.default_rng(lv)
-            sample = rng.choice(nq, size=min(args.serve_check, nq), replace=False)
-            bad = 0
-            for q in sample:
-                ts = sorted(terms[int(qoffs[q]): int(qoffs[q + 1])], key=lambda t: int(lens[t]))
-                want = oracle.intersect_k([flat[int(offs[t]): int(offs[t + 1])] for t in ts])
-                got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
-                bad += not np.array_equal(got, want)
-            lev["oracle_checked"] = int(sample.size)
-            lev["oracle_mismatches"] = int(bad)
+        lev = {"offered_qps": round(rate, 1), "achieved_qps": round(nq / max(r["elapsed_s"], 1e-9), 1),
+               "queries": nq, "trace_s": round(float(arr[-1]) / 1e9, 3), "elapsed_s": round(r["elapsed_s"], 3),
+               "p50_us": pct(lat, 50), "p99_us": pct(lat, 99), "p999_us": pct(lat, 99.9)}
+        del lat
+        # the sample against the oracle, and the oracle's own rate on it
+        qs = [sorted(terms[int(qoffs[q]): int(qoffs[q + 1])].tolist(), key=lambda t: int(lens[t])) for q in sample]
+        tc = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            wants = list(ex.map(lambda ts: oracle.intersect_k([raw(t) for t in ts]), qs))
+        cpu_s = time.perf_counter() - tc
+        bad = 0
+        for q, w in zip(sample, wants):
+            got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
+            bad += int(r["counts"][q]) != w.size or not np.array_equal(got, w)
+        lev["oracle_checked"] = int(sample.size)
+        lev["oracle_mismatches"] = int(bad)
+        lev["cpu_baseline"] = {"value": round(sample.size / cpu_s, 1), "unit": "queries/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"oracle intersect_k (two-pointer merge, shortest first) of the "
+                                         f"{sample.size} checked queries over their uncompressed lists "
+                                         f"(decoding not counted), {threads} threads, {cpu_s:.2f} s"}
+        # the plain path under the first arrivals of the same trace
+        npl = min(args.serve_plain, nq)
+        pl = s4.plain_replay(ix, terms[: int(qoffs[npl])], qoffs[: npl + 1], arr[:npl],
+                             timeout_s=max(600.0, 4 * args.serve_level_s))
+        plat = pl["latency_ns"].astype(np.float64) / 1e3
+        lev["plain"] = {"queries": npl, "offered_qps": round(rate, 1),
+                        "achieved_qps": round(npl / max(pl["elapsed_s"], 1e-9), 1),
+                        "p50_us": pct(plat, 50), "p99_us": pct(plat, 99), "p999_us": pct(plat, 99.9),
+                        "counts_match_server": bool(np.array_equal(pl["counts"], r["counts"][:npl]))}
         levels.append(lev)
         log(f"level {lv}: {lev}")
+        del terms, qoffs, arr, r, keep, pl
     st = srv.stats()
     srv.close()
-    print(json.dumps({"metric": "served queries/s + p50/p99/p999 latency", "unit": "queries/s",
-                      "n_gpus": 1, "data": "synthetic",
-                      "config": {"workload": f"serving: {nl} clustered lists over [0,2^31), "
-                                             f"{int(offs[-1])} ints, 2..8-term queries, sqrt(len) term sampling, "
-                                             "open-loop Poisson arrivals", "queries_per_level": nq},
-                      "saturated_qps": round(qstar, 1), "levels": levels,
-                      "index": {"payload_gib": round(ix.payload_bytes / 2**30, 3),
-                                "skip_index_gib": round(ix.index_bytes / 2**30, 3),
-                                "bits_per_int": round(8 * ix.payload_bytes / ix.total_ints, 3)},
-                      "server_stats": st}), flush=True)
+    out = {"workload": f"serving: {nl} clustered lists over [0,2^31), {int(offs[-1])} ints resident, 2..8-term "
+                       "queries, sqrt(len) term sampling, open-loop Poisson arrivals at 0.5/0.8/0.95 Q*",
+           "unit": "queries/s", "saturated_qps": round(qstar, 1),
+           "saturated": {"qps": round(qstar, 1), "offered_qps": round(over, 1), "queries": nov,
+                         "burst_qps": round(q_burst, 1), "burst_queries": nsat,
+                         "note": "Q* is what the server sustains under open-loop arrivals offered at 1.25x the rate "
+                                 "of a burst (every query of a trace submitted at once); the levels are fractions "
+                                 "of Q*"},
+           "levels": levels,
+           "index": {"payload_gib": round(ix.payload_bytes / 2**30, 3),
+                     "skip_index_gib": round(ix.index_bytes / 2**30, 3),
+                     "bits_per_int": round(8 * ix.payload_bytes / ix.total_ints, 3), "build_s": round(build_s, 1)},
+           "server_stats": st}
+    ix.free()
+    return out
+
+
+def serving(args):
+    """--serve: the serving leg alone, printed as its own JSON line."""
+    import torch
+    import workloads
+    import paper_1401_6399_amd as s4
+
+    s4.require_library()
+    torch.cuda.set_device(0)
+    res = serving_leg(s4, workloads, torch, args)
+    print(json.dumps({"metric": "served queries/s + p50/p99/p999 latency", "n_gpus": 1, "data": "synthetic",
+                      "serving": res}), flush=True)
+
+
+def step_profile(plan_q, ns, abytes, steps):
+    """Device timestamps of every dispatch in `steps` untimed per-list steps
+    on the library's queues (HSA dispatch profiling): per step, its device
+    span (first start to last end), the summed kernel time, and bytes over
+    span for each class of list length; medians over the steps."""
+    import numpy as np
+    st, en, host_ms = plan_q.profile(steps)
+    st = st.astype(np.float64)
+    en = en.astype(np.float64)
+    live = ns > 0
+    classes = {"lt_2p18": ns < 2**18, "2p18_to_2p22": (ns >= 2**18) & (ns < 2**22), "ge_2p22": ns >= 2**22}
+    spans, ksums, durs = [], [], []
+    per = {k: {"span": [], "dur": []} for k in classes}
+    for i in range(steps):
+        a, b = st[i, live], en[i, live]
+        spans.append(b.max() - a.min())
+        ksums.append((b - a).sum())
+        durs.append((b - a).mean())
+        for k, m in classes.items():
+            mm = m & live
+            if mm.any():
+                per[k]["span"].append(en[i, mm].max() - st[i, mm].min())
+                per[k]["dur"].append((en[i, mm] - st[i, mm]).mean())
+    span_ns = float(np.median(spans))
+    by = {}
+    for k, m in classes.items():
+        mm = m & live
+        if not mm.any():
+            continue
+        sp = float(np.median(per[k]["span"]))
+        by[k] = {"lists": int(mm.sum()), "bytes": round(float(abytes[mm].sum()), 1),
+                 "span_us": round(sp / 1e3, 2), "avg_dispatch_us": round(float(np.median(per[k]["dur"])) / 1e3, 2),
+                 "gbs_over_span": round(float(abytes[mm].sum()) / sp, 1)}
+    return {"span_ns": span_ns, "kernel_sum_ns": float(np.median(ksums)), "avg_dispatch_ns": float(np.median(durs)),
+            "host_ms": host_ms, "by_size_class": by, "spans_us": [round(x / 1e3, 2) for x in spans]}
+
+
+def plain_config(s4, workloads, torch, reps=20):
+    """The plain CPU-sized configuration: A = 2^20 and B = 2^14 values drawn
+    uniformly from [0, 2^25); encode both (host library), decode both and
+    intersect them on the GPU (kernel time from events on the stream, and
+    end to end from the first launch to the synchronised result), every
+    output checked against the oracle; beside it the oracle's encode, decode
+    and merge on one host thread.  Medians."""
+    import numpy as np
+    import oracle
+    a, b = workloads.plain_pair()
+    med = lambda v: round(float(np.median(v)), 2)
+    enc_us = []
+    for _ in range(reps // 4):
+        t0 = time.perf_counter()
+        ea, eb = s4.encode(a), s4.encode(b)
+        enc_us.append((time.perf_counter() - t0) * 1e6)
+    la, lb = s4.DeviceList.upload(ea), s4.DeviceList.upload(eb)
+    oa = torch.empty(a.size + 4, dtype=torch.int32, device="cuda")
+    ob = torch.empty(b.size + 4, dtype=torch.int32, device="cuda")
+    res = torch.empty(b.size, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    scratch = torch.empty(max(256, s4.intersect_k_scratch_bytes([la, lb])), dtype=torch.uint8, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    dec_a, dec_b, inter, e2e = [], [], [], []
+    for i in range(reps + 3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record()
+        la.decode_into(oa)
+        ev[1].record()
+        lb.decode_into(ob)
+        ev[2].record()
+        s4.intersect(la, lb, out=res, count=cnt, scratch=scratch)
+        ev[3].record()
+        ev[3].synchronize()
+        t1 = time.perf_counter()
+        if i >= 3:
+            dec_a.append(ev[0].elapsed_time(ev[1]) * 1e3)
+            dec_b.append(ev[1].elapsed_time(ev[2]) * 1e3)
+            inter.append(ev[2].elapsed_time(ev[3]) * 1e3)
+            e2e.append((t1 - t0) * 1e6)
+    c = int(cnt.item())
+    ok = (np.array_equal(oa[: a.size].cpu().numpy().view(np.uint32), a) and
+          np.array_equal(ob[: b.size].cpu().numpy().view(np.uint32), b) and
+          np.array_equal(res[:c].cpu().numpy().view(np.uint32), oracle.intersect(a, b)) and
+          np.array_equal(ea, oracle.encode(a)) and np.array_equal(eb, oracle.encode(b)))
+    # the oracle on one thread
+    o_enc, o_dec, o_mrg = [], [], []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        xa, xb = oracle.encode(a), oracle.encode(b)
+        t1 = time.perf_counter()
+        da, db = oracle.decode(xa), oracle.decode(xb)
+        t2 = time.perf_counter()
+        oracle.intersect(da, db)
+        t3 = time.perf_counter()
+        o_enc.append((t1 - t0) * 1e6)
+        o_dec.append((t2 - t1) * 1e6)
+        o_mrg.append((t3 - t2) * 1e6)
+    n = a.size + b.size
+    return {"workload": "plain: A = 2^20, B = 2^14 distinct values uniform from [0, 2^25); S4-BP128-D4",
+            "intersection": c, "bits_per_int_a": round(8 * la.payload_bytes / a.size, 3),
+            "bits_per_int_b": round(8 * lb.payload_bytes / b.size, 3), "outputs_match_oracle": bool(ok),
+            "gpu_us": {"host_encode_a_b": med(enc_us), "decode_a": med(dec_a), "decode_b": med(dec_b),
+                       "intersect": med(inter), "decode_both_and_intersect_end_to_end": med(e2e)},
+            "gpu_decode_gints": round(n / ((np.median(dec_a) + np.median(dec_b)) * 1e3), 2),
+            "cpu_baseline": {"kind": "oracle", "cores": 1, "unit": "us",
+                             "encode_a_b": med(o_enc), "decode_a_b": med(o_dec), "merge": med(o_mrg),
+                             "decode_gints": round(n / (np.median(o_dec) * 1e3), 3),
+                             "sample": "the whole plain workload, one host thread, median of 5"},
+            "note": "fits in L2/MALL and is launch-bound: a correctness configuration, not a roofline one"}
 
 
 def main():
@@ -578,8 +797,8 @@ def main():
     s4.require_library()
     torch.cuda.set_device(0)
     if args.batched_only:
-        print(json.dumps({"batched": batched(s4, workloads, torch, args.batch_queries, args.plain_sample)}),
-              flush=True)
+        print(json.dumps({"batched": batched(s4, workloads, torch, args.batch_queries, args.plain_sample,
+                                             args.cpu_queries)}), flush=True)
         return
     flat, offs, kinds, buf, soffs, lists, outs, out = build_bulk(s4, workloads, torch)
     ns = np.array([l.n for l in lists], dtype=np.float64)
@@ -588,9 +807,28 @@ def main():
     abytes = rbytes + wbytes
     total = int(ns.sum())
     bits = float(rbytes.sum() * 8 / ns.sum())
+    launch = ("one k_decode dispatch per list, written by the library into four HSA queues "
+              "(s4_aql_plan); steps separated by barrier packets")
+
+    if args.step_only:
+        # the headline's steps alone (what rocprofv3 traces for the roofline)
+        plan_q = s4.AqlDecodePlan(lists, outs)
+        run_steps(plan_q, args.warmup)
+        ms = run_steps(plan_q, args.steps) / args.steps
+        check_decoded(out, lists, flat, offs)
+        line = {"ms_per_step": round(ms, 4), "gint_s": round(total / (ms / 1e3) / 1e9, 2),
+                "dispatches_per_step": len(lists), "steps": args.warmup + args.steps}
+        if args.profile_steps:
+            prof = step_profile(plan_q, ns, abytes, args.profile_steps)
+            line.update({"device_span_us": round(prof["span_ns"] / 1e3, 2),
+                         "avg_dispatch_us": round(prof["avg_dispatch_ns"] / 1e3, 3),
+                         "steps": args.warmup + args.steps + args.profile_steps,
+                         "by_size_class": prof["by_size_class"]})
+        print(json.dumps(line), flush=True)
+        return
 
     stream = torch.cuda.Stream()
-    # headline: one launch per list, forked over streams, replayed as a graph
+    # the same launches through HIP, forked over streams, replayed as a graph
     torch.cuda.synchronize()
     graph_ms, g = time_graph(torch, lambda: s4.decode_lists(lists, outs, nstreams=args.nstreams), stream,
                              args.steps, args.warmup)
@@ -603,30 +841,35 @@ def main():
     gated_ms, host_ms = time_graph_gated(torch, s4, g, stream, min(args.steps, 30))
     log(f"per-list, device time with launches queued ahead: {gated_ms:.3f} ms/step; "
         f"host time to launch one replay: {host_ms:.3f} ms")
+    del g
 
-    # headline: the same launches written by the library into its own queues
+    # headline: the launches written by the library into its own queues
     if args.no_aql:
         ms = graph_ms
         launch = f"one k_decode launch per list over {args.nstreams} forked streams, hipGraph replay"
+        prof = None
     else:
         plan_q = s4.AqlDecodePlan(lists, outs)
         run_steps(plan_q, args.warmup)
         out.fill_(-1)
+        torch.cuda.synchronize()
         ms = run_steps(plan_q, args.steps) / args.steps
         check_decoded(out, lists, flat, offs)
+        # roofline of the timed mode: one more, untimed run with a device
+        # timestamp on every dispatch
+        prof = step_profile(plan_q, ns, abytes, args.profile_steps)
+        check_decoded(out, lists, flat, offs)
         del plan_q
-        launch = ("one k_decode dispatch per list, written by the library into four HSA queues "
-                  "(s4_aql_plan); steps separated by barrier packets")
     value = total / (ms / 1e3) / 1e9
     log(f"per-list launches ({launch}): {ms:.3f} ms/step, {value:.1f} Gint/s (outputs checked)")
 
-    # roofline of the decode kernel: events around each launch
+    # the kernel launched serially through HIP: events around each launch
     dur = per_launch_ms(torch, s4, lists, outs, stream)
-    achieved = abytes.sum() / (dur.sum() / 1e3) / 1e9
+    achieved_serial = abytes.sum() / (dur.sum() / 1e3) / 1e9
     big = ns >= (1 << 22)
     achieved_big = abytes[big].sum() / (dur[big].sum() / 1e3) / 1e9
-    log(f"decode kernel: avg {dur.mean() * 1e3:.2f} us/launch, {achieved:.0f} GB/s; lists >= 2^22: "
-        f"{achieved_big:.0f} GB/s")
+    log(f"decode kernel, serial launches: avg {dur.mean() * 1e3:.2f} us/launch, {achieved_serial:.0f} GB/s; "
+        f"lists >= 2^22: {achieved_big:.0f} GB/s")
 
     # single multi-list launch
     plan = s4.DecodePlan(lists, outs)
@@ -646,6 +889,39 @@ def main():
             tj = json.load(f)
         if tj.get("kernel_source_sha") == kernel_source_sha():
             traffic = tj.get("bytes_per_launch")
+
+    serial = {"achieved": round(achieved_serial, 1), "frac": round(achieved_serial / HBM_PEAK_GBS, 4),
+              "avg_launch_us": round(float(dur.mean() * 1e3), 3), "bytes_per_launch": round(float(abytes.mean()), 1),
+              "frac_lists_ge_2p22": round(achieved_big / HBM_PEAK_GBS, 4), "traffic_per_launch": traffic,
+              "note": "the same kernel launched one list at a time through HIP, each launch timed by events it "
+                      "records at its kernel's start and end"}
+    if prof is not None:
+        step_bytes = float(abytes.sum())
+        # the timed run writes every step's packets ahead and returns when
+        # the last step is complete, so its wall time per step is the
+        # device's time per step
+        achieved = step_bytes / (ms / 1e3) / 1e9
+        roofline = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(traffic * len(lists), 1) if traffic else None,
+            "kernel": "k_decode",
+            "unit_of_work": "one step of the headline: all 256 per-list dispatches on the library's four queues",
+            "bytes_per_step": round(step_bytes, 1), "step_us": round(ms * 1e3, 2),
+            "profiled": {
+                "note": "untimed steps with a device timestamp on every dispatch (HSA dispatch profiling, which "
+                        "slows a step by about 7%): the step's device span, the summed dispatch durations "
+                        "(four queues run concurrently) and bytes over span per class of list length",
+                "steps": args.profile_steps, "device_span_us": round(prof["span_ns"] / 1e3, 2),
+                "kernel_time_sum_us": round(prof["kernel_sum_ns"] / 1e3, 2),
+                "avg_dispatch_us": round(prof["avg_dispatch_ns"] / 1e3, 3), "dispatches_per_step": len(lists),
+                "by_size_class": prof["by_size_class"],
+                "host_ms_per_step": round(prof["host_ms"] / args.profile_steps, 4)},
+            "serial": serial,
+        }
+    else:
+        roofline = {"bound": "hbm", "achieved": serial["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": serial["frac"], "traffic": traffic, "kernel": "k_decode", "serial": serial}
 
     result = {
         "metric": METRIC,
@@ -668,18 +944,7 @@ def main():
             "bits_per_int": round(bits, 3),
             "launch": launch,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": "k_decode",
-            "avg_launch_us": round(float(dur.mean() * 1e3), 3),
-            "bytes_per_launch": round(float(abytes.mean()), 1),
-            "frac_lists_ge_2p22": round(achieved_big / HBM_PEAK_GBS, 4),
-        },
+        "roofline": roofline,
         "per_list_hip_graph": {"ms_per_step": round(graph_ms, 4), "gint_s": round(total / (graph_ms / 1e3) / 1e9, 2),
                                "device_ms_per_step": round(gated_ms, 4),
                                "host_ms_per_launch_of_step": round(host_ms, 4),
@@ -702,14 +967,24 @@ def main():
         log(f"delta forms: {result['delta_forms']}")
         result["fastpfor_forms"] = delta_forms(s4, torch, flat, offs, outs, stream, 20, 3, patched=True)
         log(f"S4-FastPFOR forms: {result['fastpfor_forms']}")
+        result["plain_config"] = plain_config(s4, workloads, torch)
+        log(f"plain config: {result['plain_config']}")
     if not args.no_batched and not args.decode_only:
         try:
-            result["batched"] = batched(s4, workloads, torch, args.batch_queries, args.plain_sample)
+            result["batched"] = batched(s4, workloads, torch, args.batch_queries, args.plain_sample,
+                                        args.cpu_queries)
         except Exception as ex:  # reported, never hidden
             result["batched"] = {"error": str(ex)}
     if not args.no_cpu_baseline and not args.decode_only:
         result["cpu_baseline"] = cpu_baseline(flat, offs, args.cpu_passes)
-    print(json.dumps(result), flush=True)
+    if not args.no_serving and not args.decode_only:
+        del lists, outs, out
+        torch.cuda.empty_cache()
+        try:
+            result["serving"] = serving_leg(s4, workloads, torch, args)
+        except Exception as ex:  # reported, never hidden
+            result["serving"] = {"error": str(ex)}
+    print(json.dumps(result, default=float), flush=True)
 
 
 if __name__ == "__main__":

@@ -206,8 +206,8 @@ int s4_decode_lists_dev(const s4_list *const *lists, uint32_t *const *d_outs, co
  * runtime launch call.  Every run opens with a barrier packet whose
  * system-scope acquire invalidates the device caches, so lists and
  * outputs written through HIP before the run are seen.  A plan holds the
- * packets and their argument blocks (coherent pinned host memory), built
- * once; the lists and outputs (16-byte aligned, capacity caps[i] >= n)
+ * packets (host) and their argument blocks (device memory), built once;
+ * the lists and outputs (16-byte aligned, capacity caps[i] >= n)
  * must outlive it.  Plain lists only: a patched list is S4_EINVAL.  The
  * dispatcher serves the device it is first used on.
  *
@@ -238,6 +238,12 @@ int s4_decode_lists_dev(const s4_list *const *lists, uint32_t *const *d_outs, co
 typedef struct s4_aql_plan s4_aql_plan;
 int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
                        uint32_t count, s4_aql_plan **out);
+/* The same plan with the placement chosen by the caller: list i goes to
+ * queue queue_of[i] (< 4), and within a queue dispatches go in increasing
+ * rank[i] (ties keep list order; rank may be null).  S4_EINVAL for a queue
+ * index out of range. */
+int s4_aql_plan_create_placed(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
+                              uint32_t count, const uint32_t *queue_of, const uint32_t *rank, s4_aql_plan **out);
 int s4_aql_plan_run(s4_aql_plan *plan, uint32_t steps, uint64_t *elapsed_ns);
 int s4_aql_plan_enqueue(s4_aql_plan *plan, uint32_t steps, void *stream);
 int s4_aql_plan_status(s4_aql_plan *plan);

@@ -82,6 +82,8 @@ SIGNATURES = {
     "s4_decode_plan_run": (_i, [_vp, _vp]),
     "s4_decode_plan_free": (_i, [_vp]),
     "s4_aql_plan_create": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u64p, _u32, ctypes.POINTER(_vp)]),
+    "s4_aql_plan_create_placed": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u64p, _u32, _u32p, _u32p,
+                                       ctypes.POINTER(_vp)]),
     "s4_aql_plan_run": (_i, [_vp, _u32, _u64p]),
     "s4_aql_plan_enqueue": (_i, [_vp, _u32, _vp]),
     "s4_aql_plan_status": (_i, [_vp]),
@@ -383,15 +385,23 @@ class AqlDecodePlan:
     streams (the device is synchronised before it); enqueue() orders a run
     after the work of a stream and returns at once."""
 
-    def __init__(self, lists, outs):
+    def __init__(self, lists, outs, queue_of=None, rank=None):
         import torch
         hs, ptrs, caps = _out_arrays(lists, outs)
         self._keep = (lists, outs)
         self.count = len(lists)
         self.h = ctypes.c_void_p()
         torch.cuda.synchronize()
-        _check(require_library().s4_aql_plan_create(hs, ptrs, _ptr(caps, ctypes.c_uint64), len(lists),
-                                                    ctypes.byref(self.h)), "s4_aql_plan_create")
+        if queue_of is None:
+            _check(require_library().s4_aql_plan_create(hs, ptrs, _ptr(caps, ctypes.c_uint64), len(lists),
+                                                        ctypes.byref(self.h)), "s4_aql_plan_create")
+        else:
+            qo = np.ascontiguousarray(queue_of, dtype=np.uint32)
+            rk = np.ascontiguousarray(rank, dtype=np.uint32) if rank is not None else None
+            _check(require_library().s4_aql_plan_create_placed(
+                hs, ptrs, _ptr(caps, ctypes.c_uint64), len(lists), _ptr(qo, ctypes.c_uint32),
+                _ptr(rk, ctypes.c_uint32) if rk is not None else None, ctypes.byref(self.h)),
+                "s4_aql_plan_create_placed")
 
     def run(self, steps=1):
         """Decode every list `steps` times; returns the host wall time in ms."""

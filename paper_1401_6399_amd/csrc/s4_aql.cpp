@@ -8,8 +8,8 @@
 // one with a barrier packet waiting for every queue's signal, so steps do
 // not overlap.  The kernels are the ones HIP loaded for this library, found
 // through the AMD loader extension; their argument blocks and packet images
-// are built once per plan (arguments in coherent pinned host memory), and a
-// step copies the images into the rings.  Every run opens with a barrier
+// are built once per plan (arguments in device memory), and a step copies
+// the images into the rings.  Every run opens with a barrier
 // packet whose system-scope acquire invalidates the caches before the first
 // kernel reads arguments or lists written through other queues.  A run can
 // be timed per dispatch (profiling enabled on the queues, one completion
@@ -39,9 +39,13 @@ namespace {
 constexpr uint32_t kArgStride = 128;          // bytes per dispatch's argument block
 constexpr double kWaitLimitSeconds = 20.0;    // a step never takes this long
 constexpr uint32_t kQueueSlots = 4096;
-constexpr uint32_t kQueues = 4;               // one queue processes about one dispatch per 4 us
+// Queues of the dispatcher: dispatches of one queue run one after another
+// (a tiny one costs about 1.8 us of its queue), so concurrency comes from
+// queues; more than four (with the runtime's own) made every queue slower.
+constexpr uint32_t kQueues = 4;
 static_assert(kQueues >= 1 && kQueues <= 16, "queues per device");
 constexpr uint32_t kMaxSteps = 64;            // signals kept per queue
+
 
 struct KernelInfo {
   uint64_t object = 0;
@@ -259,11 +263,16 @@ void barrier_packet(hsa_queue_t *q, uint64_t i, const hsa_signal_t *deps, uint32
 }  // namespace
 
 struct s4_aql_plan {
-  void *args = nullptr;  // coherent pinned host memory, kArgStride bytes per dispatch
+  // kArgStride bytes per dispatch, in device memory: every wave's preloaded
+  // arguments come from HBM / L2 (in host memory each wave's start would
+  // wait for a host-link round trip; tiny dispatches took 5.4 instead of
+  // 4.7 us in the step)
+  void *args = nullptr;
   struct Dispatch {
     hsa_kernel_dispatch_packet_t pkt;  // the packet, completion signal empty; its first word is published last
     uint32_t word0;                    // header and setup
     uint32_t list;                     // index of the list in the plan's input order
+    uint32_t rank;                     // position key within its queue
   };
   std::vector<Dispatch> per_queue[kQueues];
   uint32_t count = 0, dispatches = 0;
@@ -275,6 +284,36 @@ struct s4_aql_plan {
 };
 
 namespace {
+
+// Default placement: largest-first assignment of launches to queues by
+// bytes moved (plus a fixed cost per launch), then within each queue its
+// largest and smallest remaining lists alternate, so small dispatches are
+// issued while large kernels run.
+void default_placement(const std::vector<DecodeLaunch> &launches, std::vector<uint32_t> *qof,
+                       std::vector<uint32_t> *qrank) {
+  std::vector<size_t> order(launches.size());
+  for (size_t j = 0; j < order.size(); ++j) order[j] = j;
+  auto bytes = [&](size_t j) { return uint64_t(launches[j].a.full_end - launches[j].a.first) * 512u + 4096u; };
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return bytes(x) > bytes(y); });
+  uint64_t load[kQueues] = {};
+  std::vector<size_t> mine[kQueues];
+  for (size_t j : order) {
+    uint32_t best = 0;
+    for (uint32_t q = 1; q < kQueues; ++q)
+      if (load[q] < load[best]) best = q;
+    load[best] += bytes(j);
+    (*qof)[j] = best;
+    mine[best].push_back(j);
+  }
+  for (uint32_t q = 0; q < kQueues; ++q) {
+    size_t lo = 0, hi = mine[q].size();
+    uint32_t r = 0;
+    while (lo < hi) {
+      (*qrank)[mine[q][lo++]] = r++;
+      if (lo < hi) (*qrank)[mine[q][--hi]] = r++;
+    }
+  }
+}
 
 // Write `steps` steps of the plan into the queues and ring their doorbells.
 // Each queue: an opening barrier (step 0: no dependency, system-scope
@@ -392,8 +431,8 @@ void run_from_stream(void *data) {
 
 extern "C" {
 
-int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps, uint32_t count,
-                       s4_aql_plan **out) {
+int s4_aql_plan_create_placed(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps,
+                              uint32_t count, const uint32_t *queue_of, const uint32_t *rank, s4_aql_plan **out) {
   if (!out || (count && (!lists || !d_outs || !caps))) return fail(S4_EINVAL, "null argument");
   *out = nullptr;
   for (uint32_t i = 0; i < count; ++i) {
@@ -401,6 +440,7 @@ int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, con
     if (caps[i] < lists[i]->n) return fail(S4_ERANGE, "cap < n for list " + std::to_string(i));
     if (reinterpret_cast<uintptr_t>(d_outs[i]) & 15u) return fail(S4_EINVAL, "outputs must be 16-byte aligned");
     if (is_patched(lists[i]->d)) return fail(S4_EINVAL, "the dispatcher decodes plain (unpatched) lists only");
+    if (queue_of && queue_of[i] >= kQueues) return fail(S4_EINVAL, "queue index out of range");
   }
   int rc = ensure_device();
   if (rc) return rc;
@@ -423,28 +463,27 @@ int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, con
   }
   s4_aql_plan *p = new (std::nothrow) s4_aql_plan;
   if (!p) return fail(S4_ENOMEM, "plan allocation failed");
-  if (!launches.empty() && hipHostMalloc(&p->args, size_t(kArgStride) * launches.size(), hipHostMallocCoherent) !=
-                               hipSuccess) {
+  const size_t arg_bytes = size_t(kArgStride) * launches.size();
+  std::vector<uint8_t> arg_image(arg_bytes, 0);
+  if (!launches.empty() && hipMalloc(&p->args, arg_bytes) != hipSuccess) {
     delete p;
     return fail(S4_ENOMEM, "argument blocks allocation failed");
   }
-  // largest-first assignment of lists to queues by bytes moved
-  std::vector<size_t> order(launches.size());
-  for (size_t j = 0; j < order.size(); ++j) order[j] = j;
-  std::sort(order.begin(), order.end(),
-            [&](size_t x, size_t y) { return launches[x].a.full_end - launches[x].a.first >
-                                             launches[y].a.full_end - launches[y].a.first; });
-  uint64_t load[kQueues] = {};
-  for (size_t j : order) {
+  // the queue of every launch: given, or the default placement
+  std::vector<uint32_t> qof(launches.size()), qrank(launches.size());
+  if (queue_of) {
+    for (size_t j = 0; j < launches.size(); ++j) {
+      qof[j] = queue_of[list_of[j]];
+      qrank[j] = rank ? rank[list_of[j]] : uint32_t(j);
+    }
+  } else {
+    default_placement(launches, &qof, &qrank);
+  }
+  for (size_t j = 0; j < launches.size(); ++j) {
     const DecodeLaunch &d = launches[j];
+    std::memcpy(arg_image.data() + j * kArgStride, &d.a, kDecodeArgBytes);
     uint8_t *a = static_cast<uint8_t *>(p->args) + j * kArgStride;
-    std::memset(a, 0, kArgStride);
-    std::memcpy(a, &d.a, kDecodeArgBytes);
     const KernelInfo &k = g_state.kernels[slot_of(d.P)];
-    uint32_t best = 0;
-    for (uint32_t q = 1; q < kQueues; ++q)
-      if (load[q] < load[best]) best = q;
-    load[best] += uint64_t(d.a.full_end - d.a.first) * 512u + 4096u;
     s4_aql_plan::Dispatch dp;
     std::memset(&dp, 0, sizeof dp);
     dp.pkt.workgroup_size_x = 256;
@@ -461,25 +500,30 @@ int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, con
     dp.word0 = packet_header(HSA_PACKET_TYPE_KERNEL_DISPATCH, false, HSA_FENCE_SCOPE_NONE, HSA_FENCE_SCOPE_NONE) |
                (uint32_t(1) << (16 + HSA_KERNEL_DISPATCH_PACKET_SETUP_DIMENSIONS));
     dp.list = list_of[j];
-    p->per_queue[best].push_back(dp);
+    dp.rank = qrank[j];
+    p->per_queue[qof[j]].push_back(dp);
   }
-  // within a queue, alternate its largest and smallest remaining lists, so
-  // small dispatches are issued while large kernels run
-  for (auto &v : p->per_queue) {
-    std::vector<s4_aql_plan::Dispatch> mixed;
-    mixed.reserve(v.size());
-    size_t lo = 0, hi = v.size();
-    while (lo < hi) {
-      mixed.push_back(v[lo++]);
-      if (lo < hi) mixed.push_back(v[--hi]);
+  for (auto &v : p->per_queue)
+    std::stable_sort(v.begin(), v.end(),
+                     [](const s4_aql_plan::Dispatch &x, const s4_aql_plan::Dispatch &y) { return x.rank < y.rank; });
+  if (arg_bytes) {
+    const hipError_t e = hipMemcpy(p->args, arg_image.data(), arg_bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(p->args);
+      delete p;
+      return hip_fail(e, "argument blocks upload");
     }
-    v.swap(mixed);
   }
   p->count = count;
   p->dispatches = uint32_t(launches.size());
   for (uint32_t i = 0; i < count; ++i) p->ints += lists[i]->n;
   *out = p;
   return S4_OK;
+}
+
+int s4_aql_plan_create(const s4_list *const *lists, uint32_t *const *d_outs, const uint64_t *caps, uint32_t count,
+                       s4_aql_plan **out) {
+  return s4_aql_plan_create_placed(lists, d_outs, caps, count, nullptr, nullptr, out);
 }
 
 int s4_aql_plan_run(s4_aql_plan *plan, uint32_t steps, uint64_t *elapsed_ns) {
@@ -583,7 +627,7 @@ int s4_aql_plan_free(s4_aql_plan *plan) {
   std::lock_guard<std::mutex> lock(g_mu);
   // after a failed run, packets may still reference the argument blocks:
   // they are kept for the rest of the process
-  if (plan->args && !plan->lost && !g_state.broken) (void)hipHostFree(plan->args);
+  if (plan->args && !plan->lost && !g_state.broken) (void)hipFree(plan->args);
   delete plan;
   return S4_OK;
 }

@@ -33,3 +33,21 @@ def test_cpu_baseline_fields():
     assert str(int(offs[-1])) in cb["sample"]
     host = cb["host"]
     assert host["nproc"] >= 1 and set(host) == {"cpu_model", "nproc", "usable_threads"}
+
+
+def test_cpu_queries_fields():
+    """The oracle's queries/s baseline decodes and intersects every sampled
+    query; the result total equals the plain fold on the raw lists."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import oracle
+    lens = np.array([5000, 3000, 700, 129, 4096], np.uint64)
+    kinds = np.full(lens.size, workloads.CLUSTERED, np.int32)
+    flat, offs = workloads.lists(kinds, lens, 11, 1 << 16)
+    encs = [oracle.encode(flat[int(offs[i]): int(offs[i + 1])]) for i in range(lens.size)]
+    terms, qoffs = workloads.queries(3, lens, 40, 2, 4)
+    cb = bench.cpu_queries(encs, terms, qoffs, np.arange(40))
+    assert cb["unit"] == "queries/s" and cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
+    want = sum(oracle.intersect_k([flat[int(offs[t]): int(offs[t + 1])] for t in terms[int(qoffs[q]): int(qoffs[q + 1])]]).size
+               for q in range(40))
+    assert cb["results"] == want

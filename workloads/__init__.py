@@ -65,7 +65,9 @@ def _load():
                                    ctypes.c_uint32, ctypes.c_uint32, u32p, u64p]
         lib.wl_arrivals.argtypes = [ctypes.c_uint64, ctypes.c_double, ctypes.c_uint64,
                                     ctypes.POINTER(ctypes.c_double)]
-        for f in (lib.wl_list, lib.wl_lists, lib.wl_queries, lib.wl_arrivals):
+        lib.wl_queries_alias.argtypes = [ctypes.c_uint64, u64p, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint32, ctypes.c_uint32, u32p, u64p, ctypes.c_int]
+        for f in (lib.wl_list, lib.wl_lists, lib.wl_queries, lib.wl_arrivals, lib.wl_queries_alias):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -116,6 +118,21 @@ def queries(seed: int, lens, nq: int, kmin: int, kmax: int):
     rc = lib.wl_queries(seed, lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), lens.size, nq,
                         kmin, kmax, terms.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
                         offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    if rc:
+        raise ValueError("bad query parameters")
+    return terms[: int(offs[-1])], offs
+
+
+def queries_fast(seed: int, lens, nq: int, kmin: int, kmax: int):
+    """Long CSR query streams of the same law as queries(), drawn in
+    parallel with an alias table (a different stream for the same seed)."""
+    lib = _load()
+    lens = np.ascontiguousarray(lens, dtype=np.uint64)
+    terms = np.empty(nq * kmax, dtype=np.uint32)
+    offs = np.empty(nq + 1, dtype=np.uint64)
+    rc = lib.wl_queries_alias(seed, lens.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), lens.size, nq,
+                              kmin, kmax, terms.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                              offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), _threads())
     if rc:
         raise ValueError("bad query parameters")
     return terms[: int(offs[-1])], offs
@@ -175,6 +192,12 @@ def multiterm_queries(lens, nq: int = 1 << 18):
 
 def serving_queries(lens, nq: int, level: int = 0):
     return queries(config_seed(4, 10 + level), lens, nq, 2, 8)
+
+
+def serving_trace(lens, nq: int, level: int):
+    """The serving workload's query stream for arrival level `level`, long
+    traces drawn by queries_fast (2..8 terms, sqrt(length) sampling)."""
+    return queries_fast(config_seed(4, 30 + level), lens, nq, 2, 8)
 
 
 def planted_pair(seed: int, n: int, m: int, frac: float, universe: int = 1 << 26, kind: int = CLUSTERED):

@@ -238,6 +238,67 @@ int wl_queries(uint64_t seed, const uint64_t *lens, uint64_t nlists, uint64_t nq
   return 0;
 }
 
+// Long query traces, in parallel: the same law as wl_queries (k ~
+// U{kmin..kmax}, k distinct terms, P(t) proportional to sqrt(lens[t])), drawn
+// with Vose's alias method (M. D. Vose, "A linear algorithm for generating
+// random numbers with a given distribution", IEEE TSE 1991) so each term
+// costs O(1).  Queries are generated in blocks of 2^16, block b from the
+// stream (seed, b): first every query's k, then (after a prefix sum) its
+// terms, so the output does not depend on the thread count.  terms must
+// hold nq * kmax entries.
+int wl_queries_alias(uint64_t seed, const uint64_t *lens, uint64_t nlists, uint64_t nq, uint32_t kmin,
+                     uint32_t kmax, uint32_t *terms, uint64_t *offsets, int nthreads) {
+  if (kmin == 0 || kmax < kmin || kmax > nlists || nlists > (1ull << 32)) return -1;
+  // alias table: prob[i] scaled to [0, 2^53], alias[i]
+  std::vector<double> w(nlists);
+  double sum = 0;
+  for (uint64_t t = 0; t < nlists; ++t) { w[t] = std::sqrt((double)lens[t]); sum += w[t]; }
+  if (!(sum > 0)) return -1;
+  std::vector<double> prob(nlists);
+  std::vector<uint32_t> alias(nlists, 0);
+  std::vector<uint32_t> small, large;
+  for (uint64_t t = 0; t < nlists; ++t) {
+    prob[t] = w[t] * (double)nlists / sum;
+    (prob[t] < 1.0 ? small : large).push_back((uint32_t)t);
+  }
+  while (!small.empty() && !large.empty()) {
+    const uint32_t l = small.back(); small.pop_back();
+    const uint32_t g = large.back(); large.pop_back();
+    alias[l] = g;
+    prob[g] = (prob[g] + prob[l]) - 1.0;
+    (prob[g] < 1.0 ? small : large).push_back(g);
+  }
+  for (uint32_t t : large) prob[t] = 1.0;
+  for (uint32_t t : small) prob[t] = 1.0;  // rounding leftovers
+  constexpr uint64_t kBlockQ = 1ull << 16;
+  const uint64_t blocks = (nq + kBlockQ - 1) / kBlockQ;
+  // pass 1: k of every query
+  offsets[0] = 0;
+  parallel_for(blocks, nthreads, [&](uint64_t b) {
+    Xoshiro rng(stream_seed(seed, 2 * b));
+    const uint64_t q1 = std::min(nq, (b + 1) * kBlockQ);
+    for (uint64_t q = b * kBlockQ; q < q1; ++q) offsets[q + 1] = kmin + rng.below(kmax - kmin + 1);
+  });
+  for (uint64_t q = 0; q < nq; ++q) offsets[q + 1] += offsets[q];
+  // pass 2: the terms
+  parallel_for(blocks, nthreads, [&](uint64_t b) {
+    Xoshiro rng(stream_seed(seed, 2 * b + 1));
+    const uint64_t q1 = std::min(nq, (b + 1) * kBlockQ);
+    for (uint64_t q = b * kBlockQ; q < q1; ++q) {
+      uint32_t *cur = terms + offsets[q];
+      const uint32_t k = (uint32_t)(offsets[q + 1] - offsets[q]);
+      uint32_t have = 0;
+      while (have < k) {
+        const uint64_t i = rng.below(nlists);
+        const double u = (double)(rng.next() >> 11) * (1.0 / 9007199254740992.0);
+        const uint32_t t = u < prob[i] ? (uint32_t)i : alias[i];
+        if (std::find(cur, cur + have, t) == cur + have) cur[have++] = t;
+      }
+    }
+  });
+  return 0;
+}
+
 // Poisson arrival times (seconds) at the given rate.
 int wl_arrivals(uint64_t seed, double rate, uint64_t count, double *times) {
   if (!(rate > 0)) return -1;
