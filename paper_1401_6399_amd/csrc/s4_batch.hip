@@ -50,6 +50,9 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
   // completion stamps: one atomic per run of consecutive chunks of a query
   uint32_t run_q = kInvalid;
   uint64_t run_t = 0;
+  // search hint of the second list: valid while the wave takes the next
+  // chunk of the same pair of lists
+  uint32_t hint = 0, h_id0 = kInvalid, h_id1 = kInvalid, h_local = kInvalid;
   // drain queue p: chunks base .. base + size in queue order
   auto drain = [&](uint32_t p, uint32_t base, uint32_t size) {
     for (;;) {
@@ -70,9 +73,13 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
         const DList f1 = cst(b.lists)[id1];
         r.raw = nullptr;
         r.len = r.L.n;
+        if (id0 != h_id0 || id1 != h_id1 || local != h_local + 1) hint = 0;
         const uint32_t cnt = chain_chunk<FEAT>(
             r, local, f1, [&](uint32_t j) -> DList { return cst(b.lists)[uniform(b.sterms[tq + 1 + j])]; }, k - 1,
-            lds[w], gallop_blocks, tr);
+            lds[w], gallop_blocks, tr, hint);
+        h_id0 = id0;
+        h_id1 = id1;
+        h_local = local;
         const uint32_t slot = (FEAT & kFeatParts) ? b.item_rank[item] : item;
         store_chunk(cnt, lds[w], b.stage + uint64_t(slot) * kBlock, b.counts + slot);
         const uint64_t now = wall_clock64() - t0;
@@ -171,6 +178,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   Traffic tr;
+  uint32_t hint = 0, h_id0 = kInvalid, h_id1 = kInvalid, h_local = kInvalid;  // as in k_batch_chunks
   for (;;) {
     uint32_t it0 = 0;
     if (lane == 0) it0 = atomicAdd(b.head, grab);
@@ -186,9 +194,13 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
       const DList f1 = cst(b.lists)[id1];
       r.raw = nullptr;
       r.len = r.L.n;
+      if (id0 != h_id0 || id1 != h_id1 || local != h_local + 1) hint = 0;
       const uint32_t cnt = chain_chunk<FEAT>(
           r, local, f1, [&](uint32_t j) -> DList { return cst(b.lists)[uniform(b.sterms[tq + 1 + j])]; }, k - 1,
-          lds[w], gallop_blocks, tr);
+          lds[w], gallop_blocks, tr, hint);
+      h_id0 = id0;
+      h_id1 = id1;
+      h_local = local;
       bool ok = true;
       const uint32_t excl = lookback(b.state, item, b.epoch, cnt, b.err, ok);
       if (ok && uint64_t(excl) + cnt <= out_cap) {

@@ -510,9 +510,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_chain(DList rl, const uint32_t *
   const uint64_t n_items = (r.len + kBlock - 1) / kBlock;
   Traffic tr;
   uint32_t cnt = 0;
+  uint32_t hint = 0;  // one chunk per wave: no previous chunk to start from
   if (item < n_items)
     cnt = chain_chunk<FEAT>(r, item, args.f[0], [&](uint32_t j) -> const DList & { return args.f[j]; }, args.nf,
-                            lds[w], gallop_blocks, tr);
+                            lds[w], gallop_blocks, tr, hint);
   bool ok = true;
   const uint32_t excl = run_lookback(rs, item, epoch, cnt, ok);
   if (ok) {

@@ -423,6 +423,37 @@ __device__ __forceinline__ void coop_lower_bound2(gconst<uint32_t> v, uint32_t n
   r1 = uniform(lo1);
 }
 
+// The same two lower bounds when both answers are known to be >= start:
+// a first round probes the 32 entries from start (lanes 0..31 for key0,
+// 32..63 for key1; the entries below a key form a prefix of the window),
+// which settles both keys when their answers lie in it; only what is left
+// goes to the 32-ary search of the rest.  Consecutive chunks of one list
+// pass the previous chunk's last block as start, so in the merge regime
+// a search costs one round instead of log_32 n.
+__device__ __forceinline__ void coop_lower_bound2_from(gconst<uint32_t> v, uint32_t n, uint32_t start, uint32_t key0,
+                                                       uint32_t key1, uint32_t &r0, uint32_t &r1) {
+  if (start == 0) {
+    coop_lower_bound2(v, n, key0, key1, r0, r1);
+    return;
+  }
+  const uint32_t lane = lane_id();
+  const uint32_t pos = start + (lane & 31u);
+  const uint32_t key = lane >= 32 ? key1 : key0;
+  const bool below = pos < n && v[pos] < key;
+  const uint64_t m = __ballot(below);
+  const uint32_t c0 = uint32_t(__popcll(m & 0xFFFFFFFFull)), c1 = uint32_t(__popcll(m >> 32));
+  r0 = start + c0;
+  r1 = start + c1;
+  // a key with all 32 window entries below it (the window inside the list)
+  // continues past the window; key0 <= key1, so key1 is then unsettled too
+  if (c1 == 32 && start + 32 < n) {
+    uint32_t a0, a1;
+    coop_lower_bound2(v + (start + 32), n - (start + 32), key0, key1, a0, a1);
+    if (c0 == 32) r0 = start + 32 + a0;
+    r1 = start + 32 + a1;
+  }
+}
+
 // ------------------------------------------------------------ pair items
 
 // Per-wave LDS of the intersection kernels.
@@ -551,7 +582,7 @@ __device__ __forceinline__ uint32_t compact_chunk(bool f0, bool f1, uint32_t a0,
 // the skip index), each distinct candidate once.
 template <bool PATCHED>
 __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f, ItemLds &s,
-                                                    uint32_t gallop_blocks, Traffic &tr) {
+                                                    uint32_t gallop_blocks, Traffic &tr, uint32_t &hint) {
   const uint32_t lane = lane_id();
   const bool v0 = lane < cnt, v1 = lane + 64 < cnt;
   const uint32_t a0 = v0 ? s.r[lane] : 0u;
@@ -565,8 +596,13 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
   // two are independent, so their loads overlap
   uint32_t fmax = 0;
   if (f.n > 0) fmax = ftail ? gbl(f.tail)[f.t - 1] : gbl(f.bmax)[nbf - 1];
+  // hint: a block index no later than this chunk's first candidate (the
+  // previous chunk's last candidate, or 0); it becomes this chunk's last
   uint32_t lo = 0, hi = 0;
-  if (cnt > 0) coop_lower_bound2(gbl(f.bmax), nbf, first, last, lo, hi);
+  if (cnt > 0) {
+    coop_lower_bound2_from(gbl(f.bmax), nbf, min(hint, nbf), first, last, lo, hi);
+    hint = hi;
+  }
   const bool any = cnt > 0 && f.n > 0 && first <= fmax;
   bool f0 = false, f1 = false;
   if (any) {
@@ -661,9 +697,11 @@ __device__ __forceinline__ void store_chunk(uint32_t cnt, const ItemLds &s, uint
 // order, stopping early when nothing survives (Sec. 6: pairwise, from the
 // shortest list up).  Intersection distributes over a partition of the
 // shortest list, so chunks are independent.
+// hint0: the search hint of the first list (see intersect_chunk), carried
+// by the caller from one chunk of r to the next; later lists start at 0.
 template <uint32_t FEAT, class FList>
 __device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, const DList &f0, FList f, uint32_t nf,
-                                                ItemLds &s, uint32_t gallop_blocks, Traffic &tr) {
+                                                ItemLds &s, uint32_t gallop_blocks, Traffic &tr, uint32_t &hint0) {
   uint32_t cnt = load_chunk<FEAT>(r, item, s, tr);
   // f0 (the second-shortest list, j = 0) comes in already loaded; later
   // lists are loaded as the chain reaches them
@@ -672,8 +710,10 @@ __device__ __forceinline__ uint32_t chain_chunk(const RSide &r, uint32_t item, c
     if (j > 0) fj = f(j);
     if ((FEAT & kFeatBitmap) && fj.mode == kBitmapList)
       cnt = probe_chunk(cnt, fj, s, tr);
-    else
-      cnt = intersect_chunk<(FEAT & kFeatPatched) != 0>(cnt, fj, s, gallop_blocks, tr);
+    else {
+      uint32_t h = 0;
+      cnt = intersect_chunk<(FEAT & kFeatPatched) != 0>(cnt, fj, s, gallop_blocks, tr, j == 0 ? hint0 : h);
+    }
   }
   tr.add(4u * cnt);  // the chunk's results
   return cnt;

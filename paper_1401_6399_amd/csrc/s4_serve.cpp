@@ -705,6 +705,10 @@ int s4_server_stats_get(const s4_server *s, s4_server_stats *st) {
   return S4_OK;
 }
 
+// Replay submission batching (see s4_server_replay).
+constexpr size_t kSubmitBatch = 256;
+constexpr uint64_t kSubmitWaitNs = 10000;
+
 int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
                      const uint64_t *h_arrival_ns, uint64_t *latency_ns, uint64_t *counts, uint32_t *results,
                      uint64_t results_cap, uint64_t *res_offsets, const uint8_t *keep, double timeout_s,
@@ -731,12 +735,13 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
   const auto t0 = Clock::now();
   auto now_ns = [&]() { return ns_between(t0, Clock::now()); };
   uint64_t last_done_ns = 0, last_drain_ns = 0;
+  // queries [next, prepared) are validated and wait in `due` to be queued
+  uint64_t prepared = 0;
   while (ndone < nq) {
-    // every query due by now, validated without the lock, queued under one
+    // every query due by now, validated without the lock
     const uint64_t t = now_ns();
-    due.clear();
-    for (uint64_t q = next; q < nq && h_arrival_ns[q] <= t && due.size() < 8192; ++q) {
-      const uint64_t a = h_q_offsets[q], b = h_q_offsets[q + 1];
+    for (; prepared < nq && h_arrival_ns[prepared] <= t && due.size() < 8192; ++prepared) {
+      const uint64_t a = h_q_offsets[prepared], b = h_q_offsets[prepared + 1];
       due.emplace_back();
       int rc = prepare_query(s, h_terms + a, uint32_t(b - a), &due.back());
       if (rc) {
@@ -747,9 +752,15 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
         return rc;
       }
     }
-    // nothing due: take the lock only to drain now and then (latencies are
-    // stamped by the dispatcher, not here)
-    if (due.empty() && t < last_drain_ns + 50000) continue;
+    // queued under one lock per batch: at least kSubmitBatch queries, or
+    // the oldest has waited kSubmitWaitNs, or no more will arrive (taking
+    // the lock for every few queries of a fast arrival stream kept the
+    // dispatcher from its admissions); otherwise the lock is taken only to
+    // drain completions now and then (latencies are stamped by the
+    // dispatcher, not here)
+    const bool submit = !due.empty() && (due.size() >= kSubmitBatch || prepared == nq ||
+                                         t >= h_arrival_ns[next] + kSubmitWaitNs);
+    if (!submit && t < last_drain_ns + 50000) continue;
     last_drain_ns = t;
     {
       std::lock_guard<std::mutex> lock(s->mu);
@@ -774,6 +785,7 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
       got.swap(s->completed);
       got_jobs.swap(s->completed_jobs);
     }
+    due.erase(due.begin(), due.begin() + std::ptrdiff_t(std::min<uint64_t>(due.size(), next + due.size() - prepared)));
     // completions, outside the lock
     auto finish = [&](uint64_t id, uint64_t count, Clock::time_point at) -> uint64_t {
       if (id0 == UINT64_MAX || id < id0 || id - id0 >= q_of.size() || q_of[id - id0] == UINT64_MAX) return UINT64_MAX;
