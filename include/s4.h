@@ -572,6 +572,11 @@ typedef struct {
   uint64_t sliced_queries;   /* queries run in more than one slice */
   uint64_t device_ns;        /* summed launch-to-finish time of iterations, as seen by the dispatcher */
   uint64_t host_ns;          /* dispatcher time spent packing, launching and retiring iterations */
+  uint64_t retire_ns;        /* ... of which retiring finished iterations (results handed over) */
+  uint64_t admit_ns;         /* ... admitting queries into a free context (under the server lock;
+                                also counted when nothing was admitted) */
+  uint64_t launch_ns;        /* ... packing an iteration's tables and launching it (host_ns also
+                                counts the lock taken after a launch) */
 } s4_server_stats;
 int s4_server_stats_get(const s4_server *srv, s4_server_stats *st);
 /* Stop accepting, finish every admitted query, join the dispatcher. */

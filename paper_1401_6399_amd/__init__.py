@@ -53,7 +53,8 @@ class ServerStats(ctypes.Structure):
                 ("peak_pool_bytes", ctypes.c_uint64), ("waits_for_memory", ctypes.c_uint64),
                 ("max_batch", ctypes.c_uint64), ("direct_iterations", ctypes.c_uint64),
                 ("single_pass_iterations", ctypes.c_uint64), ("sliced_queries", ctypes.c_uint64),
-                ("device_ns", ctypes.c_uint64), ("host_ns", ctypes.c_uint64)]
+                ("device_ns", ctypes.c_uint64), ("host_ns", ctypes.c_uint64), ("retire_ns", ctypes.c_uint64),
+                ("admit_ns", ctypes.c_uint64), ("launch_ns", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -394,7 +394,7 @@ void retire_context(s4_server *s, Context &c, const uint32_t *res) {
 
 void dispatcher(s4_server *s) {
   (void)hipSetDevice(s->device);
-  uint64_t device_ns = 0, host_ns = 0;
+  uint64_t device_ns = 0, host_ns = 0, retire_ns = 0, admit_ns = 0, launch_ns = 0;
   for (;;) {
     bool progressed = false;
     for (Context &c : s->ctx) {
@@ -416,7 +416,9 @@ void dispatcher(s4_server *s) {
         } else {
           retire_context(s, c, c.h_results);
         }
-        host_ns += ns_between(t0, Clock::now());
+        const uint64_t dt = ns_between(t0, Clock::now());
+        host_ns += dt;
+        retire_ns += dt;
         progressed = true;
       }
     }
@@ -521,8 +523,11 @@ void dispatcher(s4_server *s) {
           ++s->st.iterations;
         }
       }
+      const auto t1 = Clock::now();
+      admit_ns += ns_between(t0, t1);
       if (!c.slices.empty()) {
         int rc = launch_context(s, c);
+        launch_ns += ns_between(t1, Clock::now());
         if (rc) {
           std::lock_guard<std::mutex> lock(s->mu);
           s->worker_error = rc;
@@ -542,6 +547,9 @@ void dispatcher(s4_server *s) {
       std::unique_lock<std::mutex> lock(s->mu);
       s->st.device_ns = device_ns;
       s->st.host_ns = host_ns;
+      s->st.retire_ns = retire_ns;
+      s->st.admit_ns = admit_ns;
+      s->st.launch_ns = launch_ns;
       for (Context &c : s->ctx) any_busy |= c.busy;
       const bool jobs_left = !s->jobs.empty();
       if (s->stop && !any_busy && ((s->waiting.empty() && !jobs_left) || s->worker_error)) break;
