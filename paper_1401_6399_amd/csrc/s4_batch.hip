@@ -58,16 +58,16 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
     for (;;) {
       uint32_t it0 = 0;
       if (lane == 0) it0 = atomicAdd(b.head + p, grab);
-      it0 = uint32_t(__shfl(int(it0), 0));
+      it0 = uniform(it0);  // lane 0's value: every lane is active here
       if (it0 >= size) break;
       const uint32_t it1 = min(it0 + grab, size);
       for (uint32_t rel = it0; rel < it1; ++rel) {
         const uint32_t item = base + rel;
         // one record per chunk: query, chunk within the query, first term, terms
-        const uint4 info = b.item_info[item];
+        const uint4 info = cst(b.item_info)[item];
         const uint32_t q = uniform(info.x), local = uniform(info.y), tq = uniform(info.z), k = uniform(info.w);
         // the two shortest lists' descriptors, loaded together up front
-        const uint32_t id0 = uniform(b.sterms[tq]), id1 = uniform(b.sterms[tq + (k > 1 ? 1 : 0)]);
+        const uint32_t id0 = uniform(cst(b.sterms)[tq]), id1 = uniform(cst(b.sterms)[tq + (k > 1 ? 1 : 0)]);
         RSide r;
         r.L = cst(b.lists)[id0];
         const DList f1 = cst(b.lists)[id1];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
         r.len = r.L.n;
         if (id0 != h_id0 || id1 != h_id1 || local != h_local + 1) hint = 0;
         const uint32_t cnt = chain_chunk<FEAT>(
-            r, local, f1, [&](uint32_t j) -> DList { return cst(b.lists)[uniform(b.sterms[tq + 1 + j])]; }, k - 1,
+            r, local, f1, [&](uint32_t j) -> DList { return cst(b.lists)[uniform(cst(b.sterms)[tq + 1 + j])]; }, k - 1,
             lds[w], gallop_blocks, tr, hint);
         h_id0 = id0;
         h_id1 = id1;
@@ -182,13 +182,13 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
   for (;;) {
     uint32_t it0 = 0;
     if (lane == 0) it0 = atomicAdd(b.head, grab);
-    it0 = uint32_t(__shfl(int(it0), 0));
+    it0 = uniform(it0);  // lane 0's value: every lane is active here
     if (it0 >= b.items) break;
     const uint32_t it1 = min(it0 + grab, b.items);
     for (uint32_t item = it0; item < it1; ++item) {
-      const uint4 info = b.item_info[item];
+      const uint4 info = cst(b.item_info)[item];
       const uint32_t q = uniform(info.x), local = uniform(info.y), tq = uniform(info.z), k = uniform(info.w);
-      const uint32_t id0 = uniform(b.sterms[tq]), id1 = uniform(b.sterms[tq + (k > 1 ? 1 : 0)]);
+      const uint32_t id0 = uniform(cst(b.sterms)[tq]), id1 = uniform(cst(b.sterms)[tq + (k > 1 ? 1 : 0)]);
       RSide r;
       r.L = cst(b.lists)[id0];
       const DList f1 = cst(b.lists)[id1];
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
       r.len = r.L.n;
       if (id0 != h_id0 || id1 != h_id1 || local != h_local + 1) hint = 0;
       const uint32_t cnt = chain_chunk<FEAT>(
-          r, local, f1, [&](uint32_t j) -> DList { return cst(b.lists)[uniform(b.sterms[tq + 1 + j])]; }, k - 1,
+          r, local, f1, [&](uint32_t j) -> DList { return cst(b.lists)[uniform(cst(b.sterms)[tq + 1 + j])]; }, k - 1,
           lds[w], gallop_blocks, tr, hint);
       h_id0 = id0;
       h_id1 = id1;
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
       }
       // first chunk of its entry (entries may start at any chunk of their
       // query): the previous chunk belongs to an earlier entry
-      const uint32_t qprev = item ? uniform(b.item_info[item - 1].x) : kInvalid;
+      const uint32_t qprev = item ? uniform(cst(b.item_info)[item - 1].x) : kInvalid;
       if (item == 0 || qprev != q) {
         const uint32_t q0 = item ? qprev + 1 : 0u;
         for (uint32_t qq = q0 + lane; qq <= q; qq += 64) offs[qq] = excl;

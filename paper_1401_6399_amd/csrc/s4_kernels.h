@@ -330,12 +330,29 @@ __device__ __forceinline__ void decode_row(const DList &L, uint32_t k, bool acti
   prefix_deltas<true>(L.mode, d0, d1, sv, x0, x1);
 }
 
+// The same where every row names a block of the list (k < L.nb in every
+// lane): rows whose values are not wanted pass some block that is (or
+// another valid one) and `active` false, which only keeps them out of the
+// patch step.  With no row to switch off, no lane waits on a branch or
+// zeroes its deltas.
+template <bool PATCHED>
+__device__ __forceinline__ void decode_row_any(const DList &L, uint32_t k, bool active, uint32_t i,
+                                               uint32_t x0[4], uint32_t x1[4], uint32_t *scratch) {
+  uint32_t d0[4], d1[4];
+  extract_row(L.payload + gbl(L.offs)[k], gbl(L.widths)[k], i, d0, d1);
+  const uint4 seed = gbl(L.seeds)[k];
+  if (PATCHED && is_patched(L)) patch_row(L, k, active, i, scratch, d0, d1);
+  const uint32_t sv[4] = {seed.x, seed.y, seed.z, seed.w};
+  prefix_deltas<true>(L.mode, d0, d1, sv, x0, x1);
+}
+
 // Decode block k of L (a D4 list) with the whole wave (half-wave layout):
 // lane l takes q = l mod 32 and lanes j0 = 2 (l div 32), j0 + 1; the two
 // half-waves scan over q.  Writes the 128 values to dst[0..127].
 __device__ __forceinline__ void decode_block_wave(const DList &L, uint32_t k, uint32_t *dst) {
   const uint32_t l = lane_id();
   const uint32_t q = l & 31u, j0 = (l >> 5) * 2u;
+  const uint4 seed = gbl(L.seeds)[k];  // issued with the width and offset loads
   const uint32_t b = gbl(L.widths)[k];
   const uint32_t *w = L.payload + gbl(L.offs)[k];
   const uint32_t bit = q * b, m = bit >> 5, s = bit & 31u;
@@ -344,7 +361,6 @@ __device__ __forceinline__ void decode_block_wave(const DList &L, uint32_t k, ui
   const uint32_t mask = width_mask(b);
   const uint32_t d0 = funnel(hi.x, lo.x, s) & mask;
   const uint32_t d1 = funnel(hi.y, lo.y, s) & mask;
-  const uint4 seed = gbl(L.seeds)[k];
   const uint32_t s0 = j0 ? seed.z : seed.x, s1 = j0 ? seed.w : seed.y;
   const uint32_t x0 = s0 + scan_half32(d0);
   const uint32_t x1 = s1 + scan_half32(d1);
@@ -368,18 +384,27 @@ __device__ __forceinline__ uint32_t lower_bound_u32(Ptr v, uint32_t lo, uint32_t
   return lo;
 }
 
-// Whether key is among the first n (<= 128) values of a decoded block row
-// in LDS, sorted, with the entries from n up to 128 holding 0xFFFFFFFF: a
-// lower bound by seven fixed halvings (unrolled: a step is one LDS read, a
-// compare and a select, with no loop control), then one compare.  Entries
-// at n and beyond never satisfy p < n, so a key of 0xFFFFFFFF is found only
-// where the row really holds it.
-__device__ __forceinline__ bool block_has(const uint32_t *v, uint32_t n, uint32_t key) {
-  uint32_t p = 0;
+// Whether key is among the values of a decoded block row in LDS: 128
+// sorted values, or a raw tail of n < 128 values followed by 0xFFFFFFFF
+// entries, for a key no larger than the row's largest value (the
+// candidate choice over the skip index guarantees it: a key goes to the
+// first block whose maximum is not below it, and to the tail only when
+// it is at most the list's last value).  A lower bound by seven fixed
+// halvings then lands on a real entry; one compare decides.  The probe is
+// a byte address in LDS that each step advances by its distance when the
+// entry it reads is below the key (a read with an immediate offset, a
+// compare, a select and a shifted add); the empty asm keeps the compiler
+// from rebuilding it as the row base plus an offset every step.
+__device__ __forceinline__ bool block_has(const uint32_t *v, uint32_t key) {
+  using lds_u32 = const S4_ADDRSPACE(3) uint32_t;
+  uint32_t a = uint32_t(uintptr_t((lds_u32 *)v));
 #pragma unroll
-  for (uint32_t step = kBlock / 2; step; step >>= 1)
-    if (v[p + step - 1] < key) p += step;
-  return p < n && v[p] == key;
+  for (int lg = 6; lg >= 0; --lg) {
+    const uint32_t t = *(lds_u32 *)uintptr_t(a + (4u << lg) - 4u);
+    a += uint32_t(t < key) << (lg + 2);
+    asm volatile("" : "+v"(a));
+  }
+  return *(lds_u32 *)uintptr_t(a) == key;
 }
 
 // Two lower bounds at once over v[0 .. n): r0 = first index with
@@ -429,9 +454,14 @@ __device__ __forceinline__ void coop_lower_bound2(gconst<uint32_t> v, uint32_t n
 // which settles both keys when their answers lie in it; only what is left
 // goes to the 32-ary search of the rest.  Consecutive chunks of one list
 // pass the previous chunk's last block as start, so in the merge regime
-// a search costs one round instead of log_32 n.
+// a search costs one round instead of log_32 n.  The window is returned:
+// win_at = start when the round ran (else kInvalid), and lane l (l < 32)
+// holds v[start + l] in win (kInvalid past the end).
 __device__ __forceinline__ void coop_lower_bound2_from(gconst<uint32_t> v, uint32_t n, uint32_t start, uint32_t key0,
-                                                       uint32_t key1, uint32_t &r0, uint32_t &r1) {
+                                                       uint32_t key1, uint32_t &r0, uint32_t &r1, uint32_t &win,
+                                                       uint32_t &win_at) {
+  win = kInvalid;
+  win_at = kInvalid;
   if (start == 0) {
     coop_lower_bound2(v, n, key0, key1, r0, r1);
     return;
@@ -439,7 +469,9 @@ __device__ __forceinline__ void coop_lower_bound2_from(gconst<uint32_t> v, uint3
   const uint32_t lane = lane_id();
   const uint32_t pos = start + (lane & 31u);
   const uint32_t key = lane >= 32 ? key1 : key0;
-  const bool below = pos < n && v[pos] < key;
+  if (pos < n) win = v[pos];
+  win_at = start;
+  const bool below = pos < n && win < key;
   const uint64_t m = __ballot(below);
   const uint32_t c0 = uint32_t(__popcll(m & 0xFFFFFFFFull)), c1 = uint32_t(__popcll(m >> 32));
   r0 = start + c0;
@@ -545,7 +577,7 @@ __device__ __forceinline__ uint32_t load_chunk(const RSide &r, uint32_t item, It
       // layout (patching through s.r)
       uint32_t x0[4], x1[4];
       const uint32_t ri = lane & 15u;
-      decode_row<(FEAT & kFeatPatched) != 0>(r.L, item, lane < 16, ri, x0, x1, s.r);
+      decode_row_any<(FEAT & kFeatPatched) != 0>(r.L, item, lane < 16, ri, x0, x1, s.r);
       if (lane < 16) {
         *reinterpret_cast<uint4 *>(&s.r[8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
         *reinterpret_cast<uint4 *>(&s.r[8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
@@ -598,9 +630,9 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
   if (f.n > 0) fmax = ftail ? gbl(f.tail)[f.t - 1] : gbl(f.bmax)[nbf - 1];
   // hint: a block index no later than this chunk's first candidate (the
   // previous chunk's last candidate, or 0); it becomes this chunk's last
-  uint32_t lo = 0, hi = 0;
+  uint32_t lo = 0, hi = 0, win = kInvalid, win_at = kInvalid;
   if (cnt > 0) {
-    coop_lower_bound2_from(gbl(f.bmax), nbf, min(hint, nbf), first, last, lo, hi);
+    coop_lower_bound2_from(gbl(f.bmax), nbf, min(hint, nbf), first, last, lo, hi, win, win_at);
     hint = hi;
   }
   const bool any = cnt > 0 && f.n > 0 && first <= fmax;
@@ -610,7 +642,13 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
     uint32_t c0, c1;
     if (span <= gallop_blocks) {
       // merge regime: stage the spanned bmax entries in LDS, search there
-      for (uint32_t e = lane; e < span; e += 64) s.bm[e] = (lo + e < nbf) ? gbl(f.bmax)[lo + e] : kInvalid;
+      // (from the search's window when it holds them: no memory round trip)
+      if (win_at != kInvalid && lo >= win_at && lo + span <= win_at + 32) {
+        const uint32_t x = uint32_t(__shfl(int(win), int(lo - win_at + min(lane, span - 1))));
+        if (lane < span) s.bm[lane] = x;
+      } else {
+        for (uint32_t e = lane; e < span; e += 64) s.bm[e] = (lo + e < nbf) ? gbl(f.bmax)[lo + e] : kInvalid;
+      }
       tr.add(4u * span);
       wave_sync();
       c0 = lo + lower_bound_u32(s.bm, 0, span - 1, a0);
@@ -650,19 +688,27 @@ __device__ __forceinline__ uint32_t intersect_chunk(uint32_t cnt, const DList &f
                     uint32_t(__builtin_amdgcn_readlane(int(tb), 32)) + uint32_t(__builtin_amdgcn_readlane(int(tb), 48));
         tr.blocks += min(4u, U - g);
       }
-      uint32_t x0[4], x1[4];
-      decode_row<PATCHED>(f, blk, blk < nbf, ri, x0, x1, s.f[row]);
-      if (blk < nbf) {
-        *reinterpret_cast<uint4 *>(&s.f[row][8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
-        *reinterpret_cast<uint4 *>(&s.f[row][8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
-      } else if (blk == nbf) {
+      // rows past the candidates, and the tail's row, decode a candidate
+      // block of the group instead (row 0's, else the last full block):
+      // their values are not kept
+      if (nbf > 0) {
+        const uint32_t b0 = uint32_t(__builtin_amdgcn_readfirstlane(int(blk)));
+        const uint32_t kb = blk < nbf ? blk : (b0 < nbf ? b0 : nbf - 1);
+        uint32_t x0[4], x1[4];
+        decode_row_any<PATCHED>(f, kb, blk < nbf, ri, x0, x1, s.f[row]);
+        if (blk < nbf) {
+          *reinterpret_cast<uint4 *>(&s.f[row][8 * ri]) = make_uint4(x0[0], x0[1], x0[2], x0[3]);
+          *reinterpret_cast<uint4 *>(&s.f[row][8 * ri + 4]) = make_uint4(x1[0], x1[1], x1[2], x1[3]);
+        }
+      }
+      if (blk == nbf) {
         // the raw tail, padded to a full row for block_has
         for (uint32_t e = 0; e < 8; ++e)
           s.f[row][8 * ri + e] = 8 * ri + e < f.t ? gbl(f.tail)[8 * ri + e] : kInvalid;
       }
       wave_sync();
-      if (slot0 - g < 4u) f0 = block_has(s.f[slot0 - g], c0 == nbf ? f.t : kBlock, a0);
-      if (slot1 - g < 4u) f1 = block_has(s.f[slot1 - g], c1 == nbf ? f.t : kBlock, a1);
+      if (slot0 - g < 4u) f0 = block_has(s.f[slot0 - g], a0);
+      if (slot1 - g < 4u) f1 = block_has(s.f[slot1 - g], a1);
       wave_sync();
     }
   }
