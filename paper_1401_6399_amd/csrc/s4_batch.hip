@@ -36,8 +36,11 @@ constexpr uint32_t kXcds = 8;
 // part's lists, then helps every other queue.
 // The chunk kernels are latency-bound, so resident waves matter most: the
 // plain instantiation is held to 64 VGPRs (8 waves per SIMD, whose LDS,
-// 5 KB per wave, then just fills a CU) and the others to 80 (6 waves), all
-// without spilling.
+// 5 KB per wave, then just fills a CU) and the others to 80 (6 waves),
+// without spilling.  Work added to the per-chunk path that keeps more values
+// live (loading the next candidate group's block metadata during the
+// current group, decoding r's block while the first list is searched)
+// measured slower than the round trips it saved.
 template <int WAVES, uint32_t FEAT>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT == 0 ? 8 : 6))) void k_batch_chunks(
     BatchDev b, uint32_t grab, uint32_t gallop_blocks) {
@@ -45,8 +48,10 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   const uint64_t t0 = *b.start;
+  // counting is an instantiation of its own: the timed kernels carry no
+  // counters (they cost the chunk pipeline registers and issue slots)
   Traffic tr;
-  tr.on = b.count != 0;
+  tr.on = (FEAT & kFeatCount) != 0;
   // completion stamps: one atomic per run of consecutive chunks of a query
   uint32_t run_q = kInvalid;
   uint64_t run_t = 0;
@@ -271,17 +276,24 @@ static void launch_chunks(const BatchDev &d, const s4_tuning &t, hipStream_t st)
 }
 
 // The instantiation for the kinds of list the index holds (bitmap lists
-// and parts never come together).
+// and parts never come together), with or without traffic counting.
+template <int W, uint32_t C>
+static void launch_chunks_feat(const BatchDev &d, const s4_tuning &t, hipStream_t st) {
+  switch ((d.feat & (kFeatBitmap | kFeatPatched)) | (d.parts > 1 ? kFeatParts : 0u)) {
+    case kFeatBitmap: launch_chunks<W, C | kFeatBitmap>(d, t, st); break;
+    case kFeatPatched: launch_chunks<W, C | kFeatPatched>(d, t, st); break;
+    case kFeatBitmap | kFeatPatched: launch_chunks<W, C | kFeatBitmap | kFeatPatched>(d, t, st); break;
+    case kFeatParts: launch_chunks<W, C | kFeatParts>(d, t, st); break;
+    case kFeatParts | kFeatPatched: launch_chunks<W, C | kFeatParts | kFeatPatched>(d, t, st); break;
+    default: launch_chunks<W, C>(d, t, st); break;
+  }
+}
 template <int W>
 static void launch_chunks_w(const BatchDev &d, const s4_tuning &t, hipStream_t st) {
-  switch ((d.feat & (kFeatBitmap | kFeatPatched)) | (d.parts > 1 ? kFeatParts : 0u)) {
-    case kFeatBitmap: launch_chunks<W, kFeatBitmap>(d, t, st); break;
-    case kFeatPatched: launch_chunks<W, kFeatPatched>(d, t, st); break;
-    case kFeatBitmap | kFeatPatched: launch_chunks<W, kFeatBitmap | kFeatPatched>(d, t, st); break;
-    case kFeatParts: launch_chunks<W, kFeatParts>(d, t, st); break;
-    case kFeatParts | kFeatPatched: launch_chunks<W, kFeatParts | kFeatPatched>(d, t, st); break;
-    default: launch_chunks<W, 0>(d, t, st); break;
-  }
+  if (d.count)
+    launch_chunks_feat<W, kFeatCount>(d, t, st);
+  else
+    launch_chunks_feat<W, 0>(d, t, st);
 }
 
 template <int W, uint32_t F>

@@ -198,7 +198,7 @@ struct BatchDev {
   uint32_t items, nq, ntiles;
   uint32_t epoch;             // single-pass scan generation, 1 .. 2^30 - 1
   uint32_t feat;              // kinds of list in the index (kFeat* of the chunk pipeline)
-  uint32_t count;             // nonzero: count algorithmic bytes and blocks into stats
+  uint32_t count;             // nonzero: the counting instantiation runs, adding algorithmic bytes and blocks into stats
 };
 // Enqueue one run of a batch on st: persistent chunk kernel, scan,
 // compaction into d_results, per-query counts / CSR offsets.

@@ -309,6 +309,7 @@ __device__ __forceinline__ void patch_row_rec(const DList &L, const uint4 x, boo
 constexpr uint32_t kFeatBitmap = 1;   // hybrid-index bitmap lists
 constexpr uint32_t kFeatPatched = 2;  // patched (S4-FastPFOR) lists
 constexpr uint32_t kFeatParts = 4;    // doc-ID partitioned index (per-part queues; batch kernel only)
+constexpr uint32_t kFeatCount = 8;    // algorithmic traffic counted (the batch kernel's counting runs only)
 
 // Decode block k of L with one 16-lane row per block: extract, patch when
 // the list is patched (its exceptions, staged through the row's 128-word
@@ -505,9 +506,11 @@ struct RSide {
 
 // Algorithmic bytes read by a wave (uniform): packed payload + width byte +
 // block offset + seed of every decoded block, staged skip-index entries,
-// raw values; and the number of blocks decoded.  Counted only when `on`:
-// the count (a width load and cross-lane reads per candidate group) slows
-// the chunk kernels, bound by instruction issue, by 4-15%.
+// raw values; and the number of blocks decoded.  Counted only when `on`,
+// which the batch kernel's counting instantiation alone sets: the count (a
+// width load and cross-lane reads per candidate group, and 64-bit
+// accumulators) would cost the other chunk kernels registers and issue
+// slots.
 struct Traffic {
   uint64_t bytes = 0;
   uint64_t blocks = 0;
