@@ -62,6 +62,11 @@ def test_edge_pairs(gpu):
         (np.array([base[7], 2**32 - 1], np.uint32), np.append(base[:300], np.uint32(2**32 - 1))),
         (np.array([base[7], 2**32 - 2], np.uint32), np.append(base[:300], np.uint32(2**32 - 1))),
         (np.append(base[250:300], np.uint32(2**32 - 1)), np.append(base[:300:2], np.uint32(2**32 - 1))),
+        # full blocks only, the last one ending at the largest value; and a
+        # raw tail below a key of 2^32 - 1 (the key lies past the list)
+        (np.array([base[3], 2**32 - 1], np.uint32), np.append(base[:255], np.uint32(2**32 - 1))),
+        (np.array([base[3], 2**32 - 2], np.uint32), np.append(base[:255], np.uint32(2**32 - 1))),
+        (np.array([base[299], 2**32 - 1], np.uint32), base[:300]),
         (base + np.uint32(1 << 30), base),
         (np.arange(0, 3000, 3, dtype=np.uint32), np.arange(0, 3000, 2, dtype=np.uint32)),
         (rng.choice(base, 300, replace=False), base),
