@@ -86,7 +86,7 @@ def parse():
                     help="length of each Poisson level of the serving leg (at least 2^16 queries)")
     ap.add_argument("--serve-saturate", type=int, default=1 << 24,
                     help="queries submitted at once to measure the serving burst rate")
-    ap.add_argument("--serve-saturate-s", type=float, default=10.0,
+    ap.add_argument("--serve-saturate-s", type=float, default=30.0,
                     help="length of the overloaded open-loop trace that measures the sustained rate Q*")
     ap.add_argument("--serve-plain", type=int, default=1 << 14,
                     help="queries of each level's trace replayed through the plain path")
@@ -566,15 +566,16 @@ def serving_leg(s4, workloads, torch, args):
         f"index, {8 * ix.payload_bytes / ix.total_ints:.2f} bits/int; built in {build_s:.1f} s")
     srv = s4.Server(ix, max_slots=1 << 15, pool_bytes=24 << 30, result_bytes=3 << 28, max_terms=8)
     # saturated rate: first every query of a trace submitted at once (a
-    # burst), then an open-loop trace offered above that rate for
-    # --serve-saturate-s seconds: what the server sustains under arrivals
-    # is Q*, and the levels are fractions of it
+    # burst), then an open-loop trace offered well above that rate (1.5x)
+    # for --serve-saturate-s seconds, as long as a level: what the server
+    # sustains under arrivals for that long is Q*, and the levels are
+    # fractions of it
     nsat = args.serve_saturate
     terms, qoffs = workloads.serving_trace(ix.lengths, nsat, 0)
     sat = srv.replay(terms, qoffs, np.zeros(nsat, np.uint64))
     q_burst = nsat / sat["elapsed_s"]
     log(f"burst: {q_burst:.0f} queries/s over {nsat} queries")
-    over = 1.25 * q_burst
+    over = 1.5 * q_burst
     nov = max(1 << 16, int(over * args.serve_saturate_s))
     terms, qoffs = workloads.serving_trace(ix.lengths, nov, 9)
     arr = (workloads.arrivals(workloads.config_seed(4, 29), over, nov) * 1e9).astype(np.uint64)
@@ -642,7 +643,7 @@ def serving_leg(s4, workloads, torch, args):
            "unit": "queries/s", "saturated_qps": round(qstar, 1),
            "saturated": {"qps": round(qstar, 1), "offered_qps": round(over, 1), "queries": nov,
                          "burst_qps": round(q_burst, 1), "burst_queries": nsat,
-                         "note": "Q* is what the server sustains under open-loop arrivals offered at 1.25x the rate "
+                         "note": "Q* is what the server sustains under open-loop arrivals offered at 1.5x the rate "
                                  "of a burst (every query of a trace submitted at once); the levels are fractions "
                                  "of Q*"},
            "levels": levels,

@@ -30,7 +30,10 @@
 //      scan, compaction), whose waves never wait on each other.
 // Queries that arrive while earlier ones run on the device are admitted into
 // the next free context and launched at once, so iterations overlap on the
-// device.  Per-query offsets, and the results themselves when their bound
+// device.  Submitters queue queries in batches (a replay hands over its
+// whole batch); the dispatcher takes every queued batch under the server
+// lock in one move and admits from them without it, so neither side copies
+// queries while the other waits for the lock.  Per-query offsets, and the results themselves when their bound
 // fits the context's result buffer, are written by the device straight into
 // pinned, device-mapped host memory; an iteration whose bound does not fit
 // writes to device memory and copies exactly the total back.
@@ -152,7 +155,13 @@ struct s4_server {
   Context ctx[kContexts];
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Query> waiting;
+  // queries submitted and not admitted yet: the batches submitters queue
+  // (under mu), which the dispatcher takes all at once into its own list
+  // and admits from without the lock; `queued` counts both (under mu)
+  std::deque<std::vector<Query>> incoming;
+  uint64_t queued = 0;
+  std::deque<std::vector<Query>> waiting;  // dispatcher only
+  size_t waiting_pos = 0;                  // first query of waiting.front() not admitted
   std::deque<DoneBatch> completed;     // whole queries, per iteration
   std::deque<DoneJob> completed_jobs;  // queries run in slices
   std::atomic<bool> stop{false};
@@ -433,8 +442,15 @@ void dispatcher(s4_server *s) {
       Context &c = *free_ctx;
       const auto t0 = Clock::now();
       {
-        std::unique_lock<std::mutex> lock(s->mu);
-        uint64_t items = 0, terms = 0, bound = 0, started = 0;
+        {
+          // every batch submitted so far, moved (not copied) under the lock
+          std::lock_guard<std::mutex> lock(s->mu);
+          while (!s->incoming.empty()) {
+            s->waiting.push_back(std::move(s->incoming.front()));
+            s->incoming.pop_front();
+          }
+        }
+        uint64_t items = 0, terms = 0, bound = 0, started = 0, memory_waits = 0, sliced = 0;
         // does a slice of `n` chunks, k terms and result bound `b` fit?
         auto fits = [&](uint64_t n, uint64_t k, uint64_t b) {
           if (s->pool_in_use + 4 * s4::kBlock * (items + n) > s->cfg.pool_bytes) return false;
@@ -470,7 +486,13 @@ void dispatcher(s4_server *s) {
         }
         // 2. waiting queries, oldest first
         while (!s->waiting.empty()) {
-          Query &q = s->waiting.front();
+          std::vector<Query> &batch = s->waiting.front();
+          if (s->waiting_pos == batch.size()) {
+            s->waiting.pop_front();
+            s->waiting_pos = 0;
+            continue;
+          }
+          Query &q = batch[s->waiting_pos];
           Slice sl;
           sl.c1 = std::min(q.items, s->slice);
           if (sl.c1 < q.items) {  // too long for one slice: a job
@@ -478,7 +500,7 @@ void dispatcher(s4_server *s) {
             probe.q = q;
             sl.job = &probe;
             if (!fits(sl.c1, q.k, sl.bound())) {
-              if (c.slices.empty()) ++s->st.waits_for_memory;
+              if (c.slices.empty()) ++memory_waits;
               break;
             }
             s->jobs.push_back(std::move(probe));
@@ -486,12 +508,12 @@ void dispatcher(s4_server *s) {
             sl.job = &j;
             j.next = sl.c1;
             j.outstanding = 1;
-            ++s->st.sliced_queries;
+            ++sliced;
           } else {
             // a whole query: its slice is built in place in the context
             // (one copy of the query, not two)
             if (!fits(sl.c1, q.k, q.bound)) {
-              if (c.slices.empty()) ++s->st.waits_for_memory;
+              if (c.slices.empty()) ++memory_waits;
               break;
             }
             c.slices.emplace_back();
@@ -501,14 +523,18 @@ void dispatcher(s4_server *s) {
             items += ns.c1;
             terms += q.k;
             bound += ns.bound();
-            s->waiting.pop_front();
+            ++s->waiting_pos;
             ++started;
             continue;
           }
-          s->waiting.pop_front();
+          ++s->waiting_pos;
           ++started;
           admit(std::move(sl));
         }
+        std::lock_guard<std::mutex> lock(s->mu);
+        s->queued -= started;
+        s->st.waits_for_memory += memory_waits;
+        s->st.sliced_queries += sliced;
         if (!c.slices.empty()) {
           c.items = items;
           c.terms = terms;
@@ -552,9 +578,9 @@ void dispatcher(s4_server *s) {
       s->st.launch_ns = launch_ns;
       for (Context &c : s->ctx) any_busy |= c.busy;
       const bool jobs_left = !s->jobs.empty();
-      if (s->stop && !any_busy && ((s->waiting.empty() && !jobs_left) || s->worker_error)) break;
+      if (s->stop && !any_busy && ((s->queued == 0 && !jobs_left) || s->worker_error)) break;
       idle = !progressed && !launched;
-      if (idle && !any_busy && s->waiting.empty() && !jobs_left) {
+      if (idle && !any_busy && s->queued == 0 && !jobs_left) {
         s->cv.wait_for(lock, std::chrono::milliseconds(1));
         continue;
       }
@@ -653,11 +679,13 @@ int s4_server_submit(s4_server *s, const uint32_t *terms, uint32_t k, uint64_t *
   }
   rc = check_open_locked(s);
   if (rc) return rc;
-  if (s->waiting.size() >= 64ull * s->cfg.max_slots) return fail(S4_EAGAIN, "waiting queue full");
+  if (s->queued >= 64ull * s->cfg.max_slots) return fail(S4_EAGAIN, "waiting queue full");
   q.id = s->next_id++;
   q.submitted = Clock::now();
   *id = q.id;
-  s->waiting.push_back(q);
+  if (s->incoming.empty() || s->incoming.back().size() >= 256) s->incoming.emplace_back();
+  s->incoming.back().push_back(q);
+  ++s->queued;
   ++s->st.submitted;
   s->cv.notify_one();
   return S4_OK;
@@ -774,7 +802,7 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
       std::lock_guard<std::mutex> lock(s->mu);
       int rc = check_open_locked(s);
       if (rc) return rc;
-      const uint64_t room = 64ull * s->cfg.max_slots - std::min<uint64_t>(s->waiting.size(), 64ull * s->cfg.max_slots);
+      const uint64_t room = 64ull * s->cfg.max_slots - std::min<uint64_t>(s->queued, 64ull * s->cfg.max_slots);
       const uint64_t take = std::min<uint64_t>(room, due.size());
       const auto now = Clock::now();
       if (take && id0 == UINT64_MAX) id0 = s->next_id;
@@ -785,15 +813,24 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
         const uint64_t slot = q.id - id0;
         if (slot >= q_of.size()) q_of.resize(slot + 1, UINT64_MAX);
         q_of[slot] = next + i;
-        s->waiting.push_back(q);
       }
+      // the batch goes to the server whole (moved, not copied, when all of
+      // `due` is taken)
+      if (take == due.size()) {
+        if (take) s->incoming.push_back(std::move(due));
+        due = std::vector<Query>();
+        due.reserve(kSubmitBatch);
+      } else if (take) {
+        s->incoming.emplace_back(due.begin(), due.begin() + std::ptrdiff_t(take));
+        due.erase(due.begin(), due.begin() + std::ptrdiff_t(take));
+      }
+      s->queued += take;
       s->st.submitted += take;
       next += take;
       if (take) s->cv.notify_one();
       got.swap(s->completed);
       got_jobs.swap(s->completed_jobs);
     }
-    due.erase(due.begin(), due.begin() + std::ptrdiff_t(std::min<uint64_t>(due.size(), next + due.size() - prepared)));
     // completions, outside the lock
     auto finish = [&](uint64_t id, uint64_t count, Clock::time_point at) -> uint64_t {
       if (id0 == UINT64_MAX || id < id0 || id - id0 >= q_of.size() || q_of[id - id0] == UINT64_MAX) return UINT64_MAX;
