@@ -340,10 +340,13 @@ int enqueue_serve_dev(const BatchDev &d, uint32_t *out, uint64_t out_cap, uint64
 }
 
 // Enqueue one run of a batch described by d on st.
-int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st) {
+int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st,
+                      bool begin) {
   const s4_tuning t = tuning();
-  const uint32_t begin_groups = std::max<uint32_t>(1, std::min<uint32_t>(1024, (d.nq + 255) / 256));
-  hipLaunchKernelGGL(k_batch_begin, dim3(begin_groups), dim3(256), 0, st, d);
+  if (begin) {
+    const uint32_t begin_groups = std::max<uint32_t>(1, std::min<uint32_t>(1024, (d.nq + 255) / 256));
+    hipLaunchKernelGGL(k_batch_begin, dim3(begin_groups), dim3(256), 0, st, d);
+  }
   if (d.items) {
     switch (t.waves_per_group) {
       case 1: launch_chunks_w<1>(d, t, st); break;

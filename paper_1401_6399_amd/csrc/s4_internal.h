@@ -202,7 +202,10 @@ struct BatchDev {
 };
 // Enqueue one run of a batch on st: persistent chunk kernel, scan,
 // compaction into d_results, per-query counts / CSR offsets.
-int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st);
+// begin = false: the caller's upload has reset the work queue and nothing
+// reads the per-query completion stamps, so the reset kernel is skipped
+int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, uint32_t *d_results, hipStream_t st,
+                      bool begin = true);
 // Enqueue one single-pass run on st: the persistent chunk kernel alone,
 // each chunk taking its output offset from a decoupled look-back over the
 // scan words d.state (tagged with d.epoch, so they need no clearing between

@@ -295,9 +295,11 @@ int launch_context(s4_server *s, Context &c) {
     S4_HIP(hipMemcpyAsync(c.d_tab, c.h_tab, records_at(c.terms, nq) + 16 * items, hipMemcpyHostToDevice,
                           c.stream));
     uint32_t *out = c.direct ? c.d_hresults : c.d_results;
+    // the staged form without its reset kernel: the table upload above
+    // zeroed the work queue, and the server reads no completion stamps
     int rc = c.single ? s4::enqueue_serve_dev(d, out, c.direct ? s->results_per_ctx : s4::kBlock * items,
                                               c.d_offs, c.stream)
-                      : s4::enqueue_batch_dev(d, c.d_counts, c.d_offs, out, c.stream);
+                      : s4::enqueue_batch_dev(d, c.d_counts, c.d_offs, out, c.stream, false);
     if (rc) return rc;
   }
   S4_HIP(hipEventRecord(c.done, c.stream));
