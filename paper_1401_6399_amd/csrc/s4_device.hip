@@ -573,20 +573,31 @@ __global__ __launch_bounds__(256) void k_scan_top(uint32_t *__restrict__ tile_su
   if (threadIdx.x == 0) *total = carry_s;
 }
 
-// Ordered gather of every chunk's matches into out[] (one wave per chunk).
+// Ordered gather of every chunk's matches into out[]: a wave per 64
+// chunks, each lane reading one chunk's count; the wave then copies the
+// chunks that have matches, one after another (most chunks of a batch
+// have none, so a wave per chunk would mostly start and stop).
 __global__ __launch_bounds__(256) void k_compact(const uint32_t *__restrict__ stage,
                                                  const uint32_t *__restrict__ counts,
                                                  const uint32_t *__restrict__ excl,
                                                  const uint32_t *__restrict__ tile_sums, uint32_t n,
                                                  uint32_t *__restrict__ out) {
   const uint32_t lane = lane_id();
-  const uint32_t item = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (item >= n) return;
-  const uint32_t cnt = counts[item];
-  const uint64_t off = uint64_t(excl[item]) + tile_sums[item >> 10];
-  const uint32_t *src = stage + uint64_t(item) * kBlock;
-  if (lane < cnt) out[off + lane] = src[lane];
-  if (lane + 64 < cnt) out[off + 64 + lane] = src[lane + 64];
+  const uint32_t base = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u;
+  if (base >= n) return;
+  const uint32_t item = base + lane;
+  const uint32_t cnt = item < n ? counts[item] : 0u;
+  uint64_t off = 0;
+  if (cnt) off = uint64_t(excl[item]) + tile_sums[item >> 10];
+  for (uint64_t m = __ballot(cnt != 0); m; m &= m - 1) {
+    const int l = __builtin_ctzll(m);
+    const uint32_t c = uint32_t(__builtin_amdgcn_readlane(int(cnt), l));
+    const uint64_t o = uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(off)), l))) |
+                       (uint64_t(uint32_t(__builtin_amdgcn_readlane(int(uint32_t(off >> 32)), l))) << 32);
+    const uint32_t *src = stage + uint64_t(base + uint32_t(l)) * kBlock;
+    if (lane < c) out[o + lane] = src[lane];
+    if (lane + 64 < c) out[o + 64 + lane] = src[lane + 64];
+  }
 }
 
 __global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
@@ -833,7 +844,7 @@ int scan_and_compact(const uint32_t *stage, const uint32_t *counts, uint32_t n, 
                      uint32_t ntiles, uint64_t *total, uint32_t *out, hipStream_t stream) {
   hipLaunchKernelGGL(k_scan_tiles, dim3(std::max<uint32_t>(1, ntiles)), dim3(256), 0, stream, counts, n, excl, tiles);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, stream, tiles, ntiles, total);
-  if (n) hipLaunchKernelGGL(k_compact, dim3((n + 3) / 4), dim3(256), 0, stream, stage, counts, excl, tiles, n, out);
+  if (n) hipLaunchKernelGGL(k_compact, dim3((n + 255) / 256), dim3(256), 0, stream, stage, counts, excl, tiles, n, out);
   S4_HIP(hipGetLastError());
   return S4_OK;
 }
