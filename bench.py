@@ -552,6 +552,9 @@ def serving_leg(s4, workloads, torch, args):
     import oracle
     from concurrent.futures import ThreadPoolExecutor
 
+    # the server's iterations launch with the library's default tuning, not
+    # with whatever the batch legs' autotuning last set
+    s4.set_tuning(**args.default_tuning)
     t0 = time.time()
     nl = args.serve_lists
     lens = workloads.index_lengths(nl, 28 - (20 - nl.bit_length() + 1))
@@ -647,6 +650,7 @@ def serving_leg(s4, workloads, torch, args):
                                  "of a burst (every query of a trace submitted at once); the levels are fractions "
                                  "of Q*"},
            "levels": levels,
+           "tuning": s4.get_tuning().as_dict(),
            "index": {"payload_gib": round(ix.payload_bytes / 2**30, 3),
                      "skip_index_gib": round(ix.index_bytes / 2**30, 3),
                      "bits_per_int": round(8 * ix.payload_bytes / ix.total_ints, 3), "build_s": round(build_s, 1)},
@@ -662,6 +666,7 @@ def serving(args):
     import paper_1401_6399_amd as s4
 
     s4.require_library()
+    args.default_tuning = s4.get_tuning().as_dict()
     torch.cuda.set_device(0)
     res = serving_leg(s4, workloads, torch, args)
     print(json.dumps({"metric": "served queries/s + p50/p99/p999 latency", "n_gpus": 1, "data": "synthetic",
@@ -796,6 +801,7 @@ def main():
     import paper_1401_6399_amd as s4
 
     s4.require_library()
+    args.default_tuning = s4.get_tuning().as_dict()  # before any autotuning
     torch.cuda.set_device(0)
     if args.batched_only:
         print(json.dumps({"batched": batched(s4, workloads, torch, args.batch_queries, args.plain_sample,
