@@ -249,3 +249,44 @@ def test_full_size_serving_sampled(gpu):
         w = oracle.intersect_k([flat[int(offs[t]): int(offs[t + 1])] for t in ts])
         got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
         assert np.array_equal(got, w), q
+
+
+def test_concurrent_submitters(gpu, served):
+    """Four threads submit at once (their queries reach the dispatcher in
+    batches taken under the server lock) while the main thread drains:
+    every id is distinct, every result equals the oracle's, and nothing is
+    lost or admitted twice."""
+    import threading
+    ix, flat, offs = served
+    terms, qoffs = workloads.queries(23, ix.lengths, 2000, 1, 8)
+    srv = gpu.Server(ix, max_slots=512, pool_bytes=64 << 20, result_bytes=32 << 20)
+    ids = {}
+    lock = threading.Lock()
+    errors = []
+
+    def submitter(part):
+        try:
+            for q in range(part, 2000, 4):
+                ts = terms[int(qoffs[q]): int(qoffs[q + 1])]
+                qid = srv.submit(ts)
+                with lock:
+                    ids[qid] = ts
+        except Exception as ex:  # surfaced below
+            errors.append(ex)
+
+    try:
+        threads = [threading.Thread(target=submitter, args=(p,)) for p in range(4)]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join(timeout=60)
+        assert not errors, errors
+        assert len(ids) == 2000
+        got = drain(srv, ids)
+        assert set(got) == set(ids)
+        for qid, ts in ids.items():
+            assert np.array_equal(got[qid][0], want(flat, offs, ts)), ts
+        st = srv.stats()
+        assert st["submitted"] == 2000 and st["admitted"] == 2000 and st["completed"] == 2000
+    finally:
+        srv.close()
