@@ -45,6 +45,7 @@
 #include <deque>
 #include <list>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -745,6 +746,93 @@ int s4_server_stats_get(const s4_server *s, s4_server_stats *st) {
 
 // Replay submission batching (see s4_server_replay).
 constexpr size_t kSubmitBatch = 256;
+
+// Queries of a replayed trace are validated and put in chain order ahead
+// of their arrival, by helper threads, a segment of kPrepSegment queries
+// at a time into a ring of kPrepRing segments (the work each client does
+// before it submits, done in parallel, so that one replay thread can offer
+// the server more than one thread's worth of clients).
+constexpr uint64_t kPrepSegment = 4096;
+constexpr uint64_t kPrepRing = 16;
+constexpr unsigned kPrepThreads = 3;
+
+struct PrepSegment {
+  std::vector<Query> q;
+  std::atomic<int> ready{0};  // 1 once prepared (release), 0 once consumed
+  int rc = S4_OK;             // first failure in the segment, at query bad
+  uint64_t bad = 0;
+  std::string msg;
+};
+
+struct Preparer {
+  const s4_server *s;
+  const uint32_t *terms;
+  const uint64_t *qoffs;
+  uint64_t nq, nseg;
+  std::vector<PrepSegment> ring;
+  std::atomic<uint64_t> claimed{0}, consumed{0};  // segments claimed by helpers / consumed by the replay
+  std::atomic<bool> stop{false};
+  std::vector<std::thread> helpers;
+
+  Preparer(const s4_server *srv, const uint32_t *t, const uint64_t *o, uint64_t n)
+      : s(srv), terms(t), qoffs(o), nq(n), nseg((n + kPrepSegment - 1) / kPrepSegment), ring(kPrepRing) {
+    for (auto &g : ring) g.q.resize(kPrepSegment);
+    const unsigned nh = unsigned(std::min<uint64_t>(kPrepThreads, std::max<uint64_t>(1, nseg)));
+    for (unsigned h = 0; h < nh; ++h) helpers.emplace_back([this] { run(); });
+  }
+  ~Preparer() {
+    stop.store(true);
+    for (auto &t : helpers) t.join();
+  }
+  void run() {
+    for (;;) {
+      const uint64_t seg = claimed.fetch_add(1);
+      if (seg >= nseg) return;
+      // the ring slot is free once the segment kPrepRing before is consumed
+      while (seg >= consumed.load(std::memory_order_acquire) + kPrepRing) {
+        if (stop.load()) return;
+        std::this_thread::yield();
+      }
+      PrepSegment &g = ring[seg % kPrepRing];
+      g.rc = S4_OK;
+      const uint64_t q0 = seg * kPrepSegment, q1 = std::min(nq, q0 + kPrepSegment);
+      for (uint64_t q = q0; q < q1; ++q) {
+        const int rc = prepare_query(s, terms + qoffs[q], uint32_t(qoffs[q + 1] - qoffs[q]), &g.q[q - q0]);
+        if (rc) {
+          g.rc = rc;
+          g.bad = q;
+          g.msg = s4_last_error();
+          break;
+        }
+      }
+      g.ready.store(1, std::memory_order_release);
+    }
+  }
+  // query q, prepared (waits for its segment; false on the stop flag or
+  // the time limit); rc / msg set when the segment failed at or before q
+  const Query *get(uint64_t q, Clock::time_point t0, double timeout_s, int *rc, std::string *msg) {
+    PrepSegment &g = ring[(q / kPrepSegment) % kPrepRing];
+    while (!g.ready.load(std::memory_order_acquire))
+      if (std::chrono::duration<double>(Clock::now() - t0).count() > timeout_s) {
+        *rc = S4_ERANGE;
+        *msg = "replay timed out";
+        return nullptr;
+      }
+    if (g.rc && g.bad <= q) {
+      *rc = g.rc;
+      *msg = g.msg;
+      return nullptr;
+    }
+    return &g.q[q % kPrepSegment];
+  }
+  // query q was the last of its segment (or of the trace): the slot is free
+  void release(uint64_t q) {
+    if ((q + 1) % kPrepSegment == 0 || q + 1 == nq) {
+      ring[(q / kPrepSegment) % kPrepRing].ready.store(0, std::memory_order_relaxed);
+      consumed.fetch_add(1, std::memory_order_release);
+    }
+  }
+};
 constexpr uint64_t kSubmitWaitNs = 10000;
 
 int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_offsets, uint64_t nq,
@@ -775,20 +863,23 @@ int s4_server_replay(s4_server *s, const uint32_t *h_terms, const uint64_t *h_q_
   uint64_t last_done_ns = 0, last_drain_ns = 0;
   // queries [next, prepared) are validated and wait in `due` to be queued
   uint64_t prepared = 0;
+  Preparer prep(s, h_terms, h_q_offsets, nq);
   while (ndone < nq) {
-    // every query due by now, validated without the lock
+    // every query due by now (prepared ahead by the helpers)
     const uint64_t t = now_ns();
     for (; prepared < nq && h_arrival_ns[prepared] <= t && due.size() < 8192; ++prepared) {
-      const uint64_t a = h_q_offsets[prepared], b = h_q_offsets[prepared + 1];
-      due.emplace_back();
-      int rc = prepare_query(s, h_terms + a, uint32_t(b - a), &due.back());
-      if (rc) {
-        if (rc == S4_ERANGE) {
+      int rc = S4_OK;
+      std::string msg;
+      const Query *pq = prep.get(prepared, t0, timeout_s, &rc, &msg);
+      if (!pq) {
+        if (rc == S4_ERANGE && msg != "replay timed out") {
           std::lock_guard<std::mutex> lock(s->mu);
           ++s->st.rejected;
         }
-        return rc;
+        return fail(rc, msg);
       }
+      due.push_back(*pq);
+      prep.release(prepared);
     }
     // queued under one lock per batch: at least kSubmitBatch queries, or
     // the oldest has waited kSubmitWaitNs, or no more will arrive (taking

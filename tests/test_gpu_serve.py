@@ -290,3 +290,26 @@ def test_concurrent_submitters(gpu, served):
         assert st["submitted"] == 2000 and st["admitted"] == 2000 and st["completed"] == 2000
     finally:
         srv.close()
+
+
+def test_replay_rejects_bad_query_then_serves(gpu, served):
+    """A replayed trace whose query 5000 names a term outside the index (in
+    the second segment the replay prepares ahead) fails with EINVAL and the
+    query's message; the server then serves the next trace normally."""
+    ix, flat, offs = served
+    terms, qoffs = workloads.queries(29, ix.lengths, 6000, 1, 8)
+    terms = np.array(terms, dtype=np.uint32)
+    terms[int(qoffs[5000])] = ix.count + 7
+    srv = gpu.Server(ix, max_slots=512, pool_bytes=64 << 20, result_bytes=32 << 20)
+    try:
+        with pytest.raises(gpu.S4Error) as e:
+            srv.replay(terms, qoffs, np.zeros(6000, np.uint64))
+        assert e.value.code == gpu.EINVAL and "term out of range" in str(e.value)
+        terms2, qoffs2 = workloads.queries(31, ix.lengths, 3000, 1, 8)
+        r = srv.replay(terms2, qoffs2, np.zeros(3000, np.uint64), with_results=True, results_cap=1 << 24)
+        for q in range(0, 3000, 7):
+            ts = terms2[int(qoffs2[q]): int(qoffs2[q + 1])]
+            got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
+            assert np.array_equal(got, want(flat, offs, ts)), ts
+    finally:
+        srv.close()
