@@ -516,7 +516,7 @@ int s4_plain_replay(const s4_index *index, const uint32_t *h_terms, const uint64
  *
  * Continuous-batching query server over a device-resident index (each
  * query a conjunction whose lists are intersected as in Sec. 6, shortest
- * list first).  A dispatcher thread owns three iteration contexts, each
+ * list first).  A dispatcher thread owns four iteration contexts, each
  * with its own HIP stream and buffers allocated at creation.  An iteration
  * admits waiting queries, oldest first, while the context's slots, the
  * reserved intermediate memory (the output-to-input bound: 512 bytes per
@@ -526,10 +526,10 @@ int s4_plain_replay(const s4_index *index, const uint32_t *h_terms, const uint64
  * with look-back offsets when the iteration has at most one 128-value
  * chunk per resident wave, else chunk kernel + scan + compaction), and
  * retires them.  Queries longer than slice_chunks chunks run a slice per
- * iteration (see s4_server_config), in at most two of the three contexts
- * at a time, so one context always stays free for short queries.
+ * iteration (see s4_server_config), in at most three of the four
+ * contexts at a time, so one context always stays free for short queries.
  * Queries that arrive while iterations run join the next free context, so
- * up to three iterations overlap on the device.  Submission never blocks
+ * up to four iterations overlap on the device.  Submission never blocks
  * on the GPU.
  */
 typedef struct s4_server s4_server;
