@@ -227,6 +227,87 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT
   }
 }
 
+// The staged form's tail for the server, in one launch: the chunks'
+// counts scanned in tiles of 1024 (a workgroup per tile, tiles numbered in
+// the order workgroups start, offsets across tiles by the decoupled
+// look-back of the single-pass kernel), every chunk's matches gathered to
+// their final place (a wave per 256 chunks, copying only those with
+// matches), and the CSR offset of every entry whose first chunk lies in
+// the tile (the last tile closes the table).  It replaces the tile scan,
+// the scan of tile totals, the gather and the per-entry pass, which in a
+// server iteration each waited for compute units behind the other
+// contexts' chunk kernels.  b.head[1] is the tile ticket (zeroed by the
+// table upload); b.state holds one scan word per tile.
+__global__ __launch_bounds__(256) void k_stage_tail(BatchDev b, uint32_t *__restrict__ out,
+                                                     uint64_t *__restrict__ offs) {
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t excl_s[1024];
+  __shared__ uint32_t tile_s, prefix_s, first_s;
+  const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) tile_s = atomicAdd(b.head + 1, 1u);
+  __syncthreads();
+  const uint32_t tile = tile_s;
+  const uint32_t t0 = tile * 1024u, t1 = min(t0 + 1024u, b.items);
+  uint32_t v[4], ex[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t item = t0 + 4u * threadIdx.x + uint32_t(e);
+    v[e] = item < t1 ? b.counts[item] : 0u;
+  }
+  const uint32_t local = v[0] + v[1] + v[2] + v[3];
+  const uint32_t inc = scan_wave64(local);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t run = inc - local;
+  for (uint32_t q = 0; q < w; ++q) run += wsum[q];
+  const uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    ex[e] = run;
+    excl_s[4u * threadIdx.x + uint32_t(e)] = run;
+    run += v[e];
+  }
+  // the tile's offset: wave 0 looks back; thread 0 finds the first entry
+  // that starts at or after the tile
+  if (w == 0) {
+    bool ok = true;
+    const uint32_t e = lookback(b.state, tile, b.epoch, total, b.err, ok);
+    if (lane == 0) prefix_s = ok ? e : 0u;
+  } else if (threadIdx.x == 64) {
+    uint32_t lo = 0, hi = b.nq + 1;  // over item_base[0 .. nq]
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (b.item_base[mid] < t0) lo = mid + 1;
+      else hi = mid;
+    }
+    first_s = lo;
+  }
+  __syncthreads();
+  const uint32_t P = prefix_s;
+  // each wave gathers its 256 chunks' matches, chunk by chunk
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    for (uint64_t m = __ballot(v[e] != 0); m; m &= m - 1) {
+      const int l = __builtin_ctzll(m);
+      const uint32_t c = uint32_t(__builtin_amdgcn_readlane(int(v[e]), l));
+      const uint64_t o = uint64_t(P) + uint32_t(__builtin_amdgcn_readlane(int(ex[e]), l));
+      const uint32_t item = t0 + 4u * (w * 64u + uint32_t(l)) + uint32_t(e);
+      const uint32_t *src = b.stage + uint64_t(item) * kBlock;
+      if (lane < c) out[o + lane] = src[lane];
+      if (lane + 64 < c) out[o + 64 + lane] = src[lane + 64];
+    }
+  }
+  // offsets of the entries that start in the tile; the last tile also
+  // writes those that start after the last chunk (no chunks) and the end
+  const bool last = t1 == b.items;
+  for (uint32_t q = first_s + threadIdx.x; q <= b.nq; q += 256) {
+    const uint32_t f = b.item_base[q];
+    if (f < t1) offs[q] = uint64_t(P) + excl_s[f - t0];
+    else if (last) offs[q] = uint64_t(P) + total;
+    else break;
+  }
+}
+
 // Per-query counts and CSR offsets from the global exclusive scan.
 __global__ void k_batch_finish(BatchDev b, uint64_t *__restrict__ d_counts, uint64_t *__restrict__ d_offs) {
   const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
@@ -335,6 +416,23 @@ int enqueue_serve_dev(const BatchDev &d, uint32_t *out, uint64_t out_cap, uint64
     case 8: launch_serve_w<8>(d, t, out, out_cap, d_offs, st); break;
     default: launch_serve_w<4>(d, t, out, out_cap, d_offs, st); break;
   }
+  S4_HIP(hipGetLastError());
+  return S4_OK;
+}
+
+// The server's staged iteration: chunk kernel, then k_stage_tail (needs
+// d.state, d.err and an epoch, as the single-pass form).
+int enqueue_staged_serve_dev(const BatchDev &d, uint32_t *out, uint64_t *d_offs, hipStream_t st) {
+  if (!d.items || !d.state || !d.err || d.epoch == 0 || d.epoch > kMaxEpoch)
+    return fail(S4_EINVAL, "staged server run: needs chunks, scan words and an epoch in 1 .. 2^30 - 1");
+  const s4_tuning t = tuning();
+  switch (t.waves_per_group) {
+    case 1: launch_chunks_w<1>(d, t, st); break;
+    case 2: launch_chunks_w<2>(d, t, st); break;
+    case 8: launch_chunks_w<8>(d, t, st); break;
+    default: launch_chunks_w<4>(d, t, st); break;
+  }
+  hipLaunchKernelGGL(k_stage_tail, dim3(uint32_t((d.items + 1023) / 1024)), dim3(256), 0, st, d, out, d_offs);
   S4_HIP(hipGetLastError());
   return S4_OK;
 }

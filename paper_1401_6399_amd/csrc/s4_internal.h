@@ -212,6 +212,11 @@ int enqueue_batch_dev(const BatchDev &d, uint64_t *d_counts, uint64_t *d_offs, u
 // runs) and writing its survivors to their final place in out[out_cap].
 // d_offs[nq + 1] receives the CSR offsets.  *d.head must be 0.
 int enqueue_serve_dev(const BatchDev &d, uint32_t *out, uint64_t out_cap, uint64_t *d_offs, hipStream_t st);
+// The server's staged iteration in two launches: the chunk kernel, then
+// one kernel that scans the chunks' counts (look-back across tiles),
+// gathers their matches into out and writes the CSR offsets d_offs; needs
+// d.state, d.err and an epoch as enqueue_serve_dev.
+int enqueue_staged_serve_dev(const BatchDev &d, uint32_t *out, uint64_t *d_offs, hipStream_t st);
 constexpr uint32_t kMaxEpoch = (1u << 30) - 1;
 // Most chunks a single-pass run takes under the current tuning: one per
 // resident wave.  A chunk's count is known only when its chain is done, so

@@ -129,7 +129,6 @@ struct Context {
   uint8_t *h_tab = nullptr;  // pinned
   uint8_t *d_tab = nullptr;  // device
   uint64_t *state = nullptr;       // device, one scan word per chunk (single pass)
-  uint64_t *d_counts = nullptr;    // device, per-query counts (staged form; unused by the host)
   uint32_t epoch = 0;              // scan generation of the last launch
   uint32_t *h_results = nullptr;   // pinned, device-mapped, results_per_ctx values
   uint32_t *d_hresults = nullptr;  // device view of h_results
@@ -189,7 +188,6 @@ int alloc_context(s4_server *s, Context &c) {
   S4_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
   S4_HIP(hipEventCreateWithFlags(&c.done, hipEventDisableTiming));
   const uint64_t nq = s->slots_per_ctx, items = s->items_per_ctx, nt = s->terms_per_ctx;
-  const uint32_t ntiles = uint32_t((items + 1023) / 1024);
   const size_t tab = records_at(nt, nq) + 16 * items;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -198,14 +196,12 @@ int alloc_context(s4_server *s, Context &c) {
     return o;
   };
   const size_t o_tab = take(tab), o_state = take(8 * items), o_stage = take(4 * s4::kBlock * items),
-               o_counts = take(4 * items), o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)),
-               o_ctrl = take(64), o_qtick = take(8 * nq), o_qcounts = take(8 * nq),
+               o_counts = take(4 * items), o_ctrl = take(64), o_qtick = take(8 * nq),
                o_res = take(4 * s4::kBlock * items);
   if (hipMalloc(&c.dmem, off) != hipSuccess) return s4::fail(S4_ENOMEM, "server context: device allocation failed");
   char *m = static_cast<char *>(c.dmem);
   c.d_tab = reinterpret_cast<uint8_t *>(m + o_tab);
   c.state = reinterpret_cast<uint64_t *>(m + o_state);
-  c.d_counts = reinterpret_cast<uint64_t *>(m + o_qcounts);
   c.d_results = reinterpret_cast<uint32_t *>(m + o_res);
   S4_HIP(hipMemset(c.state, 0, 8 * items));  // no word carries a live epoch
   s4::BatchDev &d = c.dev;
@@ -216,8 +212,8 @@ int alloc_context(s4_server *s, Context &c) {
   d.state = c.state;
   d.stage = reinterpret_cast<uint32_t *>(m + o_stage);
   d.counts = reinterpret_cast<uint32_t *>(m + o_counts);
-  d.excl = reinterpret_cast<uint32_t *>(m + o_excl);
-  d.tiles = reinterpret_cast<uint32_t *>(m + o_tiles);
+  d.excl = nullptr;  // the staged tail scans in place of the tile scans
+  d.tiles = nullptr;
   d.total = reinterpret_cast<uint64_t *>(m + o_ctrl + 8);
   d.start = reinterpret_cast<uint64_t *>(m + o_ctrl + 16);
   d.stats = reinterpret_cast<uint64_t *>(m + o_ctrl + 24);
@@ -286,24 +282,23 @@ int launch_context(s4_server *s, Context &c) {
     d.item_info = reinterpret_cast<const uint4 *>(c.d_tab + records_at(c.terms, nq));
     d.items = uint32_t(items);
     d.nq = uint32_t(nq);
-    d.ntiles = uint32_t((items + 1023) / 1024);
     c.single = items <= s4::single_pass_max_items();
-    if (c.single) {
-      if (++c.epoch > s4::kMaxEpoch) {
-        c.epoch = 1;
-        S4_HIP(hipMemsetAsync(c.state, 0, 8 * s->items_per_ctx, c.stream));
-      }
-      d.epoch = c.epoch;
+    // both forms place results by look-back over epoch-tagged scan words
+    if (++c.epoch > s4::kMaxEpoch) {
+      c.epoch = 1;
+      S4_HIP(hipMemsetAsync(c.state, 0, 8 * s->items_per_ctx, c.stream));
     }
+    d.epoch = c.epoch;
     *c.h_err = 0;
     S4_HIP(hipMemcpyAsync(c.d_tab, c.h_tab, records_at(c.terms, nq) + 16 * items, hipMemcpyHostToDevice,
                           c.stream));
     uint32_t *out = c.direct ? c.d_hresults : c.d_results;
-    // the staged form without its reset kernel: the table upload above
-    // zeroed the work queue, and the server reads no completion stamps
+    // the staged form: chunk kernel and one tail kernel (scan, gather,
+    // offsets); the table upload above zeroed the work queue and the tile
+    // ticket
     int rc = c.single ? s4::enqueue_serve_dev(d, out, c.direct ? s->results_per_ctx : s4::kBlock * items,
                                               c.d_offs, c.stream)
-                      : s4::enqueue_batch_dev(d, c.d_counts, c.d_offs, out, c.stream, false);
+                      : s4::enqueue_staged_serve_dev(d, out, c.d_offs, c.stream);
     if (rc) return rc;
   }
   S4_HIP(hipEventRecord(c.done, c.stream));
