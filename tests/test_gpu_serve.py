@@ -313,3 +313,42 @@ def test_replay_rejects_bad_query_then_serves(gpu, served):
             assert np.array_equal(got, want(flat, offs, ts)), ts
     finally:
         srv.close()
+
+
+def test_staged_iterations_with_chunkless_entries(gpu):
+    """Staged iterations whose entries include queries with no chunks (the
+    shortest term's list is empty): in the middle of an iteration, several
+    in a row, and at its end, where the last tile of the tail kernel writes
+    their offsets; entries straddle the tail's tiles of 1024 chunks.  Every
+    result equals the oracle's (empty where a term is empty)."""
+    lens = workloads.index_lengths(1 << 10, 17).copy()
+    lens[::9] = 0
+    kinds = np.full(lens.size, workloads.CLUSTERED, dtype=np.int32)
+    flat, offs = workloads.lists(kinds, lens, 778, 1 << 22)
+    buf, soffs = gpu.encode_many(flat, offs)
+    ix = gpu.Index(buf, soffs)
+    nq = 900
+    terms, qoffs = workloads.queries(24, lens, nq, 2, 6)
+    terms = terms.copy()
+    empties = np.nonzero(lens == 0)[0].astype(np.uint32)
+    rng = np.random.Generator(np.random.PCG64(24))
+    # every 7th query, a run of five, and the last four get an empty term
+    pick = set(range(0, nq, 7)) | set(range(400, 405)) | set(range(nq - 4, nq))
+    for q in pick:
+        terms[int(qoffs[q + 1]) - 1] = empties[rng.integers(empties.size)]
+    saved = gpu.get_tuning()
+    gpu.set_tuning(waves_per_group=1, groups_per_cu=1)
+    srv = gpu.Server(ix, max_slots=3 * 1024, pool_bytes=3 << 30, result_bytes=3 << 26)
+    try:
+        r = srv.replay(terms, qoffs, np.zeros(nq, np.uint64), with_results=True, results_cap=1 << 24)
+        for q in range(nq):
+            ts = terms[int(qoffs[q]): int(qoffs[q + 1])]
+            got = r["results"][int(r["res_offsets"][q]): int(r["res_offsets"][q + 1])]
+            assert np.array_equal(got, want(flat, offs, ts)), q
+            if q in pick:
+                assert got.size == 0, q
+        st = srv.stats()
+        assert st["single_pass_iterations"] < st["iterations"], st
+    finally:
+        srv.close()
+        gpu.set_tuning(**{k: getattr(saved, k) for k, _ in saved._fields_})
