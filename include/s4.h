@@ -524,7 +524,8 @@ int s4_plain_replay(const s4_index *index, const uint32_t *h_terms, const uint64
  * shortest list's length per query) fit, runs every admitted query to
  * completion in one persistent decode-fused launch (a single-pass kernel
  * with look-back offsets when the iteration has at most one 128-value
- * chunk per resident wave, else chunk kernel + scan + compaction), and
+ * chunk per resident wave, else the chunk kernel and one tail kernel that
+ * scans, compacts and writes the per-query offsets), and
  * retires them.  Queries longer than slice_chunks chunks run a slice per
  * iteration (see s4_server_config), in at most three of the four
  * contexts at a time, so one context always stays free for short queries.

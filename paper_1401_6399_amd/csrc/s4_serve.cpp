@@ -26,8 +26,10 @@
 //      queue), then, for an iteration of at most one chunk per resident
 //      wave, one single-pass persistent decode-fused chunk kernel whose
 //      chunks find their output offsets by decoupled look-back; a larger
-//      iteration runs the staged form (chunk kernel into per-chunk slots,
-//      scan, compaction), whose waves never wait on each other.
+//      iteration runs the staged form: the chunk kernel into per-chunk
+//      slots, whose waves never wait on each other, then one tail kernel
+//      that scans the chunk counts tile by tile (decoupled look-back between
+//      tiles), gathers the survivors and writes the per-query offsets.
 // Queries that arrive while earlier ones run on the device are admitted into
 // the next free context and launched at once, so iterations overlap on the
 // device.  Submitters queue queries in batches (a replay hands over its
