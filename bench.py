@@ -419,29 +419,63 @@ def hybrid(s4, workloads, torch, index, buf, soffs, nq, plain):
     average gap <= B held as bitmaps over [0, 2^26), B = 8, 16, 32; each
     index and workload autotuned on its own, replayed as a graph.
     Storage in bits/int counts packed payload + width bytes + tails +
-    bitmaps (skip index and select samples apart)."""
-    res = {"none": {"bitmap_lists": 0, "bits_per_int": round(8 * index.payload_bytes / index.total_ints, 3),
-                    **{f"{k}_qps": plain[k]["batched_qps"] for k in plain}}}
+    bitmaps (skip index and select samples apart).  Besides the sqrt(length)
+    queries, a second set draws terms with probability proportional to
+    length (2^14 pairs, 2^16 queries of 3..6 terms), so that the dense
+    lists, which the bitmaps replace, take part in many queries; each
+    index's counts are checked equal to the compressed index's."""
+    import numpy as np
+
+    def timed(ix, terms, qoffs):
+        b = s4.Batch(ix, terms, qoffs)
+        b.autotune(reps=2)
+        stream = torch.cuda.Stream()
+        ms, _ = time_graph(torch, lambda: b.run(use_graph=False), stream, steps=5, warmup=2)
+        abytes, _ = counted_traffic(b)
+        counts = b.counts[: b.nq].clone()
+        del b
+        return ms, abytes, counts
+
     queries = {"pairwise": workloads.pairwise_queries(index.lengths, nq),
                "multiterm": workloads.multiterm_queries(index.lengths, nq)}
+    dense = {"pairwise_by_length": workloads.length_weighted_queries(workloads.config_seed(2, 7), index.lengths,
+                                                                     1 << 14, 2, 2),
+             "multiterm_by_length": workloads.length_weighted_queries(workloads.config_seed(3, 7), index.lengths,
+                                                                      1 << 16, 3, 6)}
+    base = {}
+    res = {"none": {"bitmap_lists": 0, "bits_per_int": round(8 * index.payload_bytes / index.total_ints, 3),
+                    **{f"{k}_qps": plain[k]["batched_qps"] for k in plain}}}
+    for name, (terms, qoffs) in dense.items():
+        ms, abytes, counts = timed(index, terms, qoffs)
+        base[name] = (ms, counts)
+        nqd = int(qoffs.size - 1)
+        res["none"][f"{name}_queries"] = nqd
+        res["none"][f"{name}_qps"] = round(nqd / (ms / 1e3), 1)
+        res["none"][f"{name}_ms"] = round(ms, 3)
+        res["none"][f"{name}_algorithmic_mb"] = round(abytes / 1e6, 2)
+    log(f"hyb+m2 none: {res['none']}")
     for gap in (8, 16, 32):
         hx = s4.Index(buf, soffs, universe=1 << 26, bitmap_gap=gap)
         row = {"bitmap_lists": hx.bitmap_lists, "bitmap_mib": round(hx.bitmap_bytes / 2**20, 1),
                "bits_per_int": round(8 * hx.payload_bytes / hx.total_ints, 3)}
-        for name, (terms, qoffs) in queries.items():
-            b = s4.Batch(hx, terms, qoffs)
-            b.autotune(reps=2)
-            stream = torch.cuda.Stream()
-            ms, _ = time_graph(torch, lambda: b.run(use_graph=False), stream, steps=5, warmup=2)
-            abytes, _ = counted_traffic(b)
-            row[f"{name}_qps"] = round(b.nq / (ms / 1e3), 1)
+        for name, (terms, qoffs) in {**queries, **dense}.items():
+            ms, abytes, counts = timed(hx, terms, qoffs)
+            ref_ms = plain[name]["batched_ms"] if name in plain else base[name][0]
+            row[f"{name}_qps"] = round(int(qoffs.size - 1) / (ms / 1e3), 1)
             row[f"{name}_ms"] = round(ms, 3)
             row[f"{name}_algorithmic_mb"] = round(abytes / 1e6, 2)
-            row[f"{name}_speedup_vs_no_bitmaps"] = round(plain[name]["batched_ms"] / ms, 3)
-            del b
+            row[f"{name}_speedup_vs_no_bitmaps"] = round(ref_ms / ms, 3)
+            if name in base:
+                row[f"{name}_counts_match_no_bitmaps"] = bool(torch.equal(counts, base[name][1]))
         res[f"B={gap}"] = row
         log(f"hyb+m2 B={gap}: {row}")
         hx.free()
+    frac = {}
+    for name, (terms, qoffs) in {**queries, **dense}.items():
+        lens = np.asarray(index.lengths, dtype=np.float64)
+        ql = np.maximum.reduceat(lens[terms], qoffs[:-1].astype(np.int64))
+        frac[name] = {f"B={g}": round(float(np.mean(ql * g >= float(1 << 26))), 4) for g in (8, 16, 32)}
+    res["queries_with_a_bitmap_list"] = frac
     return res
 
 

@@ -34,15 +34,20 @@ constexpr uint32_t kXcds = 8;
 // workgroup first drains the parts of its own XCD (part x mod P for fewer
 // than 8 parts, parts x, x + 8, ... otherwise), so each XCD's L2 holds one
 // part's lists, then helps every other queue.
-// The chunk kernels are latency-bound, so resident waves matter most: the
-// plain instantiation is held to 64 VGPRs (8 waves per SIMD, whose LDS,
-// 5 KB per wave, then just fills a CU) and the others to 80 (6 waves),
-// without spilling.  Work added to the per-chunk path that keeps more values
-// live (loading the next candidate group's block metadata during the
-// current group, decoding r's block while the first list is searched)
-// measured slower than the round trips it saved.
+// The chunk kernels are latency-bound, so resident waves matter most: an
+// instantiation is held to 64 VGPRs (8 waves per SIMD, whose LDS, 5 KB per
+// wave, then just fills a CU) where that spills nothing and pays, else to
+// 80 (6 waves): the traffic-counting ones and those for a partitioned index
+// (at 8 waves 3-6% slower on most of its batches); bitmap and patched lists
+// run at 8 (7-12% faster than at 6).  Work added to the per-chunk path that
+// keeps more values live (loading the next candidate group's block metadata
+// during the current group, decoding r's block while the first list is
+// searched) measured slower than the round trips it saved.
+constexpr int chunk_waves_per_simd(uint32_t feat) {
+  return (feat & (kFeatCount | kFeatParts)) ? 6 : 8;
+}
 template <int WAVES, uint32_t FEAT>
-__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(FEAT == 0 ? 8 : 6))) void k_batch_chunks(
+__global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(chunk_waves_per_simd(FEAT)))) void k_batch_chunks(
     BatchDev b, uint32_t grab, uint32_t gallop_blocks) {
   __shared__ ItemLds lds[WAVES];
   const uint32_t w = threadIdx.x >> 6;

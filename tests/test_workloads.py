@@ -4,6 +4,7 @@ output independent of the thread count."""
 import ctypes
 
 import numpy as np
+import pytest
 
 import workloads
 
@@ -51,3 +52,18 @@ def test_law():
     t2, _ = workloads.queries(12, lens, 1 << 19, 1, 1)
     got2 = np.bincount(t2, minlength=lens.size) / t2.size
     assert np.abs(got2 - got).max() < 0.002
+
+
+def test_length_weighted_law():
+    """length_weighted_queries: one-term draws follow P(t) = len / sum(len)
+    (chi-square over the terms), and lengths of 2^32 or more are refused."""
+    lens = workloads.index_lengths(1 << 8, 16)
+    t1, o1 = workloads.length_weighted_queries(13, lens, 1 << 19, 1, 1)
+    assert np.array_equal(o1, np.arange(o1.size, dtype=np.uint64))
+    p = lens.astype(np.float64) / float(lens.sum())
+    e = p * t1.size
+    got = np.bincount(t1, minlength=lens.size).astype(np.float64)
+    chi2 = float(((got - e) ** 2 / e).sum())
+    assert chi2 < 255 + 6 * np.sqrt(2 * 255)
+    with pytest.raises(ValueError):
+        workloads.length_weighted_queries(13, np.array([1 << 32, 5], dtype=np.uint64), 4, 1, 1)

@@ -190,6 +190,18 @@ def multiterm_queries(lens, nq: int = 1 << 18):
     return queries(config_seed(3, 1), lens, nq, 3, 6)
 
 
+def length_weighted_queries(seed: int, lens, nq: int, kmin: int, kmax: int):
+    """CSR query stream like queries(), with P(t) proportional to lens[t]
+    instead of its square root: a term drawn as the term of a random
+    posting, so the long (dense) lists that dominate real query logs come
+    up often.  queries() weighs by the square root of what it is given, so
+    it is given the squared lengths."""
+    lv = np.ascontiguousarray(lens, dtype=np.uint64)
+    if lv.size and int(lv.max()) >= 1 << 32:
+        raise ValueError("lengths must be below 2^32")
+    return queries(seed, lv * lv, nq, kmin, kmax)
+
+
 def serving_queries(lens, nq: int, level: int = 0):
     return queries(config_seed(4, 10 + level), lens, nq, 2, 8)
 
