@@ -20,7 +20,8 @@ __global__ void k_batch_begin(BatchDev b) {
     b.stats[0] = 0;
     b.stats[1] = 0;
   }
-  for (uint32_t p = t; p < max(b.parts, 1u); p += gridDim.x * blockDim.x) b.head[p] = 0;
+  const uint32_t nheads = b.parts > 1 ? b.parts : kSubQueues;
+  for (uint32_t p = t; p < nheads; p += gridDim.x * blockDim.x) b.head[p * kHeadStride] = 0;
   for (uint32_t q = t; q < b.nq; q += gridDim.x * blockDim.x) b.qtick[q] = 0;
 }
 
@@ -50,8 +51,15 @@ template <int WAVES, uint32_t FEAT>
 __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(chunk_waves_per_simd(FEAT)))) void k_batch_chunks(
     BatchDev b, uint32_t grab, uint32_t gallop_blocks) {
   __shared__ ItemLds lds[WAVES];
+  // queues this workgroup has found empty (bit p, p < 32): its other waves
+  // skip them rather than fetch from an exhausted head once each.  The word
+  // is wave 0's last skip-index staging entry (the launch stages at most
+  // kMaxGallopBlocks - 1), so the workgroup's LDS stays 5 KB per wave.
+  uint32_t *const empty_q = &lds[0].bm[kMaxGallopBlocks - 1];
   const uint32_t w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
+  if (threadIdx.x == 0) *empty_q = 0;
+  __syncthreads();
   const uint64_t t0 = *b.start;
   // counting is an instantiation of its own: the timed kernels carry no
   // counters (they cost the chunk pipeline registers and issue slots)
@@ -65,11 +73,16 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(chun
   uint32_t hint = 0, h_id0 = kInvalid, h_id1 = kInvalid, h_local = kInvalid;
   // drain queue p: chunks base .. base + size in queue order
   auto drain = [&](uint32_t p, uint32_t base, uint32_t size) {
+    const uint32_t pbit = p < 32 ? 1u << p : 0u;
     for (;;) {
+      if (uniform(*(volatile uint32_t *)empty_q) & pbit) break;
       uint32_t it0 = 0;
-      if (lane == 0) it0 = atomicAdd(b.head + p, grab);
+      if (lane == 0) it0 = atomicAdd(b.head + p * kHeadStride, grab);
       it0 = uniform(it0);  // lane 0's value: every lane is active here
-      if (it0 >= size) break;
+      if (it0 >= size) {
+        if (lane == 0) atomicOr(empty_q, pbit);
+        break;
+      }
       const uint32_t it1 = min(it0 + grab, size);
       for (uint32_t rel = it0; rel < it1; ++rel) {
         const uint32_t item = base + rel;
@@ -106,7 +119,16 @@ __global__ __launch_bounds__(WAVES * 64) __attribute__((amdgpu_waves_per_eu(chun
     }
   };
   if (!(FEAT & kFeatParts)) {
-    drain(0, 0, b.items);
+    // kSubQueues contiguous slices of the chunks: a workgroup drains its
+    // own XCD's slice first (a query's chunks stay together, and so its
+    // lists in that XCD's L2), then helps the others in turn
+    const uint32_t x = blockIdx.x % kSubQueues;
+    for (uint32_t v = 0; v < kSubQueues; ++v) {
+      const uint32_t p = (x + v) % kSubQueues;
+      const uint32_t lo = uint32_t(uint64_t(b.items) * p / kSubQueues);
+      const uint32_t hi = uint32_t(uint64_t(b.items) * (p + 1) / kSubQueues);
+      drain(p, lo, hi - lo);
+    }
   } else {
     const uint32_t P = b.parts, x = blockIdx.x % kXcds;
     const uint32_t own = P >= kXcds ? (P - x + kXcds - 1) / kXcds : 1u;
@@ -358,7 +380,7 @@ static void launch_chunks(const BatchDev &d, const s4_tuning &t, hipStream_t st)
   uint32_t groups = uint32_t(cu_count()) * t.groups_per_cu;
   groups = std::max<uint32_t>(1, std::min<uint32_t>(groups, (d.items + per_group - 1) / per_group));
   hipLaunchKernelGGL((k_batch_chunks<W, F>), dim3(groups), dim3(W * 64), 0, st, d, grab,
-                     std::min(t.gallop_blocks, kMaxGallopBlocks));
+                     std::min(t.gallop_blocks, kMaxGallopBlocks - 1));
 }
 
 // The instantiation for the kinds of list the index holds (bitmap lists
@@ -851,7 +873,8 @@ int s4_batch_plan(const s4_index *ix, const uint32_t *h_terms, const uint64_t *h
   const size_t o_sterms = take(4 * nterms * P), o_qoff = take(4 * (nq + 1)), o_ib = take(4 * (nq + 1)),
                o_iq = take(16 * items), o_stage = take(4 * kBlock * items), o_counts = take(4 * items),
                o_excl = take(4 * items), o_tiles = take(4 * (ntiles + 1)), o_ctrl = take(64),
-               o_qtick = take(8 * nq), o_heads = take(4 * P), o_rank = take(4 * item_rank.size()),
+               o_qtick = take(8 * nq), o_heads = take(4 * kHeadStride * std::max<uint32_t>(P, kSubQueues)),
+               o_rank = take(4 * item_rank.size()),
                o_pbase = take(4 * part_base.size());
   s4_batch *bt = new (std::nothrow) s4_batch;
   if (!bt) return fail(S4_ENOMEM, "handle allocation failed");

@@ -18,6 +18,13 @@ constexpr uint32_t kHeaderBytes = 32;
 constexpr uint32_t kBlock = 128;          // integers per block (Sec. 4.3)
 constexpr uint32_t kPayloadPadBytes = 64; // lets extraction read 3 rows past any block
 constexpr uint32_t kMaxGallopBlocks = 512;
+// Chunk work queues: an unpartitioned batch splits its chunks into
+// kSubQueues contiguous slices (one per XCD), and every queue head sits
+// kHeadStride words (256 bytes) from the next: atomics on one word are
+// served one after another device-wide (about 11 ns each measured), so
+// thousands of waves fetching from one head wait on each other.
+constexpr uint32_t kSubQueues = 8;
+constexpr uint32_t kHeadStride = 64;
 constexpr uint32_t kMaxTerms = 32;  // lists after the shortest one in a conjunction
 constexpr uint32_t kPage = 512;     // blocks whose exceptions a patched stream pools
 constexpr uint16_t kFlagPatched = 8;  // stream flag bit 3: S4-FastPFOR
@@ -182,7 +189,8 @@ struct BatchDev {
   uint32_t *counts;           // [items]
   uint32_t *excl;             // [items]
   uint32_t *tiles;            // [ntiles + 1]
-  uint32_t *head;             // work-queue head (one per part)
+  uint32_t *head;             // work-queue heads, queue p at head[p * kHeadStride]: one per part, else
+                              // kSubQueues; head[1] is the staged tail's tile ticket
   uint64_t *total;            // number of results
   uint64_t *start;            // device clock at the start of the run
   uint64_t *qtick;            // [nq] completion time of each query

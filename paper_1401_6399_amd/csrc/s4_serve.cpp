@@ -126,8 +126,9 @@ struct Context {
   hipEvent_t done = nullptr;
   void *dmem = nullptr;
   s4::BatchDev dev{};
-  // query tables of one iteration, packed: queue head (zero), terms, first
-  // chunk of each query, chunk records (each part 16-byte aligned)
+  // query tables of one iteration, packed: the queue heads (zero; one per
+  // sub-queue, 256 bytes apart), terms, first chunk of each query, chunk
+  // records (each part 16-byte aligned)
   uint8_t *h_tab = nullptr;  // pinned
   uint8_t *d_tab = nullptr;  // device
   uint64_t *state = nullptr;       // device, one scan word per chunk (single pass)
@@ -182,8 +183,8 @@ struct s4_server {
 namespace {
 
 // byte offsets of the parts of a packed table
-size_t terms_at() { return 16; }
-size_t bases_at(uint64_t nt) { return 16 + s4::align_up(4 * nt, 16); }
+size_t terms_at() { return 4 * s4::kSubQueues * s4::kHeadStride; }
+size_t bases_at(uint64_t nt) { return terms_at() + s4::align_up(4 * nt, 16); }
 size_t records_at(uint64_t nt, uint64_t nq) { return bases_at(nt) + s4::align_up(4 * (nq + 1), 16); }
 
 int alloc_context(s4_server *s, Context &c) {
@@ -254,7 +255,7 @@ int launch_context(s4_server *s, Context &c) {
   uint32_t *sterms = reinterpret_cast<uint32_t *>(c.h_tab + terms_at());
   uint32_t *ib = reinterpret_cast<uint32_t *>(c.h_tab + bases_at(c.terms));
   uint32_t *iq = reinterpret_cast<uint32_t *>(c.h_tab + records_at(c.terms, nq));
-  std::memset(head, 0, 16);
+  std::memset(head, 0, terms_at());
   uint64_t t = 0, it = 0;
   for (uint64_t q = 0; q < nq; ++q) {
     const Slice &sl = c.slices[q];
