@@ -447,6 +447,33 @@ int enqueue_serve_dev(const BatchDev &d, uint32_t *out, uint64_t out_cap, uint64
   return S4_OK;
 }
 
+// Chunk records from one entry per query: chunk i belongs to the entry q
+// with item_base[q] <= i < item_base[q + 1] (the largest q with
+// item_base[q] <= i, which passes over entries without chunks); its
+// record is {q, the entry's first chunk + i - item_base[q], first term,
+// terms}.
+__global__ __launch_bounds__(256) void k_expand_items(BatchDev b, const uint4 *__restrict__ qinfo,
+                                                      uint4 *__restrict__ records) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= b.items) return;
+  uint32_t lo = 0, hi = b.nq;  // item_base[lo] <= i < item_base[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (b.item_base[mid] <= i) lo = mid;
+    else hi = mid;
+  }
+  const uint4 e = qinfo[lo];
+  records[i] = make_uint4(lo, e.x + i - b.item_base[lo], e.y, e.z);
+}
+
+int enqueue_expand_items(const BatchDev &d, const uint4 *qinfo, uint4 *records, hipStream_t st) {
+  if (!d.items || !d.nq || !d.item_base || !qinfo || !records)
+    return fail(S4_EINVAL, "chunk records: needs chunks, entries and tables");
+  hipLaunchKernelGGL(k_expand_items, dim3((d.items + 255) / 256), dim3(256), 0, st, d, qinfo, records);
+  S4_HIP(hipGetLastError());
+  return S4_OK;
+}
+
 // The server's staged iteration: chunk kernel, then k_stage_tail (needs
 // d.state, d.err and an epoch, as the single-pass form).
 int enqueue_staged_serve_dev(const BatchDev &d, uint32_t *out, uint64_t *d_offs, hipStream_t st) {

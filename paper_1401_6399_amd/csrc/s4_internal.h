@@ -225,6 +225,10 @@ int enqueue_serve_dev(const BatchDev &d, uint32_t *out, uint64_t out_cap, uint64
 // gathers their matches into out and writes the CSR offsets d_offs; needs
 // d.state, d.err and an epoch as enqueue_serve_dev.
 int enqueue_staged_serve_dev(const BatchDev &d, uint32_t *out, uint64_t *d_offs, hipStream_t st);
+// The chunk records of d (records[items]) from one entry per query
+// (qinfo[q] = {first chunk of the entry within its query, first term,
+// terms, 0}) and d.item_base, written on st.
+int enqueue_expand_items(const BatchDev &d, const uint4 *qinfo, uint4 *records, hipStream_t st);
 constexpr uint32_t kMaxEpoch = (1u << 30) - 1;
 // Most chunks a single-pass run takes under the current tuning: one per
 // resident wave.  A chunk's count is known only when its chain is done, so

@@ -127,8 +127,9 @@ struct Context {
   void *dmem = nullptr;
   s4::BatchDev dev{};
   // query tables of one iteration, packed: the queue heads (zero; one per
-  // sub-queue, 256 bytes apart), terms, first chunk of each query, chunk
-  // records (each part 16-byte aligned)
+  // sub-queue, 256 bytes apart), terms, first chunk of each query, one
+  // 16-byte entry per query (uploaded), then the chunk records the device
+  // expands from them (each part 16-byte aligned)
   uint8_t *h_tab = nullptr;  // pinned
   uint8_t *d_tab = nullptr;  // device
   uint64_t *state = nullptr;       // device, one scan word per chunk (single pass)
@@ -185,7 +186,8 @@ namespace {
 // byte offsets of the parts of a packed table
 size_t terms_at() { return 4 * s4::kSubQueues * s4::kHeadStride; }
 size_t bases_at(uint64_t nt) { return terms_at() + s4::align_up(4 * nt, 16); }
-size_t records_at(uint64_t nt, uint64_t nq) { return bases_at(nt) + s4::align_up(4 * (nq + 1), 16); }
+size_t qinfo_at(uint64_t nt, uint64_t nq) { return bases_at(nt) + s4::align_up(4 * (nq + 1), 16); }
+size_t records_at(uint64_t nt, uint64_t nq) { return qinfo_at(nt, nq) + 16 * nq; }
 
 int alloc_context(s4_server *s, Context &c) {
   S4_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
@@ -254,24 +256,21 @@ int launch_context(s4_server *s, Context &c) {
   uint32_t *head = reinterpret_cast<uint32_t *>(c.h_tab);
   uint32_t *sterms = reinterpret_cast<uint32_t *>(c.h_tab + terms_at());
   uint32_t *ib = reinterpret_cast<uint32_t *>(c.h_tab + bases_at(c.terms));
-  uint32_t *iq = reinterpret_cast<uint32_t *>(c.h_tab + records_at(c.terms, nq));
+  uint32_t *qi = reinterpret_cast<uint32_t *>(c.h_tab + qinfo_at(c.terms, nq));
   std::memset(head, 0, terms_at());
   uint64_t t = 0, it = 0;
+  // one entry per query; the device expands them into chunk records
   for (uint64_t q = 0; q < nq; ++q) {
     const Slice &sl = c.slices[q];
     const Query &qq = sl.query();
     ib[q] = uint32_t(it);
     for (uint32_t j = 0; j < qq.k; ++j) sterms[t + j] = qq.terms[j];
-    const uint64_t n = sl.c1 - sl.c0;
-    for (uint64_t i = 0; i < n; ++i) {
-      uint32_t *rec = iq + 4 * (it + i);
-      rec[0] = uint32_t(q);
-      rec[1] = uint32_t(sl.c0 + i);
-      rec[2] = uint32_t(t);
-      rec[3] = qq.k;
-    }
+    qi[4 * q] = uint32_t(sl.c0);
+    qi[4 * q + 1] = uint32_t(t);
+    qi[4 * q + 2] = qq.k;
+    qi[4 * q + 3] = 0;
     t += qq.k;
-    it += n;
+    it += sl.c1 - sl.c0;
   }
   ib[nq] = uint32_t(it);
   c.direct = c.bound <= s->results_per_ctx;
@@ -293,15 +292,17 @@ int launch_context(s4_server *s, Context &c) {
     }
     d.epoch = c.epoch;
     *c.h_err = 0;
-    S4_HIP(hipMemcpyAsync(c.d_tab, c.h_tab, records_at(c.terms, nq) + 16 * items, hipMemcpyHostToDevice,
-                          c.stream));
+    S4_HIP(hipMemcpyAsync(c.d_tab, c.h_tab, records_at(c.terms, nq), hipMemcpyHostToDevice, c.stream));
+    int rc = s4::enqueue_expand_items(d, reinterpret_cast<const uint4 *>(c.d_tab + qinfo_at(c.terms, nq)),
+                                      reinterpret_cast<uint4 *>(c.d_tab + records_at(c.terms, nq)), c.stream);
+    if (rc) return rc;
     uint32_t *out = c.direct ? c.d_hresults : c.d_results;
     // the staged form: chunk kernel and one tail kernel (scan, gather,
     // offsets); the table upload above zeroed the work queue and the tile
     // ticket
-    int rc = c.single ? s4::enqueue_serve_dev(d, out, c.direct ? s->results_per_ctx : s4::kBlock * items,
-                                              c.d_offs, c.stream)
-                      : s4::enqueue_staged_serve_dev(d, out, c.d_offs, c.stream);
+    rc = c.single ? s4::enqueue_serve_dev(d, out, c.direct ? s->results_per_ctx : s4::kBlock * items, c.d_offs,
+                                          c.stream)
+                  : s4::enqueue_staged_serve_dev(d, out, c.d_offs, c.stream);
     if (rc) return rc;
   }
   S4_HIP(hipEventRecord(c.done, c.stream));
