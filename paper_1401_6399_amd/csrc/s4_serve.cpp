@@ -23,8 +23,9 @@
 //      joined by the consumer, off the dispatcher thread;
 //   3. launches the admitted queries as one batch on that context's stream:
 //      one upload of the packed query tables (which also resets the work
-//      queue), then, for an iteration of at most one chunk per resident
-//      wave, one single-pass persistent decode-fused chunk kernel whose
+//      queues; one entry per query), a kernel that expands the entries
+//      into chunk records, then, for an iteration of at most one chunk per
+//      resident wave, one single-pass persistent decode-fused chunk kernel whose
 //      chunks find their output offsets by decoupled look-back; a larger
 //      iteration runs the staged form: the chunk kernel into per-chunk
 //      slots, whose waves never wait on each other, then one tail kernel
