@@ -46,6 +46,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <list>
 #include <mutex>
 #include <string>
@@ -111,10 +112,10 @@ struct Job {
 
 // A query's share of one iteration: chunks [c0, c1) of its shortest list.
 struct Slice {
-  Query q;             // the whole query (job == nullptr)
-  Job *job = nullptr;  // or the job this slice belongs to
+  const Query *q = nullptr;  // the whole query, in a submitted batch the context holds (job == nullptr)
+  Job *job = nullptr;        // or the job this slice belongs to
   uint64_t c0 = 0, c1 = 0;
-  const Query &query() const { return job ? job->q : q; }
+  const Query &query() const { return job ? job->q : *q; }
   // values of the shortest list in the slice: the bound on its results
   uint64_t bound() const {
     const uint64_t m = query().bound;
@@ -141,6 +142,9 @@ struct Context {
   uint32_t *h_err = nullptr, *d_err = nullptr;    // pinned, device-mapped: scan failure flag
   uint32_t *d_results = nullptr;  // device, 128 values per chunk
   std::vector<Slice> slices;
+  // the submitted batches its whole-query slices point into, held until
+  // the iteration retires (a slice is a pointer, not a copy of the query)
+  std::vector<std::shared_ptr<const std::vector<Query>>> held;
   uint64_t items = 0, terms = 0, bound = 0;
   bool busy = false;
   bool has_job = false;  // holds a slice of a query run in slices
@@ -168,7 +172,7 @@ struct s4_server {
   // and admits from without the lock; `queued` counts both (under mu)
   std::deque<std::vector<Query>> incoming;
   uint64_t queued = 0;
-  std::deque<std::vector<Query>> waiting;  // dispatcher only
+  std::deque<std::shared_ptr<const std::vector<Query>>> waiting;  // dispatcher only
   size_t waiting_pos = 0;                  // first query of waiting.front() not admitted
   std::deque<DoneBatch> completed;     // whole queries, per iteration
   std::deque<DoneJob> completed_jobs;  // queries run in slices
@@ -357,8 +361,8 @@ void retire_context(s4_server *s, Context &c, const uint32_t *res) {
   for (size_t i = 0; i < n; ++i) {
     Slice &sl = c.slices[i];
     if (!sl.job) {
-      bt.ids.push_back(sl.q.id);
-      bt.latency_ns.push_back(ns_between(sl.q.submitted, now));
+      bt.ids.push_back(sl.q->id);
+      bt.latency_ns.push_back(ns_between(sl.q->submitted, now));
       bt.offs.push_back(bt.offs.back() + (c.h_offs[i + 1] - c.h_offs[i]));
       continue;
     }
@@ -401,6 +405,7 @@ void retire_context(s4_server *s, Context &c, const uint32_t *res) {
   s->active -= finished;
   s->pool_in_use -= c.reserved_stage;
   c.slices.clear();
+  c.held.clear();
   c.reserved_stage = 0;
   c.has_job = false;
   c.busy = false;
@@ -452,7 +457,7 @@ void dispatcher(s4_server *s) {
           // every batch submitted so far, moved (not copied) under the lock
           std::lock_guard<std::mutex> lock(s->mu);
           while (!s->incoming.empty()) {
-            s->waiting.push_back(std::move(s->incoming.front()));
+            s->waiting.push_back(std::make_shared<const std::vector<Query>>(std::move(s->incoming.front())));
             s->incoming.pop_front();
           }
         }
@@ -492,13 +497,13 @@ void dispatcher(s4_server *s) {
         }
         // 2. waiting queries, oldest first
         while (!s->waiting.empty()) {
-          std::vector<Query> &batch = s->waiting.front();
+          const std::vector<Query> &batch = *s->waiting.front();
           if (s->waiting_pos == batch.size()) {
             s->waiting.pop_front();
             s->waiting_pos = 0;
             continue;
           }
-          Query &q = batch[s->waiting_pos];
+          const Query &q = batch[s->waiting_pos];
           Slice sl;
           sl.c1 = std::min(q.items, s->slice);
           if (sl.c1 < q.items) {  // too long for one slice: a job
@@ -516,15 +521,16 @@ void dispatcher(s4_server *s) {
             j.outstanding = 1;
             ++sliced;
           } else {
-            // a whole query: its slice is built in place in the context
-            // (one copy of the query, not two)
+            // a whole query: its slice points at it in its batch, which
+            // the context holds until the iteration retires (no copy)
             if (!fits(sl.c1, q.k, q.bound)) {
               if (c.slices.empty()) ++memory_waits;
               break;
             }
+            if (c.held.empty() || c.held.back() != s->waiting.front()) c.held.push_back(s->waiting.front());
             c.slices.emplace_back();
             Slice &ns = c.slices.back();
-            ns.q = q;
+            ns.q = &q;
             ns.c1 = sl.c1;
             items += ns.c1;
             terms += q.k;
